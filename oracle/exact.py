@@ -1,0 +1,108 @@
+"""O1: the exact discrete control u = A_2^-1 y_Omega (oracle; test infrastructure only).
+
+The control equation eqn:forControl reads (beta A^-alpha + (gamma/beta) A^alpha) u = y_Omega,
+written here as (c_neg A^-alpha + c_pos A^alpha) u = f.  A is the d-dimensional
+finite-difference Dirichlet Laplacian, diagonalised by the tensor sine transform
+(eqn:DiagLaplace, eqn:DiagFLaplace3D), and A^alpha is defined spectrally
+(eqn:frac_Oper).  Hence
+
+    u = F^(x d) diag(1/s(rho)) F^(x d) f ,  s(rho) = c_neg rho^-alpha + c_pos rho^alpha,
+
+which is what every routine below evaluates, each by a different route.
+"""
+import numpy as np
+import scipy.fft as sfft
+
+from . import spectral
+
+
+def solve_full(f, alpha, c_neg, c_pos):
+    """u on the full grid: forward sine transform, divide by s(rho), inverse
+    (eqn:DiagFLaplace3D / eqn:DiagFLaplace2D).  The orthonormal DST-I of scipy is
+    the library step for F (it equals spectral.dst_matrix, pinned in the tests)."""
+    f = np.asarray(f, dtype=np.float64)
+    fh = sfft.dstn(f, type=1, norm="ortho")
+    s = spectral.symbol(spectral.rho_grid(f.shape), alpha, c_neg, c_pos)
+    return sfft.idstn(fh / s, type=1, norm="ortho")
+
+
+def apply_full(x, alpha, c_neg, c_pos):
+    """A_2 x on the full grid (the same diagonalisation, multiplying by s)."""
+    x = np.asarray(x, dtype=np.float64)
+    xh = sfft.dstn(x, type=1, norm="ortho")
+    s = spectral.symbol(spectral.rho_grid(x.shape), alpha, c_neg, c_pos)
+    return sfft.idstn(xh * s, type=1, norm="ortho")
+
+
+def brute_force(f, alpha, c_neg, c_pos):
+    """Dense route that uses no sine transform: A = Kronecker sum of the 1D
+    tridiagonal matrices (eqn_low_rank_lap), eigendecomposition by numpy.linalg.eigh,
+    A_2 = c_neg A^-alpha + c_pos A^alpha from the eigenpairs, dense solve.
+    Only for n^d up to a few thousand."""
+    f = np.asarray(f, dtype=np.float64)
+    ns = f.shape
+    N = int(np.prod(ns))
+    A = np.zeros((N, N))
+    for l, n in enumerate(ns):
+        mats = [np.eye(m) for m in ns]
+        mats[l] = spectral.laplacian_1d(n)
+        K = mats[0]
+        for M in mats[1:]:
+            K = np.kron(K, M)
+        A += K
+    lam, Q = np.linalg.eigh(A)
+    A2 = (Q * (c_neg * lam ** (-alpha) + c_pos * lam**alpha)) @ Q.T
+    return np.linalg.solve(A2, f.reshape(N)).reshape(ns)
+
+
+def sine_mode(n, k):
+    """Grid values sin(k pi x_i), x_i = i/(n+1): the k-th eigenvector of A_(l)."""
+    x = np.arange(1, n + 1) / (n + 1.0)
+    return np.sin(k * np.pi * x)
+
+
+def single_mode_factor(ns, ks, alpha, c_neg, c_pos):
+    """For f = (x)_l sin(k_l pi x): u = f / s(sum_l lambda_{k_l}) exactly."""
+    rho = sum(spectral.eigenvalues(n)[k - 1] for n, k in zip(ns, ks))
+    return 1.0 / float(spectral.symbol(rho, alpha, c_neg, c_pos))
+
+
+def solve_cp_restricted(weights, factors, alpha, c_neg, c_pos, rows):
+    """u at the sample grid points rows[0] x rows[1] x rows[2] (0-based indices)
+    for a canonical right-hand side f = sum_t xi_t (x)_l f^(l)_t (eqn:CP_form).
+
+    f-hat = (x)_l F f^(l)_t is exact (Kronecker identity), then slab by slab over the
+    first spectral index i1: W = f-hat[i1] / s(lambda_i1 + lambda_j + lambda_k),
+    u[R1,R2,R3] += F[R1, i1] (x) (F[R2,:] W F[R3,:]^T).  O(n^2) memory, no n^3 array."""
+    w = np.asarray(weights, dtype=np.float64)
+    ns = [f.shape[0] for f in factors]
+    assert len(ns) == 3
+    lam = [spectral.eigenvalues(n) for n in ns]
+    Fh = [spectral.dst(f) for f in factors]          # F f_t per mode
+    Fr = [spectral.dst_matrix(n)[np.asarray(r)] for n, r in zip(ns, rows)]
+    out = np.zeros((len(rows[0]), len(rows[1]), len(rows[2])))
+    rho23 = lam[1][:, None] + lam[2][None, :]
+    for i1 in range(ns[0]):
+        slab = (Fh[1] * (w * Fh[0][i1])) @ Fh[2].T       # f-hat[i1, :, :]
+        rho = lam[0][i1] + rho23
+        W = slab / (c_neg * rho ** (-alpha) + c_pos * rho**alpha)
+        out += np.multiply.outer(Fr[0][:, i1], Fr[1] @ W @ Fr[2].T)
+    return out
+
+
+def solve_cp_restricted_slabs(weights, factors, alpha, c_neg, c_pos, rows, slabs):
+    """The same sum as solve_cp_restricted restricted to the first-index slabs
+    listed in `slabs` (used to time a bounded sample of the full evaluation)."""
+    w = np.asarray(weights, dtype=np.float64)
+    ns = [f.shape[0] for f in factors]
+    lam = [spectral.eigenvalues(n) for n in ns]
+    Fh = [spectral.dst(f) for f in factors]
+    Fr = [spectral.dst_matrix(n)[np.asarray(r)] for n, r in zip(ns, rows)]
+    out = np.zeros((len(rows[0]), len(rows[1]), len(rows[2])))
+    rho23 = lam[1][:, None] + lam[2][None, :]
+    for i1 in slabs:
+        slab = (Fh[1] * (w * Fh[0][i1])) @ Fh[2].T
+        rho = lam[0][i1] + rho23
+        W = slab / (c_neg * rho ** (-alpha) + c_pos * rho**alpha)
+        out += np.multiply.outer(Fr[0][:, i1], Fr[1] @ W @ Fr[2].T)
+    return out
