@@ -1,0 +1,261 @@
+/*
+ * tp.h -- C ABI of the rank-structured PCG solver for the fractional control equation
+ *
+ *   A_2 u = (c_neg A^-alpha + c_pos A^alpha) u = f          (eqn:forControl)
+ *
+ * of Heidel, Khoromskaia, Khoromskij, Schulz (arXiv:1809.01971).  A is the
+ * d-dimensional (d = 2, 3) finite-difference Dirichlet Laplacian on n interior
+ * points per mode (h = 1/(n+1)), diagonalised by the orthonormal sine transform
+ * (eqn:DiagLaplace, eqn:DiagFLaplace3D).  The paper's coefficients are
+ * c_neg = beta, c_pos = gamma/beta.
+ *
+ * Conventions for every entry point
+ *   - Pointers marked "device" are HIP device memory owned by the caller; the
+ *     library never frees them.  Pointers marked "host" are ordinary host memory.
+ *   - Matrices are column-major.  A factor matrix of mode l is n[l] x cap with
+ *     leading dimension n[l]; its first rank[l] columns are meaningful.
+ *   - All work is ordered on the stream given to tp_create.  Calls that return
+ *     host values (ranks, scalars, info) synchronise that stream.
+ *   - A context is used by one host thread at a time.
+ *   - Errors: every call returns a tp_status; on failure tp_last_error() gives a
+ *     message (thread-local, valid until the next call on that thread).  Invalid
+ *     arguments are rejected before any device work is enqueued.
+ *   - The grid size n must satisfy n >= 1 and n+1 a power of two (the sine
+ *     transform runs as a radix-2 FFT); n+1 <= 32768 in mixed precision and
+ *     n+1 <= 16384 in FP64.
+ */
+#ifndef TP_H
+#define TP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TP_OK = 0,
+  TP_EINVAL = 1,    /* invalid argument (shape, rank, parameter, precision mismatch) */
+  TP_ENOMEM = 2,    /* workspace or device allocation too small / failed */
+  TP_ENOCONV = 3,   /* PCG reached kmax; x holds the last iterate (the tables' '---') */
+  TP_ERANK = 4,     /* a truncation hit the rank cap with the tolerance unmet */
+  TP_EHIP = 5       /* a HIP runtime call failed */
+} tp_status;
+
+typedef enum { TP_FP64 = 0, TP_MIXED = 1 } tp_precision;
+typedef enum { TP_SYM_FIT = 0, TP_SYM_SINC = 1 } tp_symbol_method;
+
+typedef struct tp_ctx tp_ctx;
+typedef struct tp_symbol tp_symbol;
+
+/* Library version (major*100 + minor). */
+int tp_version(void);
+
+/* Message for the last non-OK status on this thread. */
+const char* tp_last_error(void);
+
+/* Create a context on HIP device `device`, ordering work on `stream` (a hipStream_t,
+ * NULL = default stream).  `workspace_bytes` of device memory are allocated once
+ * here (0 = 2 GiB); no entry point allocates device memory afterwards except
+ * tp_symbol_build (which owns its symbols) and the per-grid sine tables created
+ * on first use of a grid size. */
+tp_status tp_create(int device, void* stream, size_t workspace_bytes, tp_ctx** out);
+tp_status tp_destroy(tp_ctx* ctx);
+
+/* ---------------------------------------------------------------------------
+ * Tensors
+ * ------------------------------------------------------------------------- */
+
+/* Tucker tensor T = core x_1 V^(1) x_2 V^(2) (x_3 V^(3))  (eqn:Tucker_form).
+ * core: device, capacity cap^d elements; holds rank[0] x rank[1] (x rank[2])
+ *       column-major, packed (leading dimensions equal the ranks).
+ * factor[l]: device, n[l] x cap column-major, ld n[l].
+ * cap: at most 128 (the sum of two iterates is diagonalised at size <= 256).
+ * prec: TP_FP64 -> double elements, TP_MIXED -> float elements (core and factors).
+ * rank: host-side mode ranks; written by every call that produces the tensor.
+ * Outputs written by truncation have orthonormal factors. */
+typedef struct {
+  int32_t d;
+  int32_t n[3];
+  int32_t cap;
+  int32_t prec;
+  int32_t rank[3];
+  void* core;
+  void* factor[3];
+} tp_tensor;
+
+/* Canonical tensor sum_k weight[k] (x)_l factor[l][:,k]  (eqn:CP_form), device memory,
+ * always FP64 (right-hand sides enter in double). */
+typedef struct {
+  int32_t d;
+  int32_t n[3];
+  int32_t rank;
+  const double* weight;      /* device, rank */
+  const double* factor[3];   /* device, n[l] x rank, ld n[l] */
+} tp_cp;
+
+/* Gaussian test matrices for the sketched truncation of operator products:
+ * omega[l] is device, n[l] x q, ld n[l], FP64, 2 <= q <= 192.  The random numbers are an input:
+ * the library draws none. */
+typedef struct {
+  int32_t q;
+  const double* omega[3];
+} tp_sketch;
+
+/* ---------------------------------------------------------------------------
+ * Operator symbols  (Sec. 2 eqn:sinc_Laplace_tr; Sec. 4.1 Lemma 4.1; Sec. 4.2)
+ * ------------------------------------------------------------------------- */
+
+/* In the sine basis A_2 is diagonal with entries s(rho), rho = sum_l lambda_{i_l},
+ * s = c_neg rho^-alpha + c_pos rho^alpha.  Lemma 4.1 is applied to A_2 itself:
+ * s(rho) = rho * g(rho), g = c_neg rho^-(1+alpha) + c_pos rho^-(1-alpha), and g is
+ * an exponential sum sum_k w_k exp(-tau_k rho), so the operator symbol is a
+ * canonical tensor of rank d*K in spectral coordinates.  The preconditioner is a
+ * rank-K' exponential sum approximating 1/s (a low Kronecker rank approximation
+ * of A_2^-1, Sec. 1).
+ *
+ * method TP_SYM_SINC: g by the sinc rule u_k = k*h, k = -sinc_kl..sinc_kr,
+ *   t = log(1+e^u), weights h phi'(u) [c_neg t^alpha/Gamma(1+alpha) rho0^-(1+alpha)
+ *   + c_pos t^-alpha/Gamma(1-alpha) rho0^-(1-alpha)], rho0 = d*lambda_1.
+ * method TP_SYM_FIT: g by relative-error least squares on op_terms geometric
+ *   exponents (fewer terms for the same accuracy).
+ * The preconditioner always uses the least-squares fit with pre_terms exponents. */
+typedef struct {
+  int32_t d;
+  int32_t n[3];
+  double alpha;        /* 0 < alpha <= 1 */
+  double c_neg;        /* >= 0 */
+  double c_pos;        /* >= 0, c_neg + c_pos > 0 */
+  int32_t method;      /* tp_symbol_method */
+  int32_t op_terms;    /* TP_SYM_FIT: K (0 = 32) */
+  int32_t pre_terms;   /* K' (0 = 12) */
+  int32_t sinc_kl;     /* TP_SYM_SINC (0 = library default) */
+  int32_t sinc_kr;
+  double sinc_h;
+  int32_t prec;        /* precision of the factor matrices (tp_precision) */
+} tp_symbol_desc;
+
+/* Build the operator symbol and the preconditioner symbol on the GPU.  Both are
+ * owned by the library (free with tp_symbol_free).  err (host, 2 doubles, may be
+ * NULL) receives the measured max relative errors of the two exponential sums
+ * on 4096 log-spaced points of [rho_min, rho_max]. */
+tp_status tp_symbol_build(tp_ctx* ctx, const tp_symbol_desc* desc, tp_symbol** op,
+                          tp_symbol** pre, double* err);
+tp_status tp_symbol_free(tp_symbol* sym);
+/* rank (host): canonical rank of the symbol; err (host): its measured error. */
+tp_status tp_symbol_info(const tp_symbol* sym, int32_t* rank, double* err);
+/* Values of the symbol at `count` multi-indices idx (device, count x d int32,
+ * 0-based, row i = point i) into out (device, count doubles). */
+tp_status tp_symbol_eval(tp_ctx* ctx, const tp_symbol* sym, int32_t count,
+                         const int32_t* idx, double* out);
+
+/* ---------------------------------------------------------------------------
+ * Tensor arithmetic
+ * ------------------------------------------------------------------------- */
+
+/* Exact Tucker form of a canonical tensor: orthonormal bases of the factor
+ * column spans, core = sum_k w_k (x)_l (Q_l^T f_k^(l)).  If tol > 0 the result
+ * is then HOSVD-truncated at tol (relative).  out->cap bounds the ranks. */
+tp_status tp_from_cp(tp_ctx* ctx, const tp_cp* b, tp_tensor* out, double tol);
+
+/* y = trunc(F (s (.) F x)): the low-rank matrix-vector product of
+ * eqn:Lap3DtimesX with the canonical symbol s, truncated to relative accuracy
+ * tol and mode ranks <= cap.  The truncation works in spectral coordinates
+ * (F is orthogonal per mode, so it commutes with the truncation) by a sketched
+ * HOSVD: Khatri-Rao products of the test matrices span each mode, their
+ * orthonormal bases compress the product, and an exact HOSVD of the compressed
+ * core selects the ranks.  sketch->q must exceed the output rank.  y may alias x. */
+tp_status tp_apply(tp_ctx* ctx, const tp_symbol* sym, const tp_tensor* x, tp_tensor* y,
+                   double tol, int32_t cap, const tp_sketch* sketch);
+
+/* y = trunc(sum_i coef[i] * xs[i]) by the exact HOSVD of the sum (Sec. 5, RHOSVD
+ * step of Algorithm alg:pcg's trunc): factors are concatenated, orthonormalised,
+ * the block core is projected and its mode Gram matrices are diagonalised in FP64.
+ * coef: host, count doubles; xs: host array of count tensor pointers.  y may
+ * alias any xs[i]. */
+tp_status tp_truncate(tp_ctx* ctx, int32_t count, const double* coef,
+                      const tp_tensor* const* xs, tp_tensor* y, double tol, int32_t cap);
+
+/* <x, y> (Euclidean, Sec. 3.1 with M = I) from factor Gram matrices and the
+ * cores; out is host. */
+tp_status tp_inner(tp_ctx* ctx, const tp_tensor* x, const tp_tensor* y, double* out);
+
+/* Values of x on the sub-grid rows[0] x rows[1] (x rows[2]) (device int32 arrays
+ * of m[l] 0-based indices) into out (device, m[0]*m[1]*m[2] doubles, column-major). */
+tp_status tp_eval_grid(tp_ctx* ctx, const tp_tensor* x, const int32_t* const* rows,
+                       const int32_t* m, double* out);
+
+/* ---------------------------------------------------------------------------
+ * PCG  (Algorithm alg:pcg)
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  double tau;        /* stop when ||R||/||B|| <= tau */
+  int32_t kmax;      /* iteration limit (paper: 100) */
+  double trunc_tol;  /* relative truncation tolerance epsilon of trunc */
+  int32_t cap;       /* mode-rank cap of every iterate (<= x->cap) */
+  int32_t true_residual; /* nonzero: also compute ||B - A_2 X||/||B|| */
+} tp_pcg_opts;
+
+typedef struct {
+  int32_t iters;
+  int32_t status;    /* tp_status of the solve */
+  int32_t rank[3];   /* ranks of the returned X */
+  double rel_res;    /* ||R||/||B|| of the recursive residual */
+  double true_rel_res;  /* only if requested, else -1 */
+  double op_applies; /* number of operator/preconditioner products */
+} tp_pcg_info;
+
+/* Solve A_2 x = b with the operator symbol `op`, the preconditioner symbol `pre`
+ * and X0 = 0.  Iterates are Tucker tensors (the mixed Tucker-canonical route of
+ * Sec. 5); every update is truncated as in Algorithm alg:pcg.  x->prec selects
+ * the arithmetic; op and pre must have been built with that precision. */
+tp_status tp_pcg_solve(tp_ctx* ctx, const tp_symbol* op, const tp_symbol* pre,
+                       const tp_cp* b, tp_tensor* x, const tp_pcg_opts* opts,
+                       const tp_sketch* sketch, tp_pcg_info* info);
+
+/* ---------------------------------------------------------------------------
+ * Kernel-level entry points (for parity tests of single steps)
+ * ------------------------------------------------------------------------- */
+
+/* Orthonormal DST-I (F_jk = sqrt(2/(n+1)) sin(pi j k/(n+1))) of `cols` columns
+ * of length n: in/out device, column-major with ld n, FP64 (prec 0) or FP32
+ * (prec 1).  in may equal out. */
+tp_status tp_dst(tp_ctx* ctx, int32_t n, int32_t cols, int32_t prec, const void* in, void* out);
+
+/* Symmetric eigendecomposition (cyclic Jacobi, FP64) of `count` K x K matrices
+ * a (device, count*K*K, column-major): eigenvalues descending into w (device,
+ * count*K), eigenvectors into v (device, count*K*K).  K <= 256. */
+tp_status tp_syev(tp_ctx* ctx, int32_t K, int32_t count, const double* a, double* w, double* v);
+
+/* 1D eigenvalues lambda_k = (4/h^2) sin^2(pi k h/2), h = 1/(n+1), into out
+ * (device, n doubles). */
+tp_status tp_lambda(tp_ctx* ctx, int32_t n, double* out);
+
+/* ---------------------------------------------------------------------------
+ * Measurement
+ * ------------------------------------------------------------------------- */
+
+/* Kernel classes timed when profiling is on. */
+typedef enum {
+  TP_PROF_GEMM_F64 = 0,      /* FP64 contractions (Gram, sketch, projection, core) */
+  TP_PROF_GEMM_F32 = 1,      /* FP32 contractions of the mixed path */
+  TP_PROF_GEMM_F32_F64 = 2,  /* FP32 operands accumulated into FP64 results */
+  TP_PROF_GEMM_F64_F32 = 3,  /* FP64 operands rounded into FP32 results */
+  TP_PROF_DST_F64 = 4,
+  TP_PROF_DST_F32 = 5,
+  TP_PROF_SYEV = 6
+} tp_prof_class;
+
+/* enable != 0: record a HIP event pair around every launch of the classes above on the
+ * context stream (and reset the totals); enable == 0: stop recording. */
+tp_status tp_profile(tp_ctx* ctx, int32_t enable);
+/* Totals since tp_profile(ctx, 1) for class cls (host outputs, any may be NULL):
+ * summed event time in ms, launch count, algorithmic flops and algorithmic bytes. */
+tp_status tp_profile_read(tp_ctx* ctx, int32_t cls, double* ms, double* launches, double* flops,
+                          double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TP_H */

@@ -1,0 +1,349 @@
+"""ctypes binding of libtp.so: argument marshalling only (names follow include/tp.h)."""
+import ctypes as C
+import os
+
+import numpy as np
+
+TP_OK, TP_EINVAL, TP_ENOMEM, TP_ENOCONV, TP_ERANK, TP_EHIP = range(6)
+TP_FP64, TP_MIXED = 0, 1
+TP_SYM_FIT, TP_SYM_SINC = 0, 1
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+
+def library_path():
+    return os.path.join(_HERE, "libtp.so")
+
+
+class TPError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("tp status %d: %s" % (status, msg))
+        self.status = status
+
+
+class tp_tensor(C.Structure):
+    _fields_ = [("d", C.c_int32), ("n", C.c_int32 * 3), ("cap", C.c_int32), ("prec", C.c_int32),
+                ("rank", C.c_int32 * 3), ("core", C.c_void_p), ("factor", C.c_void_p * 3)]
+
+
+class tp_cp(C.Structure):
+    _fields_ = [("d", C.c_int32), ("n", C.c_int32 * 3), ("rank", C.c_int32),
+                ("weight", C.c_void_p), ("factor", C.c_void_p * 3)]
+
+
+class tp_sketch(C.Structure):
+    _fields_ = [("q", C.c_int32), ("omega", C.c_void_p * 3)]
+
+
+class tp_symbol_desc(C.Structure):
+    _fields_ = [("d", C.c_int32), ("n", C.c_int32 * 3), ("alpha", C.c_double), ("c_neg", C.c_double),
+                ("c_pos", C.c_double), ("method", C.c_int32), ("op_terms", C.c_int32),
+                ("pre_terms", C.c_int32), ("sinc_kl", C.c_int32), ("sinc_kr", C.c_int32),
+                ("sinc_h", C.c_double), ("prec", C.c_int32)]
+
+
+class tp_pcg_opts(C.Structure):
+    _fields_ = [("tau", C.c_double), ("kmax", C.c_int32), ("trunc_tol", C.c_double), ("cap", C.c_int32),
+                ("true_residual", C.c_int32)]
+
+
+class tp_pcg_info(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("rank", C.c_int32 * 3),
+                ("rel_res", C.c_double), ("true_rel_res", C.c_double), ("op_applies", C.c_double)]
+
+
+P = C.c_void_p
+_SIGS = {
+    "tp_version": ([], C.c_int),
+    "tp_last_error": ([], C.c_char_p),
+    "tp_create": ([C.c_int, P, C.c_size_t, C.POINTER(P)], C.c_int),
+    "tp_destroy": ([P], C.c_int),
+    "tp_symbol_build": ([P, C.POINTER(tp_symbol_desc), C.POINTER(P), C.POINTER(P), C.POINTER(C.c_double)], C.c_int),
+    "tp_symbol_free": ([P], C.c_int),
+    "tp_symbol_info": ([P, C.POINTER(C.c_int32), C.POINTER(C.c_double)], C.c_int),
+    "tp_symbol_eval": ([P, P, C.c_int32, P, P], C.c_int),
+    "tp_from_cp": ([P, C.POINTER(tp_cp), C.POINTER(tp_tensor), C.c_double], C.c_int),
+    "tp_apply": ([P, P, C.POINTER(tp_tensor), C.POINTER(tp_tensor), C.c_double, C.c_int32,
+                  C.POINTER(tp_sketch)], C.c_int),
+    "tp_truncate": ([P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.POINTER(tp_tensor)),
+                     C.POINTER(tp_tensor), C.c_double, C.c_int32], C.c_int),
+    "tp_inner": ([P, C.POINTER(tp_tensor), C.POINTER(tp_tensor), C.POINTER(C.c_double)], C.c_int),
+    "tp_eval_grid": ([P, C.POINTER(tp_tensor), C.POINTER(P), C.POINTER(C.c_int32), P], C.c_int),
+    "tp_pcg_solve": ([P, P, P, C.POINTER(tp_cp), C.POINTER(tp_tensor), C.POINTER(tp_pcg_opts),
+                      C.POINTER(tp_sketch), C.POINTER(tp_pcg_info)], C.c_int),
+    "tp_dst": ([P, C.c_int32, C.c_int32, C.c_int32, P, P], C.c_int),
+    "tp_syev": ([P, C.c_int32, C.c_int32, P, P, P], C.c_int),
+    "tp_lambda": ([P, C.c_int32, P], C.c_int),
+    "tp_profile": ([P, C.c_int32], C.c_int),
+    "tp_profile_read": ([P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                         C.POINTER(C.c_double)], C.c_int),
+}
+
+PROF_CLASSES = ["gemm_f64", "gemm_f32", "gemm_f32_f64", "gemm_f64_f32", "dst_f64", "dst_f32", "syev"]
+
+
+def load_library():
+    """Load libtp.so (raises OSError when it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        path = library_path()
+        if not os.path.exists(path):
+            raise OSError("libtp.so not built: run __graft_entry__.build() (expected at %s)" % path)
+        lib = C.CDLL(path)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(lib, name)
+            f.argtypes = args
+            f.restype = res
+        _LIB = lib
+    return _LIB
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(status, allow=()):
+    if status != TP_OK and status not in allow:
+        msg = load_library().tp_last_error().decode(errors="replace")
+        raise TPError(status, msg)
+    return status
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype(prec):
+    t = _torch()
+    return t.float64 if prec == TP_FP64 else t.float32
+
+
+class Context:
+    """tp_ctx on a CUDA/HIP device, ordering work on torch's current stream."""
+
+    def __init__(self, device=0, workspace_bytes=0):
+        t = _torch()
+        self.lib = load_library()
+        self.device = device
+        t.cuda.set_device(device)
+        self.stream = t.cuda.current_stream(device)
+        h = P()
+        _check(self.lib.tp_create(device, P(self.stream.cuda_stream), workspace_bytes, C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- kernel-level entry points
+    def dst(self, x, out=None):
+        t = _torch()
+        prec = TP_FP64 if x.dtype == t.float64 else TP_MIXED
+        x = x.contiguous()
+        n, cols = (x.shape[0], 1) if x.dim() == 1 else (x.shape[0], x.shape[1])
+        # column-major columns of length n: a torch (cols, n) tensor is that layout
+        xc = x.t().contiguous() if x.dim() == 2 else x
+        out_t = t.empty_like(xc) if out is None else out
+        _check(self.lib.tp_dst(self.h, n, cols, prec, P(xc.data_ptr()), P(out_t.data_ptr())))
+        return out_t.t() if x.dim() == 2 else out_t
+
+    def syev(self, a):
+        """a: (count, K, K) float64 CUDA tensor of symmetric matrices."""
+        t = _torch()
+        a = a.contiguous()
+        cnt, K, _ = a.shape
+        w = t.empty((cnt, K), dtype=t.float64, device=a.device)
+        v = t.empty((cnt, K, K), dtype=t.float64, device=a.device)
+        _check(self.lib.tp_syev(self.h, K, cnt, P(a.data_ptr()), P(w.data_ptr()), P(v.data_ptr())))
+        # v is column-major per matrix: v[b] stored as (K x K) col-major -> transpose view
+        return w, v.transpose(1, 2)
+
+    def lam(self, n):
+        t = _torch()
+        out = t.empty(n, dtype=t.float64, device="cuda")
+        _check(self.lib.tp_lambda(self.h, n, P(out.data_ptr())))
+        return out
+
+    # ---- measurement
+    def profile(self, enable=True):
+        _check(self.lib.tp_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self):
+        out = {}
+        for i, name in enumerate(PROF_CLASSES):
+            v = [C.c_double() for _ in range(4)]
+            _check(self.lib.tp_profile_read(self.h, i, *[C.byref(x) for x in v]))
+            out[name] = {"ms": v[0].value, "launches": v[1].value, "flops": v[2].value, "bytes": v[3].value}
+        return out
+
+    # ---- symbols
+    def symbol_build(self, d, n, alpha, c_neg, c_pos, prec=TP_FP64, method=TP_SYM_FIT, op_terms=0,
+                     pre_terms=0, sinc_kl=0, sinc_kr=0, sinc_h=0.0):
+        desc = tp_symbol_desc()
+        desc.d = d
+        for m in range(3):
+            desc.n[m] = n if m < d else 0
+        desc.alpha, desc.c_neg, desc.c_pos = alpha, c_neg, c_pos
+        desc.method, desc.op_terms, desc.pre_terms = method, op_terms, pre_terms
+        desc.sinc_kl, desc.sinc_kr, desc.sinc_h = sinc_kl, sinc_kr, sinc_h
+        desc.prec = prec
+        op, pre = P(), P()
+        err = (C.c_double * 2)()
+        _check(self.lib.tp_symbol_build(self.h, C.byref(desc), C.byref(op), C.byref(pre), err))
+        return Symbol(self, op, d, prec), Symbol(self, pre, d, prec), (err[0], err[1])
+
+    # ---- tensors
+    def from_cp(self, weights, factors, out, tol=0.0, allow_erank=False):
+        keep, cp = cp_struct(weights, factors)
+        st = _check(self.lib.tp_from_cp(self.h, C.byref(cp), C.byref(out.s), tol),
+                    allow=(TP_ERANK,) if allow_erank else ())
+        out._sync_ranks()
+        return st
+
+    def apply(self, sym, x, y, tol, cap, sketch, allow_erank=False):
+        sk, keep = sketch_struct(sketch)
+        st = _check(self.lib.tp_apply(self.h, sym.h, C.byref(x.s), C.byref(y.s), tol, cap, C.byref(sk)),
+                    allow=(TP_ERANK,) if allow_erank else ())
+        y._sync_ranks()
+        return st
+
+    def truncate(self, coefs, xs, y, tol, cap, allow_erank=False):
+        n = len(xs)
+        cf = (C.c_double * n)(*coefs)
+        arr = (C.POINTER(tp_tensor) * n)(*[C.pointer(x.s) for x in xs])
+        st = _check(self.lib.tp_truncate(self.h, n, cf, arr, C.byref(y.s), tol, cap),
+                    allow=(TP_ERANK,) if allow_erank else ())
+        y._sync_ranks()
+        return st
+
+    def inner(self, x, y):
+        out = C.c_double()
+        _check(self.lib.tp_inner(self.h, C.byref(x.s), C.byref(y.s), C.byref(out)))
+        return out.value
+
+    def eval_grid(self, x, rows):
+        t = _torch()
+        rs = [t.as_tensor(np.asarray(r, dtype=np.int32), device="cuda") for r in rows]
+        m = (C.c_int32 * 3)(*([len(r) for r in rows] + [1] * (3 - len(rows))))
+        ptrs = (P * 3)(*([P(r.data_ptr()) for r in rs] + [None] * (3 - len(rs))))
+        out = t.empty(int(np.prod([len(r) for r in rows])), dtype=t.float64, device="cuda")
+        _check(self.lib.tp_eval_grid(self.h, C.byref(x.s), ptrs, m, P(out.data_ptr())))
+        # column-major (m0, m1, m2) -> numpy C-order array indexed [i0, i1, i2]
+        return out.cpu().numpy().reshape([len(r) for r in rows][::-1]).transpose(
+            list(range(len(rows)))[::-1])
+
+    def pcg_solve(self, op, pre, weights, factors, x, tau, kmax, trunc_tol, cap, sketch, true_residual=False,
+                  allow=(TP_ERANK, TP_ENOCONV)):
+        keep, cp = cp_struct(weights, factors)
+        sk, keep2 = sketch_struct(sketch)
+        o = tp_pcg_opts(tau, kmax, trunc_tol, cap, 1 if true_residual else 0)
+        info = tp_pcg_info()
+        st = _check(self.lib.tp_pcg_solve(self.h, op.h, pre.h, C.byref(cp), C.byref(x.s), C.byref(o),
+                                          C.byref(sk), C.byref(info)), allow=allow)
+        x._sync_ranks()
+        return st, {"iters": info.iters, "status": info.status, "rank": list(info.rank)[:x.d],
+                    "rel_res": info.rel_res, "true_rel_res": info.true_rel_res,
+                    "applies": info.op_applies}
+
+
+class Symbol:
+    def __init__(self, ctx, h, d, prec):
+        self.ctx, self.h, self.d, self.prec = ctx, h, d, prec
+
+    def info(self):
+        r, e = C.c_int32(), C.c_double()
+        _check(self.ctx.lib.tp_symbol_info(self.h, C.byref(r), C.byref(e)))
+        return r.value, e.value
+
+    def eval(self, idx):
+        """idx: (count, d) int array of 0-based multi-indices -> values (numpy)."""
+        t = _torch()
+        it = t.as_tensor(np.ascontiguousarray(idx, dtype=np.int32), device="cuda")
+        out = t.empty(it.shape[0], dtype=t.float64, device="cuda")
+        _check(self.ctx.lib.tp_symbol_eval(self.ctx.h, self.h, it.shape[0], P(it.data_ptr()), P(out.data_ptr())))
+        return out.cpu().numpy()
+
+    def free(self):
+        if self.h:
+            self.ctx.lib.tp_symbol_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Tensor:
+    """Tucker tensor in torch-owned device memory (core cap^d, factors n x cap column-major)."""
+
+    def __init__(self, d, n, cap, prec=TP_FP64, device="cuda"):
+        t = _torch()
+        self.d, self.n, self.cap, self.prec = d, n, cap, prec
+        dt = _dtype(prec)
+        self.core = t.zeros(cap ** d, dtype=dt, device=device)
+        self.factors = [t.zeros(cap * n, dtype=dt, device=device) for _ in range(d)]
+        s = tp_tensor()
+        s.d, s.cap, s.prec = d, cap, prec
+        for m in range(3):
+            s.n[m] = n if m < d else 0
+            s.rank[m] = 0
+        s.core = self.core.data_ptr()
+        for m in range(d):
+            s.factor[m] = self.factors[m].data_ptr()
+        self.s = s
+        self.rank = [0] * d
+
+    def _sync_ranks(self):
+        self.rank = [self.s.rank[m] for m in range(self.d)]
+
+    def numpy_parts(self):
+        """(core, [factors]) as float64 numpy arrays with the current ranks."""
+        r = self.rank
+        core = self.core[: int(np.prod(r))].double().cpu().numpy().reshape(r[::-1]).transpose(
+            list(range(self.d))[::-1])
+        fs = [self.factors[m][: self.n * r[m]].double().cpu().numpy().reshape(r[m], self.n).T
+              for m in range(self.d)]
+        return core, fs
+
+
+def cp_struct(weights, factors):
+    """Device copies of a canonical tensor (float64) and its tp_cp struct."""
+    t = _torch()
+    w = t.as_tensor(np.asarray(weights, dtype=np.float64), device="cuda")
+    fs = [t.as_tensor(np.asfortranarray(np.asarray(f, dtype=np.float64)).T.copy(), device="cuda")
+          for f in factors]   # (R, n) C-order == (n, R) column-major
+    cp = tp_cp()
+    cp.d = len(factors)
+    for m in range(3):
+        cp.n[m] = factors[m].shape[0] if m < cp.d else 0
+    cp.rank = len(weights)
+    cp.weight = w.data_ptr()
+    for m in range(cp.d):
+        cp.factor[m] = fs[m].data_ptr()
+    return (w, fs), cp
+
+
+def sketch_struct(sketch):
+    """sketch: list of d torch float64 CUDA tensors of shape (q, n) (== n x q column-major)."""
+    sk = tp_sketch()
+    sk.q = sketch[0].shape[0]
+    for m, o in enumerate(sketch):
+        sk.omega[m] = o.data_ptr()
+    return sk, sketch
+
+
+def sketch_tensors(omegas):
+    """numpy (n, q) Gaussian matrices -> device tensors in the layout the library reads."""
+    t = _torch()
+    return [t.as_tensor(np.ascontiguousarray(np.asarray(o, dtype=np.float64).T), device="cuda") for o in omegas]

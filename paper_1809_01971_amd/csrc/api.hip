@@ -1,0 +1,1416 @@
+// Host side of the C ABI declared in include/tp.h.
+//
+// Orchestrates the kernels of kernels.hip on the context's stream.  Device memory
+// for intermediate results comes from one workspace allocated at tp_create and
+// handed out by a stack allocator; mode ranks are read back to the host after
+// each rank-revealing step (ranks decide the shapes of the following launches).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/tp.h"
+#include "tp_internal.h"
+
+using namespace tpk;
+
+namespace {
+
+thread_local std::string g_err;
+
+tp_status fail(tp_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIPCHK(...)                                                                         \
+  do {                                                                                      \
+    hipError_t e_ = (__VA_ARGS__);                                                          \
+    if (e_ != hipSuccess) return fail(TP_EHIP, "%s failed: %s (%s:%d)", #__VA_ARGS__,     \
+                                      hipGetErrorString(e_), __FILE__, __LINE__);         \
+  } while (0)
+
+#define TPCHK(...)                         \
+  do {                                     \
+    tp_status s_ = (__VA_ARGS__);          \
+    if (s_ != TP_OK) return s_;            \
+  } while (0)
+
+constexpr int kMaxRank = 256;   // eigensolver limit: every Gram is at most 256 x 256
+constexpr int kMaxCap = 128;    // sums of two iterates stay within kMaxRank
+constexpr int kMaxSketch = 192; // sketch width
+
+}  // namespace
+
+struct tp_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t ws_size = 0, ws_top = 0;
+  double* host = nullptr;        // pinned host scratch (kHost doubles)
+  EigJob* jobs = nullptr;        // device eig job descriptors
+  EigJob* jobs_host = nullptr;   // pinned staging
+  std::map<int, double*> tab64;
+  std::map<int, float*> tab32;
+  bool jobs_pending = false;     // jobs_host may still be read by an enqueued copy
+  // optional per-kernel-class timing with HIP events on the context stream
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_next = 0;
+  struct Rec { int cls; size_t e0, e1; double flops, bytes; };
+  std::vector<Rec> recs;
+  double prof_ms[16] = {0}, prof_n[16] = {0}, prof_flops[16] = {0}, prof_bytes[16] = {0};
+  static constexpr size_t kHost = 1 << 16;
+  static constexpr int kJobs = 64;
+};
+
+struct tp_symbol {
+  int d = 0, n[3] = {0, 0, 0}, prec = 0;
+  int kind = 0;          // 0: operator rho*g, 1: preconditioner
+  int K = 0;             // exponentials
+  int R = 0;             // canonical rank (d*K for the operator)
+  double err = 0;
+  double* weights = nullptr;   // R (device)
+  void* factors[3] = {nullptr, nullptr, nullptr};  // n x R (device, T)
+  double* tau = nullptr;       // K
+  double* w = nullptr;         // K
+  double* lam[3] = {nullptr, nullptr, nullptr};
+  std::vector<void*> owned;
+};
+
+namespace {
+
+// ------------------------------------------------------------------------------ workspace
+struct Mark { size_t top; };
+
+template <typename T>
+tp_status wsalloc(tp_ctx* c, size_t count, T** out) {
+  size_t bytes = ((count * sizeof(T)) + 255) & ~size_t(255);
+  if (bytes == 0) bytes = 256;
+  if (c->ws_top + bytes > c->ws_size)
+    return fail(TP_ENOMEM, "workspace exhausted: need %zu more bytes (top %zu of %zu)", bytes, c->ws_top, c->ws_size);
+  *out = reinterpret_cast<T*>(c->ws + c->ws_top);
+  c->ws_top += bytes;
+  return TP_OK;
+}
+struct WsScope {
+  tp_ctx* c;
+  size_t top;
+  explicit WsScope(tp_ctx* cc) : c(cc), top(cc->ws_top) {}
+  ~WsScope() { c->ws_top = top; }
+};
+
+// ------------------------------------------------------------------------------ profiling
+// Kernel classes reported by tp_profile_read.
+enum { PC_GEMM_F64 = 0, PC_GEMM_F32 = 1, PC_GEMM_F32_F64 = 2, PC_GEMM_F64_F32 = 3, PC_DST_F64 = 4, PC_DST_F32 = 5,
+       PC_SYEV = 6, PC_COUNT = 7 };
+
+tp_status prof_begin(tp_ctx* c, size_t* e0) {
+  if (!c->prof) return TP_OK;
+  if (c->ev_next + 2 > c->ev_pool.size()) {
+    size_t old = c->ev_pool.size();
+    c->ev_pool.resize(old + 1024);
+    for (size_t i = old; i < c->ev_pool.size(); ++i) HIPCHK(hipEventCreate(&c->ev_pool[i]));
+  }
+  *e0 = c->ev_next++;
+  HIPCHK(hipEventRecord(c->ev_pool[*e0], c->stream));
+  return TP_OK;
+}
+tp_status prof_end(tp_ctx* c, int cls, size_t e0, double flops, double bytes) {
+  if (!c->prof) return TP_OK;
+  size_t e1 = c->ev_next++;
+  HIPCHK(hipEventRecord(c->ev_pool[e1], c->stream));
+  c->recs.push_back({cls, e0, e1, flops, bytes});
+  return TP_OK;
+}
+// Fold recorded events into the per-class totals (synchronises the stream).
+tp_status prof_flush(tp_ctx* c) {
+  if (c->recs.empty()) return TP_OK;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (auto& r : c->recs) {
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev_pool[r.e0], c->ev_pool[r.e1]));
+    c->prof_ms[r.cls] += ms;
+    c->prof_n[r.cls] += 1;
+    c->prof_flops[r.cls] += r.flops;
+    c->prof_bytes[r.cls] += r.bytes;
+  }
+  c->recs.clear();
+  c->ev_next = 0;
+  return TP_OK;
+}
+
+bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+tp_status check_grid(int n, int prec) {
+  if (n < 1) return fail(TP_EINVAL, "grid size n=%d must be >= 1", n);
+  if (!pow2(n + 1)) return fail(TP_EINVAL, "grid size n=%d: n+1 must be a power of two", n);
+  int lim = prec == TP_FP64 ? 16384 : 32768;
+  if (n + 1 > lim) return fail(TP_EINVAL, "grid size n=%d exceeds the %s sine-transform limit n+1<=%d", n,
+                               prec == TP_FP64 ? "FP64" : "mixed", lim);
+  return TP_OK;
+}
+
+template <typename T>
+tp_status get_table(tp_ctx* c, int N, const T** out);
+template <>
+tp_status get_table<double>(tp_ctx* c, int N, const double** out) {
+  auto it = c->tab64.find(N);
+  if (it == c->tab64.end()) {
+    double* p = nullptr;
+    HIPCHK(hipMalloc(&p, sizeof(double) * 2 * N));
+    HIPCHK(dst_table<double>(N, p, c->stream));
+    it = c->tab64.emplace(N, p).first;
+  }
+  *out = it->second;
+  return TP_OK;
+}
+template <>
+tp_status get_table<float>(tp_ctx* c, int N, const float** out) {
+  auto it = c->tab32.find(N);
+  if (it == c->tab32.end()) {
+    float* p = nullptr;
+    HIPCHK(hipMalloc(&p, sizeof(float) * 2 * N));
+    HIPCHK(dst_table<float>(N, p, c->stream));
+    it = c->tab32.emplace(N, p).first;
+  }
+  *out = it->second;
+  return TP_OK;
+}
+
+template <typename T>
+tp_status dst_cols(tp_ctx* c, int n, int cols, const T* in, T* out) {
+  if (cols <= 0) return TP_OK;
+  const T* tab = nullptr;
+  TPCHK(get_table<T>(c, n + 1, &tab));
+  size_t e0 = 0;
+  TPCHK(prof_begin(c, &e0));
+  HIPCHK(dst1<T>(n + 1, cols, in, n, out, n, tab, c->stream));
+  // algorithmic work of a real FFT-based DST: ~2.5 N log2(2N) flops per column; bytes: in + out
+  double lg = std::log2(2.0 * (n + 1));
+  TPCHK(prof_end(c, std::is_same<T, double>::value ? PC_DST_F64 : PC_DST_F32, e0, 2.5 * (n + 1) * lg * cols,
+                 2.0 * n * cols * sizeof(T)));
+  return TP_OK;
+}
+
+tp_status sync_to_host(tp_ctx* c, const void* dev, size_t bytes, void* host) {
+  if (bytes == 0) return TP_OK;
+  HIPCHK(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return TP_OK;
+}
+
+template <typename TA, typename TB, typename TC, typename Tacc>
+int gemm_class() {
+  if (std::is_same<TA, double>::value && std::is_same<TC, double>::value) return PC_GEMM_F64;
+  if (std::is_same<TA, float>::value && std::is_same<TC, float>::value) return PC_GEMM_F32;
+  if (std::is_same<TA, float>::value) return PC_GEMM_F32_F64;
+  return PC_GEMM_F64_F32;
+}
+
+// ------------------------------------------------------------------------------ GEMM helpers
+template <typename TA, typename TB, typename TC, typename Tacc>
+tp_status run(tp_ctx* c, const GemmArgs<TA, TB, TC, Tacc>& g) {
+  size_t e0 = 0;
+  TPCHK(prof_begin(c, &e0));
+  HIPCHK(gemm<TA, TB, TC, Tacc>(g, c->stream));
+  if (c->prof) {
+    // algorithmic work: 2 M N K per product; bytes: operands once + result once (face-split
+    // operands count their two factor matrices)
+    double M = g.M, N = g.N, K = g.K, b = g.batch;
+    double fl = 2.0 * M * N * K * b;
+    double ba = g.fsA ? (double)M * (g.FA.r1 + K / std::max(1, g.FA.r1)) : M * K * (g.divA > 1 || g.sA ? b / g.divA : 1);
+    double bb = g.fsB ? (double)K * (g.FB.r1 + N / std::max(1, g.FB.r1)) : K * N * (g.sB ? b / g.divB : 1);
+    double by = ba * sizeof(TA) + bb * sizeof(TB) + M * N * b * sizeof(TC);
+    TPCHK(prof_end(c, gemm_class<TA, TB, TC, Tacc>(), e0, fl, by));
+  }
+  return TP_OK;
+}
+
+// C (M x N) = alpha op(A) op(B) + beta C, plain operands.
+template <typename TA, typename TB, typename TC, typename Tacc>
+tp_status mm(tp_ctx* c, bool tA, bool tB, int M, int N, int K, double alpha, const TA* A, int lda, const TB* B,
+             int ldb, double beta, TC* C, int ldc) {
+  GemmArgs<TA, TB, TC, Tacc> g;
+  g.M = M; g.N = N; g.K = K;
+  g.alpha = (Tacc)alpha; g.beta = (Tacc)beta;
+  g.A = A; g.lda = lda; g.tA = tA;
+  g.B = B; g.ldb = ldb; g.tB = tB;
+  g.C = C; g.ldc = ldc;
+  return run(c, g);
+}
+
+// ------------------------------------------------------------------------------ eigen
+// Diagonalise `cnt` symmetric matrices (device, double), returning eigenvalues on the host.
+tp_status eig(tp_ctx* c, int cnt, const int* K, const double* const* A, double* const* W, double* const* V,
+              std::vector<std::vector<double>>* host_w) {
+  if (cnt > tp_ctx::kJobs) return fail(TP_EINVAL, "too many eigen jobs");
+  if (c->jobs_pending) {
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->jobs_pending = false;
+  }
+  int Kmax = 0;
+  for (int i = 0; i < cnt; ++i) Kmax = std::max(Kmax, K[i]);
+  double* work = nullptr;
+  if (Kmax > 128) {
+    int Kp = (Kmax + 1) & ~1;
+    TPCHK(wsalloc(c, (size_t)Kp * Kp * cnt, &work));  // released with the caller's scope
+  }
+  for (int i = 0; i < cnt; ++i) {
+    if (K[i] > kMaxRank) return fail(TP_ERANK, "Gram matrix of size %d exceeds the eigensolver limit %d", K[i], kMaxRank);
+    int Kp = (Kmax + 1) & ~1;
+    c->jobs_host[i] = EigJob{K[i], A[i], W[i], V[i], work ? work + (size_t)Kp * Kp * i : nullptr};
+  }
+  if (Kmax == 0) return TP_OK;
+  HIPCHK(hipMemcpyAsync(c->jobs, c->jobs_host, sizeof(EigJob) * cnt, hipMemcpyHostToDevice, c->stream));
+  size_t e0 = 0;
+  TPCHK(prof_begin(c, &e0));
+  HIPCHK(syev_batched(c->jobs, cnt, Kmax, c->stream));
+  {
+    // algorithmic work: a symmetric eigendecomposition costs about 9 K^3 flops; bytes: A in, V and w out
+    double fl = 0, by = 0;
+    for (int i = 0; i < cnt; ++i) { fl += 9.0 * K[i] * K[i] * K[i]; by += 8.0 * (2.0 * K[i] * K[i] + K[i]); }
+    TPCHK(prof_end(c, PC_SYEV, e0, fl, by));
+  }
+  c->jobs_pending = true;
+  if (host_w) {
+    host_w->assign(cnt, {});
+    size_t off = 0;
+    for (int i = 0; i < cnt; ++i) {
+      HIPCHK(hipMemcpyAsync(c->host + off, W[i], sizeof(double) * K[i], hipMemcpyDeviceToHost, c->stream));
+      off += K[i];
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->jobs_pending = false;
+    off = 0;
+    for (int i = 0; i < cnt; ++i) {
+      (*host_w)[i].assign(c->host + off, c->host + off + K[i]);
+      off += K[i];
+    }
+  }
+  return TP_OK;
+}
+
+// Orthonormal basis of the column span of V (n x K, double, ld n), two passes of
+// Gram eigen-decomposition (rank revealing: eigenvalues below reltol*max are dropped).
+// Returns Q (n x q, ld n) in workspace.
+tp_status ortho(tp_ctx* c, int n, int K, const double* V, double reltol, double** Qout, int* qout) {
+  *qout = 0;
+  if (K == 0) { *Qout = nullptr; return TP_OK; }
+  double *G, *w, *E, *W, *Q1;
+  TPCHK(wsalloc(c, (size_t)K * K, &G));
+  TPCHK(wsalloc(c, (size_t)K, &w));
+  TPCHK(wsalloc(c, (size_t)K * K, &E));
+  TPCHK(wsalloc(c, (size_t)K * K, &W));
+  TPCHK(mm<double, double, double, double>(c, true, false, K, K, n, 1.0, V, n, V, n, 0.0, G, K));
+  std::vector<std::vector<double>> hw;
+  const double* Ap[1] = {G};
+  double* Wp[1] = {w};
+  double* Vp[1] = {E};
+  int Ks[1] = {K};
+  TPCHK(eig(c, 1, Ks, Ap, Wp, Vp, &hw));
+  double mx = hw[0].empty() ? 0.0 : hw[0][0];
+  int q = 0;
+  while (q < K && hw[0][q] > reltol * mx && hw[0][q] > 0) ++q;
+  if (q == 0) { *Qout = nullptr; return TP_OK; }
+  HIPCHK(eig_inv_sqrt(E, w, K, q, W, c->stream));
+  TPCHK(wsalloc(c, (size_t)n * q, &Q1));
+  TPCHK(mm<double, double, double, double>(c, false, false, n, q, K, 1.0, V, n, W, K, 0.0, Q1, n));
+  // second pass on Q1 (q x q Gram close to identity)
+  TPCHK(mm<double, double, double, double>(c, true, false, q, q, n, 1.0, Q1, n, Q1, n, 0.0, G, q));
+  Ks[0] = q;
+  TPCHK(eig(c, 1, Ks, Ap, Wp, Vp, &hw));
+  int q2 = 0;
+  while (q2 < q && hw[0][q2] > 1e-14 * hw[0][0] && hw[0][q2] > 0) ++q2;
+  HIPCHK(eig_inv_sqrt(E, w, q, q2, W, c->stream));
+  double* Q;
+  TPCHK(wsalloc(c, (size_t)n * q2, &Q));
+  TPCHK(mm<double, double, double, double>(c, false, false, n, q2, q, 1.0, Q1, n, W, q, 0.0, Q, n));
+  *Qout = Q;
+  *qout = q2;
+  return TP_OK;
+}
+
+// out = alpha * C x_1 op(A1) x_2 op(A2) [x_3 op(A3)] + beta*out, all double.
+// C is r1 x r2 (x r3) packed; op(A_m) is p_m x r_m.
+tp_status tucker_contract(tp_ctx* c, int d, const int* r, const double* C, const double* const* A, const int* lda,
+                          const bool* tA, const int* p, double alpha, double beta, double* out) {
+  WsScope scope(c);
+  if (d == 2) {
+    double* Y1;
+    TPCHK(wsalloc(c, (size_t)p[0] * r[1], &Y1));
+    TPCHK(mm<double, double, double, double>(c, tA[0], false, p[0], r[1], r[0], 1.0, A[0], lda[0], C, r[0], 0.0, Y1, p[0]));
+    // out (p0 x p1) = alpha Y1 op(A1)^T
+    TPCHK(mm<double, double, double, double>(c, false, !tA[1], p[0], p[1], r[1], alpha, Y1, p[0], A[1], lda[1], beta, out, p[0]));
+    return TP_OK;
+  }
+  double *Y1, *Y2;
+  TPCHK(wsalloc(c, (size_t)p[0] * r[1] * r[2], &Y1));
+  TPCHK(wsalloc(c, (size_t)p[0] * p[1] * r[2], &Y2));
+  TPCHK(mm<double, double, double, double>(c, tA[0], false, p[0], r[1] * r[2], r[0], 1.0, A[0], lda[0], C, r[0], 0.0, Y1, p[0]));
+  {
+    GemmArgs<double, double, double, double> g;
+    g.M = p[0]; g.N = p[1]; g.K = r[1]; g.batch = r[2];
+    g.A = Y1; g.lda = p[0]; g.sA = (long)p[0] * r[1];
+    g.B = A[1]; g.ldb = lda[1]; g.tB = !tA[1]; g.sB = 0;
+    g.C = Y2; g.ldc = p[0]; g.sC = (long)p[0] * p[1];
+    TPCHK(run(c, g));
+  }
+  TPCHK(mm<double, double, double, double>(c, false, !tA[2], p[0] * p[1], p[2], r[2], alpha, Y2, p[0] * p[1], A[2], lda[2], beta, out, p[0] * p[1]));
+  return TP_OK;
+}
+
+// HOSVD of a dense core M (q1 x q2 x q3, type T): per-mode Gram eigendecompositions,
+// ranks by sum_{i>r} s_i^2 <= tol^2 ||M||^2 / d (capped), bases U_m (double, q_m x r_m, ld q_m)
+// and the new core M x_m U_m^T written to core_out (type TO).
+template <typename T, typename TO>
+tp_status hosvd(tp_ctx* c, int d, const int* q, const T* M, double tol, int cap, int* rout, double** U,
+                TO* core_out, bool* capped) {
+  using Tacc = double;
+  double* G[3];
+  double* w[3];
+  double* E[3];
+  for (int m = 0; m < d; ++m) {
+    TPCHK(wsalloc(c, (size_t)q[m] * q[m], &G[m]));
+    TPCHK(wsalloc(c, (size_t)q[m], &w[m]));
+    TPCHK(wsalloc(c, (size_t)q[m] * q[m], &E[m]));
+  }
+  {
+    WsScope scope(c);
+    if (d == 2) {
+      TPCHK((mm<T, T, double, Tacc>(c, false, true, q[0], q[0], q[1], 1.0, M, q[0], M, q[0], 0.0, G[0], q[0])));
+      TPCHK((mm<T, T, double, Tacc>(c, true, false, q[1], q[1], q[0], 1.0, M, q[0], M, q[0], 0.0, G[1], q[1])));
+    } else {
+      int q23 = q[1] * q[2], q12 = q[0] * q[1];
+      TPCHK((mm<T, T, double, Tacc>(c, false, true, q[0], q[0], q23, 1.0, M, q[0], M, q[0], 0.0, G[0], q[0])));
+      TPCHK((mm<T, T, double, Tacc>(c, true, false, q[2], q[2], q12, 1.0, M, q12, M, q12, 0.0, G[2], q[2])));
+      T* Mp;
+      TPCHK(wsalloc(c, (size_t)q[0] * q[1] * q[2], &Mp));
+      HIPCHK(permute3<T>(M, q[0], q[1], q[2], Mp, 1, 0, 2, c->stream));
+      TPCHK((mm<T, T, double, Tacc>(c, false, true, q[1], q[1], q[0] * q[2], 1.0, Mp, q[1], Mp, q[1], 0.0, G[1], q[1])));
+    }
+  }
+  std::vector<std::vector<double>> hw;
+  const double* Ap[3] = {G[0], G[1], d == 3 ? G[2] : nullptr};
+  TPCHK(eig(c, d, q, Ap, w, E, &hw));
+  *capped = false;
+  for (int m = 0; m < d; ++m) {
+    double tot = 0;
+    for (double v : hw[m]) tot += std::max(v, 0.0);
+    double thr = tol * tol * tot / d;
+    int r = q[m];
+    double tail = 0;
+    // smallest r with sum_{i >= r} w_i <= thr
+    for (int i = q[m] - 1; i >= 1; --i) {
+      double v = std::max(hw[m][i], 0.0);
+      if (tail + v > thr) break;
+      tail += v;
+      r = i;
+    }
+    if (r > cap) { r = cap; *capped = true; }
+    if (r < 1) r = 1;
+    rout[m] = r;
+    U[m] = E[m];
+  }
+  // core = M x_m U_m^T
+  WsScope scope(c);
+  if (d == 2) {
+    if (std::is_same<T, double>::value) {
+      double* X1;
+      TPCHK(wsalloc(c, (size_t)rout[0] * q[1], &X1));
+      TPCHK((mm<double, double, double, double>(c, true, false, rout[0], q[1], q[0], 1.0, U[0], q[0], (const double*)M, q[0], 0.0, X1, rout[0])));
+      TPCHK((mm<double, double, TO, double>(c, false, false, rout[0], rout[1], q[1], 1.0, X1, rout[0], U[1], q[1], 0.0, core_out, rout[0])));
+    } else {
+      float *Uf0, *Uf1, *X1;
+      TPCHK(wsalloc(c, (size_t)q[0] * q[0], &Uf0));
+      TPCHK(wsalloc(c, (size_t)q[1] * q[1], &Uf1));
+      HIPCHK((convert<double, float>(U[0], Uf0, (long)q[0] * rout[0], c->stream)));
+      HIPCHK((convert<double, float>(U[1], Uf1, (long)q[1] * rout[1], c->stream)));
+      TPCHK(wsalloc(c, (size_t)rout[0] * q[1], &X1));
+      TPCHK((mm<float, float, float, float>(c, true, false, rout[0], q[1], q[0], 1.0, Uf0, q[0], (const float*)M, q[0], 0.0, X1, rout[0])));
+      TPCHK((mm<float, float, TO, typename std::conditional<std::is_same<TO, double>::value, double, float>::type>(
+          c, false, false, rout[0], rout[1], q[1], 1.0, X1, rout[0], Uf1, q[1], 0.0, core_out, rout[0])));
+    }
+    return TP_OK;
+  }
+  // d == 3
+  if (std::is_same<T, double>::value) {
+    const double* Md = (const double*)M;
+    double *X1, *X2;
+    TPCHK(wsalloc(c, (size_t)rout[0] * q[1] * q[2], &X1));
+    TPCHK(wsalloc(c, (size_t)rout[0] * rout[1] * q[2], &X2));
+    TPCHK((mm<double, double, double, double>(c, true, false, rout[0], q[1] * q[2], q[0], 1.0, U[0], q[0], Md, q[0], 0.0, X1, rout[0])));
+    GemmArgs<double, double, double, double> g;
+    g.M = rout[0]; g.N = rout[1]; g.K = q[1]; g.batch = q[2];
+    g.A = X1; g.lda = rout[0]; g.sA = (long)rout[0] * q[1];
+    g.B = U[1]; g.ldb = q[1];
+    g.C = X2; g.ldc = rout[0]; g.sC = (long)rout[0] * rout[1];
+    TPCHK(run(c, g));
+    TPCHK((mm<double, double, TO, double>(c, false, false, rout[0] * rout[1], rout[2], q[2], 1.0, X2, rout[0] * rout[1], U[2], q[2], 0.0, core_out, rout[0] * rout[1])));
+  } else {
+    const float* Mf = (const float*)M;
+    float *Uf[3], *X1, *X2;
+    for (int m = 0; m < 3; ++m) {
+      TPCHK(wsalloc(c, (size_t)q[m] * rout[m], &Uf[m]));
+      HIPCHK((convert<double, float>(U[m], Uf[m], (long)q[m] * rout[m], c->stream)));
+    }
+    TPCHK(wsalloc(c, (size_t)rout[0] * q[1] * q[2], &X1));
+    TPCHK(wsalloc(c, (size_t)rout[0] * rout[1] * q[2], &X2));
+    TPCHK((mm<float, float, float, float>(c, true, false, rout[0], q[1] * q[2], q[0], 1.0, Uf[0], q[0], Mf, q[0], 0.0, X1, rout[0])));
+    GemmArgs<float, float, float, float> g;
+    g.M = rout[0]; g.N = rout[1]; g.K = q[1]; g.batch = q[2];
+    g.A = X1; g.lda = rout[0]; g.sA = (long)rout[0] * q[1];
+    g.B = Uf[1]; g.ldb = q[1];
+    g.C = X2; g.ldc = rout[0]; g.sC = (long)rout[0] * rout[1];
+    TPCHK(run(c, g));
+    TPCHK((mm<float, float, TO, typename std::conditional<std::is_same<TO, double>::value, double, float>::type>(
+        c, false, false, rout[0] * rout[1], rout[2], q[2], 1.0, X2, rout[0] * rout[1], Uf[2], q[2], 0.0, core_out, rout[0] * rout[1])));
+  }
+  return TP_OK;
+}
+
+// ------------------------------------------------------------------------------ tensor checks
+tp_status check_tensor(const tp_tensor* t, const char* name, bool need_rank) {
+  if (!t) return fail(TP_EINVAL, "%s is NULL", name);
+  if (t->d != 2 && t->d != 3) return fail(TP_EINVAL, "%s: d=%d must be 2 or 3", name, t->d);
+  if (t->prec != TP_FP64 && t->prec != TP_MIXED) return fail(TP_EINVAL, "%s: unknown precision %d", name, t->prec);
+  if (t->cap < 1 || t->cap > kMaxCap) return fail(TP_EINVAL, "%s: cap=%d must be in [1,%d]", name, t->cap, kMaxCap);
+  for (int m = 0; m < t->d; ++m) {
+    TPCHK(check_grid(t->n[m], t->prec));
+    if (!t->factor[m]) return fail(TP_EINVAL, "%s: factor[%d] is NULL", name, m);
+    if (need_rank && (t->rank[m] < 0 || t->rank[m] > t->cap))
+      return fail(TP_EINVAL, "%s: rank[%d]=%d outside [0,cap=%d]", name, m, t->rank[m], t->cap);
+  }
+  if (!t->core) return fail(TP_EINVAL, "%s: core is NULL", name);
+  return TP_OK;
+}
+
+bool same_shape(const tp_tensor* a, const tp_tensor* b) {
+  if (a->d != b->d || a->prec != b->prec) return false;
+  for (int m = 0; m < a->d; ++m)
+    if (a->n[m] != b->n[m]) return false;
+  return true;
+}
+
+bool is_zero(const tp_tensor* t) {
+  for (int m = 0; m < t->d; ++m)
+    if (t->rank[m] == 0) return true;
+  return false;
+}
+
+template <typename T>
+tp_status set_zero(tp_ctx* c, tp_tensor* y) {
+  for (int m = 0; m < y->d; ++m) y->rank[m] = 0;
+  (void)c;
+  return TP_OK;
+}
+
+// ------------------------------------------------------------------------------ truncation of sums
+template <typename T>
+tp_status truncate_impl(tp_ctx* c, int count, const double* coef, const tp_tensor* const* xs, tp_tensor* y,
+                        double tol, int cap, bool* capped) {
+  WsScope scope(c);
+  const int d = y->d;
+  std::vector<int> idx;
+  for (int i = 0; i < count; ++i)
+    if (!is_zero(xs[i]) && coef[i] != 0.0) idx.push_back(i);
+  if (idx.empty()) return set_zero<T>(c, y);
+  int K[3] = {0, 0, 0};
+  for (int i : idx)
+    for (int m = 0; m < d; ++m) K[m] += xs[i]->rank[m];
+  double* V[3];
+  double* Q[3];
+  int q[3];
+  double* R[3];
+  for (int m = 0; m < d; ++m) {
+    int n = y->n[m];
+    TPCHK(wsalloc(c, (size_t)n * K[m], &V[m]));
+    int off = 0;
+    for (int i : idx) {
+      HIPCHK((copy2d<T, double>(n, xs[i]->rank[m], (const T*)xs[i]->factor[m], n, V[m] + (size_t)n * off, n, 1.0, c->stream)));
+      off += xs[i]->rank[m];
+    }
+    TPCHK(ortho(c, n, K[m], V[m], 1e-15, &Q[m], &q[m]));
+    if (q[m] == 0) return set_zero<T>(c, y);
+    TPCHK(wsalloc(c, (size_t)q[m] * K[m], &R[m]));
+    TPCHK((mm<double, double, double, double>(c, true, false, q[m], K[m], n, 1.0, Q[m], n, V[m], n, 0.0, R[m], q[m])));
+  }
+  size_t msz = (size_t)q[0] * q[1] * (d == 3 ? q[2] : 1);
+  double* M;
+  TPCHK(wsalloc(c, msz, &M));
+  int off[3] = {0, 0, 0};
+  bool first = true;
+  for (int i : idx) {
+    const tp_tensor* x = xs[i];
+    size_t csz = (size_t)x->rank[0] * x->rank[1] * (d == 3 ? x->rank[2] : 1);
+    WsScope inner(c);
+    double* Cd;
+    TPCHK(wsalloc(c, csz, &Cd));
+    HIPCHK((convert<T, double>((const T*)x->core, Cd, (long)csz, c->stream)));
+    const double* A[3];
+    int lda[3];
+    bool tA[3] = {false, false, false};
+    for (int m = 0; m < d; ++m) {
+      A[m] = R[m] + (size_t)q[m] * off[m];
+      lda[m] = q[m];
+    }
+    TPCHK(tucker_contract(c, d, x->rank, Cd, A, lda, tA, q, coef[i], first ? 0.0 : 1.0, M));
+    first = false;
+    for (int m = 0; m < d; ++m) off[m] += x->rank[m];
+  }
+  int rn[3] = {1, 1, 1};
+  double* U[3];
+  TPCHK((hosvd<double, T>(c, d, q, M, tol, cap, rn, U, (T*)y->core, capped)));
+  for (int m = 0; m < d; ++m) {
+    int n = y->n[m];
+    TPCHK((mm<double, double, T, double>(c, false, false, n, rn[m], q[m], 1.0, Q[m], n, U[m], q[m], 0.0, (T*)y->factor[m], n)));
+    y->rank[m] = rn[m];
+  }
+  return TP_OK;
+}
+
+// ------------------------------------------------------------------------------ apply (sketched)
+template <typename T>
+tp_status apply_impl(tp_ctx* c, const tp_symbol* S, const tp_tensor* x, tp_tensor* y, double tol, int cap,
+                     const tp_sketch* sk, bool* capped) {
+  using Tacc = T;
+  WsScope scope(c);
+  const int d = x->d;
+  if (is_zero(x)) return set_zero<T>(c, y);
+  const int R = S->R, Qs = sk->q;
+  int r[3] = {x->rank[0], x->rank[1], d == 3 ? x->rank[2] : 1};
+  const int n0 = x->n[0];
+  (void)n0;
+  // 1. spectral factors
+  T* Vh[3];
+  for (int m = 0; m < d; ++m) {
+    TPCHK(wsalloc(c, (size_t)x->n[m] * r[m], &Vh[m]));
+    TPCHK(dst_cols<T>(c, x->n[m], r[m], (const T*)x->factor[m], Vh[m]));
+  }
+  // core in T, local copy (y may alias x)
+  size_t csz = (size_t)r[0] * r[1] * r[2];
+  T* Cx;
+  TPCHK(wsalloc(c, csz, &Cx));
+  HIPCHK((convert<T, T>((const T*)x->core, Cx, (long)csz, c->stream)));
+  // 2. sketch matrices in T
+  const T* Om[3];
+  for (int m = 0; m < d; ++m) {
+    if (std::is_same<T, double>::value) {
+      Om[m] = (const T*)sk->omega[m];
+    } else {
+      T* o;
+      TPCHK(wsalloc(c, (size_t)x->n[m] * Qs, &o));
+      HIPCHK((convert<double, T>(sk->omega[m], o, (long)x->n[m] * Qs, c->stream)));
+      Om[m] = o;
+    }
+  }
+  // 3. A_m[i + r_m (k + R q)] = sum_x Vh_m(x,i) S_m(x,k) Om_m(x,q)
+  T* Am[3];
+  for (int m = 0; m < d; ++m) {
+    TPCHK(wsalloc(c, (size_t)r[m] * R * Qs, &Am[m]));
+    GemmArgs<T, T, T, Tacc> g;
+    g.M = r[m]; g.N = R * Qs; g.K = x->n[m];
+    g.A = Vh[m]; g.lda = x->n[m]; g.tA = true;
+    g.fsB = true; g.FB.x1 = (const T*)S->factors[m]; g.FB.ld1 = x->n[m]; g.FB.r1 = R;
+    g.FB.x2 = Om[m]; g.FB.ld2 = x->n[m];
+    g.C = Am[m]; g.ldc = r[m];
+    TPCHK(run(c, g));
+  }
+  // 4. per-mode sketch, orthonormal bases, projections
+  double* Qb[3];
+  int q[3];
+  T* Qt[3];
+  T* P[3];
+  for (int m = 0; m < d; ++m) {
+    const int n = x->n[m];
+    double* Y;
+    TPCHK(wsalloc(c, (size_t)n * Qs, &Y));
+    {
+      WsScope s2(c);
+      T* t;
+      TPCHK(wsalloc(c, (size_t)r[m] * R * Qs, &t));
+      if (d == 3) {
+        int o1 = m == 0 ? 1 : 0, o2 = m == 2 ? 1 : 2;
+        T* Cm = Cx;
+        if (m != 0) {
+          TPCHK(wsalloc(c, csz, &Cm));
+          // permute so that axis m comes first, then o1, then o2
+          HIPCHK(permute3<T>(Cx, r[0], r[1], r[2], Cm, m, o1, o2, c->stream));
+        }
+        T* T1;
+        TPCHK(wsalloc(c, (size_t)r[m] * r[o1] * R * Qs, &T1));
+        TPCHK((mm<T, T, T, Tacc>(c, false, false, r[m] * r[o1], R * Qs, r[o2], 1.0, Cm, r[m] * r[o1], Am[o2], r[o2], 0.0, T1, r[m] * r[o1])));
+        HIPCHK(contract_mid<T>(T1, Am[o1], r[m], r[o1], R * Qs, t, c->stream));
+      } else {
+        int o = 1 - m;
+        T* Cm = Cx;
+        if (m == 1) {
+          TPCHK(wsalloc(c, csz, &Cm));
+          HIPCHK(permute3<T>(Cx, r[0], r[1], 1, Cm, 1, 0, 2, c->stream));
+        }
+        TPCHK((mm<T, T, T, Tacc>(c, false, false, r[m], R * Qs, r[o], 1.0, Cm, r[m], Am[o], r[o], 0.0, t, r[m])));
+      }
+      // Y (n x Qs, double) = FS(Vh_m, S_m, sigma) (n x r_m R) * t (r_m R x Qs)
+      GemmArgs<T, T, double, double> g;
+      g.M = n; g.N = Qs; g.K = r[m] * R;
+      g.fsA = true; g.FA.x1 = Vh[m]; g.FA.ld1 = n; g.FA.r1 = r[m];
+      g.FA.x2 = (const T*)S->factors[m]; g.FA.ld2 = n; g.FA.w = S->weights;
+      g.B = t; g.ldb = r[m] * R;
+      g.C = Y; g.ldc = n;
+      TPCHK(run(c, g));
+    }
+    TPCHK(ortho(c, n, Qs, Y, 1e-14, &Qb[m], &q[m]));
+    if (q[m] == 0) return set_zero<T>(c, y);
+    if (std::is_same<T, double>::value) {
+      Qt[m] = (T*)Qb[m];
+    } else {
+      TPCHK(wsalloc(c, (size_t)n * q[m], &Qt[m]));
+      HIPCHK((convert<double, T>(Qb[m], Qt[m], (long)n * q[m], c->stream)));
+    }
+    // P_m[a + q (i + r k)] = sum_x Q(x,a) Vh(x,i) S(x,k) (* sigma_k on the last mode)
+    TPCHK(wsalloc(c, (size_t)q[m] * r[m] * R, &P[m]));
+    GemmArgs<T, T, T, Tacc> gp;
+    gp.M = q[m]; gp.N = r[m] * R; gp.K = n;
+    gp.A = Qt[m]; gp.lda = n; gp.tA = true;
+    gp.fsB = true; gp.FB.x1 = Vh[m]; gp.FB.ld1 = n; gp.FB.r1 = r[m];
+    gp.FB.x2 = (const T*)S->factors[m]; gp.FB.ld2 = n; gp.FB.w = (m == d - 1) ? S->weights : nullptr;
+    gp.C = P[m]; gp.ldc = q[m];
+    TPCHK(run(c, gp));
+  }
+  // 5. projected core M = sum_k sigma_k C x_1 P1_k x_2 P2_k (x_3 P3_k)
+  size_t msz = (size_t)q[0] * q[1] * (d == 3 ? q[2] : 1);
+  T* M;
+  TPCHK(wsalloc(c, msz, &M));
+  {
+    WsScope s3(c);
+    if (d == 3) {
+      T *D, *E;
+      TPCHK(wsalloc(c, (size_t)R * q[0] * r[1] * r[2], &D));
+      TPCHK(wsalloc(c, (size_t)R * r[2] * q[0] * q[1], &E));
+      GemmArgs<T, T, T, Tacc> g1;
+      g1.M = q[0]; g1.N = r[1] * r[2]; g1.K = r[0]; g1.batch = R;
+      g1.A = P[0]; g1.lda = q[0]; g1.sA = (long)q[0] * r[0];
+      g1.B = Cx; g1.ldb = r[0]; g1.sB = 0;
+      g1.C = D; g1.ldc = q[0]; g1.sC = (long)q[0] * r[1] * r[2];
+      TPCHK(run(c, g1));
+      GemmArgs<T, T, T, Tacc> g2;
+      g2.M = q[0]; g2.N = q[1]; g2.K = r[1]; g2.batch = R * r[2];
+      g2.A = D; g2.lda = q[0]; g2.sA = (long)q[0] * r[1];
+      g2.B = P[1]; g2.ldb = q[1]; g2.tB = true; g2.sB = (long)q[1] * r[1]; g2.divB = r[2];
+      g2.C = E; g2.ldc = q[0]; g2.sC = (long)q[0] * q[1];
+      TPCHK(run(c, g2));
+      TPCHK((mm<T, T, T, Tacc>(c, false, true, q[0] * q[1], q[2], r[2] * R, 1.0, E, q[0] * q[1], P[2], q[2], 0.0, M, q[0] * q[1])));
+    } else {
+      T* D;
+      TPCHK(wsalloc(c, (size_t)R * q[0] * r[1], &D));
+      GemmArgs<T, T, T, Tacc> g1;
+      g1.M = q[0]; g1.N = r[1]; g1.K = r[0]; g1.batch = R;
+      g1.A = P[0]; g1.lda = q[0]; g1.sA = (long)q[0] * r[0];
+      g1.B = Cx; g1.ldb = r[0]; g1.sB = 0;
+      g1.C = D; g1.ldc = q[0]; g1.sC = (long)q[0] * r[1];
+      TPCHK(run(c, g1));
+      TPCHK((mm<T, T, T, Tacc>(c, false, true, q[0], q[1], r[1] * R, 1.0, D, q[0], P[1], q[1], 0.0, M, q[0])));
+    }
+  }
+  // 6. HOSVD of the projected core
+  int rn[3] = {1, 1, 1};
+  double* U[3];
+  TPCHK((hosvd<T, T>(c, d, q, M, tol, cap, rn, U, (T*)y->core, capped)));
+  // 7. factors: F (Q U), spectral -> physical
+  for (int m = 0; m < d; ++m) {
+    int n = x->n[m];
+    WsScope s4(c);
+    T* W;
+    TPCHK(wsalloc(c, (size_t)n * rn[m], &W));
+    TPCHK((mm<double, double, T, double>(c, false, false, n, rn[m], q[m], 1.0, Qb[m], n, U[m], q[m], 0.0, W, n)));
+    TPCHK(dst_cols<T>(c, n, rn[m], W, (T*)y->factor[m]));
+    y->rank[m] = rn[m];
+  }
+  return TP_OK;
+}
+
+// ------------------------------------------------------------------------------ inner product
+template <typename T>
+tp_status inner_impl(tp_ctx* c, const tp_tensor* x, const tp_tensor* y, double* out) {
+  WsScope scope(c);
+  if (is_zero(x) || is_zero(y)) { *out = 0.0; return TP_OK; }
+  const int d = x->d;
+  double* G[3];
+  int px[3] = {1, 1, 1}, ry[3] = {1, 1, 1};
+  for (int m = 0; m < d; ++m) {
+    px[m] = x->rank[m];
+    ry[m] = y->rank[m];
+    TPCHK(wsalloc(c, (size_t)px[m] * ry[m], &G[m]));
+    using Tc = double;
+    TPCHK((mm<T, T, Tc, double>(c, true, false, px[m], ry[m], x->n[m], 1.0, (const T*)x->factor[m], x->n[m],
+                                (const T*)y->factor[m], y->n[m], 0.0, G[m], px[m])));
+  }
+  size_t cy = (size_t)ry[0] * ry[1] * ry[2], cx = (size_t)px[0] * px[1] * px[2];
+  double *Cy, *Cx, *Z, *res;
+  TPCHK(wsalloc(c, cy, &Cy));
+  TPCHK(wsalloc(c, cx, &Cx));
+  TPCHK(wsalloc(c, cx, &Z));
+  TPCHK(wsalloc(c, 1, &res));
+  HIPCHK((convert<T, double>((const T*)y->core, Cy, (long)cy, c->stream)));
+  HIPCHK((convert<T, double>((const T*)x->core, Cx, (long)cx, c->stream)));
+  const double* A[3] = {G[0], G[1], G[2]};
+  int lda[3] = {px[0], px[1], px[2]};
+  bool tA[3] = {false, false, false};
+  TPCHK(tucker_contract(c, d, ry, Cy, A, lda, tA, px, 1.0, 0.0, Z));
+  HIPCHK(dot<double>(Cx, Z, (long)cx, res, c->stream));
+  TPCHK(sync_to_host(c, res, sizeof(double), c->host));
+  *out = c->host[0];
+  return TP_OK;
+}
+
+// ------------------------------------------------------------------------------ CP -> Tucker
+template <typename T>
+tp_status from_cp_impl(tp_ctx* c, const tp_cp* b, tp_tensor* out, double tol, bool* capped) {
+  WsScope scope(c);
+  const int d = b->d, R = b->rank;
+  *capped = false;
+  if (R == 0) return set_zero<T>(c, out);
+  double* Q[3];
+  double* Rm[3];
+  int q[3] = {1, 1, 1};
+  for (int m = 0; m < d; ++m) {
+    int n = b->n[m];
+    TPCHK(ortho(c, n, R, b->factor[m], 1e-15, &Q[m], &q[m]));
+    if (q[m] == 0) return set_zero<T>(c, out);
+    TPCHK(wsalloc(c, (size_t)q[m] * R, &Rm[m]));
+    TPCHK((mm<double, double, double, double>(c, true, false, q[m], R, n, 1.0, Q[m], n, b->factor[m], n, 0.0, Rm[m], q[m])));
+  }
+  // R1 diag(w)
+  HIPCHK(scale_cols_d(Rm[0], q[0], R, q[0], b->weight, c->stream));
+  size_t msz = (size_t)q[0] * q[1] * (d == 3 ? q[2] : 1);
+  double* M;
+  TPCHK(wsalloc(c, msz, &M));
+  if (d == 3) {
+    double* KR;
+    TPCHK(wsalloc(c, (size_t)q[1] * q[2] * R, &KR));
+    HIPCHK(khatri_rao_d(Rm[1], q[1], Rm[2], q[2], R, KR, c->stream));
+    TPCHK((mm<double, double, double, double>(c, false, true, q[0], q[1] * q[2], R, 1.0, Rm[0], q[0], KR, q[1] * q[2], 0.0, M, q[0])));
+  } else {
+    TPCHK((mm<double, double, double, double>(c, false, true, q[0], q[1], R, 1.0, Rm[0], q[0], Rm[1], q[1], 0.0, M, q[0])));
+  }
+  if (tol > 0) {
+    int rn[3] = {1, 1, 1};
+    double* U[3];
+    TPCHK((hosvd<double, T>(c, d, q, M, tol, out->cap, rn, U, (T*)out->core, capped)));
+    for (int m = 0; m < d; ++m) {
+      int n = b->n[m];
+      TPCHK((mm<double, double, T, double>(c, false, false, n, rn[m], q[m], 1.0, Q[m], n, U[m], q[m], 0.0, (T*)out->factor[m], n)));
+      out->rank[m] = rn[m];
+    }
+    return TP_OK;
+  }
+  for (int m = 0; m < d; ++m)
+    if (q[m] > out->cap) return fail(TP_ERANK, "from_cp: mode %d rank %d exceeds cap %d", m, q[m], out->cap);
+  HIPCHK((convert<double, T>(M, (T*)out->core, (long)msz, c->stream)));
+  for (int m = 0; m < d; ++m) {
+    HIPCHK((convert<double, T>(Q[m], (T*)out->factor[m], (long)b->n[m] * q[m], c->stream)));
+    out->rank[m] = q[m];
+  }
+  return TP_OK;
+}
+
+// ------------------------------------------------------------------------------ symbol build
+template <typename T>
+tp_status build_factors(tp_ctx* c, tp_symbol* s) {
+  for (int m = 0; m < s->d; ++m) {
+    T* F = nullptr;
+    HIPCHK(hipMalloc(&F, sizeof(T) * (size_t)s->n[m] * s->R));
+    s->owned.push_back(F);
+    s->factors[m] = F;
+    if (s->kind == 0) {
+      for (int blk = 0; blk < s->d; ++blk)
+        HIPCHK(expfactors<T>(s->lam[m], s->n[m], s->tau, s->K, F + (size_t)s->n[m] * s->K * blk, s->n[m],
+                             blk == m ? 1 : 0, c->stream));
+    } else {
+      HIPCHK(expfactors<T>(s->lam[m], s->n[m], s->tau, s->K, F, s->n[m], 0, c->stream));
+    }
+  }
+  HIPCHK(hipMalloc(&s->weights, sizeof(double) * s->R));
+  s->owned.push_back(s->weights);
+  for (int blk = 0; blk < (s->kind == 0 ? s->d : 1); ++blk)
+    HIPCHK(hipMemcpyAsync(s->weights + (size_t)blk * s->K, s->w, sizeof(double) * s->K, hipMemcpyDeviceToDevice, c->stream));
+  return TP_OK;
+}
+
+// Least-squares exponential sum for f (kind 0: g, 1: 1/s) over candidates; keeps the best.
+tp_status fit_expsum(tp_ctx* c, int kind, double alpha, double cn, double cp, double rho0, double B, int K,
+                     const std::vector<FitCand>& cands, double* tau_out, double* w_out, double* err_out) {
+  WsScope scope(c);
+  const int m = 1000, nc = (int)cands.size();
+  double *A, *t, *G, *bvec, *ew, *E, *cn_, *err, *wsol, *ones;
+  FitCand* cd;
+  TPCHK(wsalloc(c, (size_t)nc, &cd));
+  TPCHK(wsalloc(c, (size_t)nc * m * K, &A));
+  TPCHK(wsalloc(c, (size_t)nc * K, &t));
+  TPCHK(wsalloc(c, (size_t)nc * K * K, &G));
+  TPCHK(wsalloc(c, (size_t)nc * K, &bvec));
+  TPCHK(wsalloc(c, (size_t)nc * K, &ew));
+  TPCHK(wsalloc(c, (size_t)nc * K * K, &E));
+  TPCHK(wsalloc(c, (size_t)nc * K, &cn_));
+  TPCHK(wsalloc(c, (size_t)nc, &err));
+  TPCHK(wsalloc(c, (size_t)nc * K, &wsol));
+  TPCHK(wsalloc(c, (size_t)m, &ones));
+  HIPCHK(hipMemcpyAsync(cd, cands.data(), sizeof(FitCand) * nc, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(fit_design(kind, alpha, cn, cp, rho0, B, K, m, cd, nc, A, t, c->stream));
+  // column scaling: cn_ = 1/||A_k|| from the Gram diagonal; scaled Gram = D G D
+  GemmArgs<double, double, double, double> g;
+  g.M = K; g.N = K; g.K = m; g.batch = nc;
+  g.A = A; g.lda = m; g.tA = true; g.sA = (long)m * K;
+  g.B = A; g.ldb = m; g.sB = (long)m * K;
+  g.C = G; g.ldc = K; g.sC = (long)K * K;
+  TPCHK(run(c, g));
+  std::vector<double> hones(m, 1.0);
+  HIPCHK(hipMemcpyAsync(ones, hones.data(), sizeof(double) * m, hipMemcpyHostToDevice, c->stream));
+  GemmArgs<double, double, double, double> gb;
+  gb.M = K; gb.N = 1; gb.K = m; gb.batch = nc;
+  gb.A = A; gb.lda = m; gb.tA = true; gb.sA = (long)m * K;
+  gb.B = ones; gb.ldb = m; gb.sB = 0;
+  gb.C = bvec; gb.ldc = K; gb.sC = K;
+  TPCHK(run(c, gb));
+  HIPCHK(fit_scale(K, nc, G, bvec, cn_, c->stream));
+  std::vector<int> Ks(nc, K);
+  std::vector<const double*> Ap(nc);
+  std::vector<double*> Wp(nc), Vp(nc);
+  for (int ci = 0; ci < nc; ++ci) {
+    Ap[ci] = G + (size_t)ci * K * K;
+    Wp[ci] = ew + (size_t)ci * K;
+    Vp[ci] = E + (size_t)ci * K * K;
+  }
+  TPCHK(eig(c, nc, Ks.data(), Ap.data(), Wp.data(), Vp.data(), nullptr));
+  HIPCHK(fit_solve(K, nc, ew, E, bvec, cn_, 1e-15, wsol, c->stream));
+  HIPCHK(fit_error(kind, alpha, cn, cp, rho0, B, K, t, wsol, nc, 4096, err, c->stream));
+  std::vector<double> herr(nc);
+  TPCHK(sync_to_host(c, err, sizeof(double) * nc, herr.data()));
+  int best = 0;
+  for (int ci = 1; ci < nc; ++ci)
+    if (herr[ci] < herr[best] || std::isnan(herr[best])) best = ci;
+  *err_out = herr[best];
+  HIPCHK(hipMemcpyAsync(tau_out, t + (size_t)best * K, sizeof(double) * K, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(w_out, wsol + (size_t)best * K, sizeof(double) * K, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return TP_OK;
+}
+
+}  // namespace
+
+// ==================================================================================== C ABI
+extern "C" {
+
+int tp_version(void) { return 100; }
+
+const char* tp_last_error(void) { return g_err.c_str(); }
+
+tp_status tp_create(int device, void* stream, size_t workspace_bytes, tp_ctx** out) {
+  if (!out) return fail(TP_EINVAL, "out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  HIPCHK(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(TP_EINVAL, "device %d not in [0,%d)", device, ndev);
+  HIPCHK(hipSetDevice(device));
+  tp_ctx* c = new tp_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  c->ws_size = workspace_bytes ? workspace_bytes : (size_t(2) << 30);
+  hipError_t e = hipMalloc(&c->ws, c->ws_size);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(TP_ENOMEM, "workspace allocation of %zu bytes failed: %s", workspace_bytes, hipGetErrorString(e));
+  }
+  HIPCHK(hipHostMalloc(&c->host, sizeof(double) * tp_ctx::kHost, hipHostMallocDefault));
+  HIPCHK(hipHostMalloc(&c->jobs_host, sizeof(EigJob) * tp_ctx::kJobs, hipHostMallocDefault));
+  HIPCHK(hipMalloc(&c->jobs, sizeof(EigJob) * tp_ctx::kJobs));
+  *out = c;
+  return TP_OK;
+}
+
+tp_status tp_destroy(tp_ctx* c) {
+  if (!c) return TP_OK;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  for (auto& e : c->ev_pool) (void)hipEventDestroy(e);
+  for (auto& kv : c->tab64) (void)hipFree(kv.second);
+  for (auto& kv : c->tab32) (void)hipFree(kv.second);
+  (void)hipFree(c->ws);
+  (void)hipFree(c->jobs);
+  (void)hipHostFree(c->host);
+  (void)hipHostFree(c->jobs_host);
+  delete c;
+  return TP_OK;
+}
+
+tp_status tp_profile(tp_ctx* c, int32_t enable) {
+  if (!c) return fail(TP_EINVAL, "NULL context");
+  TPCHK(prof_flush(c));
+  c->prof = enable != 0;
+  for (int i = 0; i < 16; ++i) c->prof_ms[i] = c->prof_n[i] = c->prof_flops[i] = c->prof_bytes[i] = 0;
+  return TP_OK;
+}
+
+tp_status tp_profile_read(tp_ctx* c, int32_t cls, double* ms, double* launches, double* flops, double* bytes) {
+  if (!c) return fail(TP_EINVAL, "NULL context");
+  if (cls < 0 || cls >= PC_COUNT) return fail(TP_EINVAL, "class %d outside [0,%d)", cls, (int)PC_COUNT);
+  TPCHK(prof_flush(c));
+  if (ms) *ms = c->prof_ms[cls];
+  if (launches) *launches = c->prof_n[cls];
+  if (flops) *flops = c->prof_flops[cls];
+  if (bytes) *bytes = c->prof_bytes[cls];
+  return TP_OK;
+}
+
+tp_status tp_lambda(tp_ctx* c, int32_t n, double* out) {
+  if (!c || !out) return fail(TP_EINVAL, "NULL argument");
+  if (n < 1) return fail(TP_EINVAL, "n=%d must be >= 1", n);
+  HIPCHK(lambda_1d(n, out, c->stream));
+  return TP_OK;
+}
+
+tp_status tp_dst(tp_ctx* c, int32_t n, int32_t cols, int32_t prec, const void* in, void* out) {
+  if (!c || !in || !out) return fail(TP_EINVAL, "NULL argument");
+  if (cols < 0) return fail(TP_EINVAL, "cols=%d < 0", cols);
+  TPCHK(check_grid(n, prec));
+  if (prec == TP_FP64) return dst_cols<double>(c, n, cols, (const double*)in, (double*)out);
+  if (prec == TP_MIXED) return dst_cols<float>(c, n, cols, (const float*)in, (float*)out);
+  return fail(TP_EINVAL, "unknown precision %d", prec);
+}
+
+tp_status tp_syev(tp_ctx* c, int32_t K, int32_t count, const double* a, double* w, double* v) {
+  if (!c || !a || !w || !v) return fail(TP_EINVAL, "NULL argument");
+  if (K < 1 || K > kMaxRank) return fail(TP_EINVAL, "K=%d must be in [1,%d]", K, kMaxRank);
+  if (count < 0 || count > tp_ctx::kJobs) return fail(TP_EINVAL, "count=%d must be in [0,%d]", count, tp_ctx::kJobs);
+  std::vector<int> Ks(count, K);
+  std::vector<const double*> Ap(count);
+  std::vector<double*> Wp(count), Vp(count);
+  for (int i = 0; i < count; ++i) {
+    Ap[i] = a + (size_t)i * K * K;
+    Wp[i] = w + (size_t)i * K;
+    Vp[i] = v + (size_t)i * K * K;
+  }
+  TPCHK(eig(c, count, Ks.data(), Ap.data(), Wp.data(), Vp.data(), nullptr));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return TP_OK;
+}
+
+tp_status tp_symbol_build(tp_ctx* c, const tp_symbol_desc* desc, tp_symbol** op, tp_symbol** pre, double* err) {
+  if (!c || !desc || !op || !pre) return fail(TP_EINVAL, "NULL argument");
+  *op = nullptr;
+  *pre = nullptr;
+  const tp_symbol_desc& D = *desc;
+  if (D.d != 2 && D.d != 3) return fail(TP_EINVAL, "d=%d must be 2 or 3", D.d);
+  if (!(D.alpha > 0.0 && D.alpha <= 1.0)) return fail(TP_EINVAL, "alpha=%g must be in (0,1]", D.alpha);
+  if (!(D.c_neg >= 0.0) || !(D.c_pos >= 0.0) || !(D.c_neg + D.c_pos > 0.0))
+    return fail(TP_EINVAL, "coefficients c_neg=%g c_pos=%g must be >= 0 and not both 0", D.c_neg, D.c_pos);
+  if (D.prec != TP_FP64 && D.prec != TP_MIXED) return fail(TP_EINVAL, "unknown precision %d", D.prec);
+  for (int m = 0; m < D.d; ++m) TPCHK(check_grid(D.n[m], D.prec));
+  int Kop = D.op_terms > 0 ? D.op_terms : 32;
+  int Kpre = D.pre_terms > 0 ? D.pre_terms : 12;
+  if (D.method == TP_SYM_FIT && (Kop < 2 || Kop > 64)) return fail(TP_EINVAL, "op_terms=%d must be in [2,64]", Kop);
+  if (Kpre < 2 || Kpre > 64) return fail(TP_EINVAL, "pre_terms=%d must be in [2,64]", Kpre);
+  if (D.method != TP_SYM_FIT && D.method != TP_SYM_SINC) return fail(TP_EINVAL, "unknown method %d", D.method);
+  int kl = D.sinc_kl > 0 ? D.sinc_kl : 60, kr = D.sinc_kr > 0 ? D.sinc_kr : 20;
+  double hh = D.sinc_h > 0 ? D.sinc_h : 0.55;
+  if (D.method == TP_SYM_SINC && kl + kr + 2 > 2048) return fail(TP_EINVAL, "sinc rule too long");
+
+  tp_symbol* s[2] = {new tp_symbol(), new tp_symbol()};
+  auto cleanup = [&](tp_status st) {
+    for (int i = 0; i < 2; ++i) {
+      if (s[i]) { for (void* p : s[i]->owned) (void)hipFree(p); delete s[i]; }
+    }
+    return st;
+  };
+  double lam1[3], lamn[3];
+  for (int i = 0; i < 2; ++i) {
+    s[i]->d = D.d;
+    s[i]->prec = D.prec;
+    s[i]->kind = i;
+    for (int m = 0; m < D.d; ++m) {
+      s[i]->n[m] = D.n[m];
+      double* l = nullptr;
+      if (hipMalloc(&l, sizeof(double) * D.n[m]) != hipSuccess) return cleanup(fail(TP_ENOMEM, "hipMalloc failed"));
+      s[i]->owned.push_back(l);
+      s[i]->lam[m] = l;
+      if (lambda_1d(D.n[m], l, c->stream) != hipSuccess) return cleanup(fail(TP_EHIP, "lambda kernel failed"));
+    }
+  }
+  for (int m = 0; m < D.d; ++m) {
+    double h = 1.0 / (D.n[m] + 1.0);
+    lam1[m] = 4.0 / (h * h) * std::pow(std::sin(M_PI * h / 2), 2);
+    lamn[m] = 4.0 / (h * h) * std::pow(std::sin(M_PI * D.n[m] * h / 2), 2);
+  }
+  double rmin = 0, rmax = 0;
+  for (int m = 0; m < D.d; ++m) { rmin += lam1[m]; rmax += lamn[m]; }
+  const double rho0 = rmin, B = rmax / rmin * 1.0000001;
+  // operator
+  {
+    tp_symbol* so = s[0];
+    int K = D.method == TP_SYM_FIT ? Kop : kl + kr + 1 + (std::fabs(1.0 - D.alpha) < 1e-15 ? 1 : 0);
+    so->K = K;
+    so->R = D.d * K;
+    if (hipMalloc(&so->tau, sizeof(double) * K) != hipSuccess || hipMalloc(&so->w, sizeof(double) * K) != hipSuccess)
+      return cleanup(fail(TP_ENOMEM, "hipMalloc failed"));
+    so->owned.push_back(so->tau);
+    so->owned.push_back(so->w);
+    if (D.method == TP_SYM_FIT) {
+      std::vector<FitCand> cands;
+      for (double a : {-1.5, -1.0, -0.5})
+        for (double b : {1.75, 2.25, 2.75}) cands.push_back({a, b});
+      double e = 0;
+      tp_status st = fit_expsum(c, 0, D.alpha, D.c_neg, D.c_pos, rho0, B, K, cands, so->tau, so->w, &e);
+      if (st != TP_OK) return cleanup(st);
+      // the fit is in the scaled variable y = rho/rho0: tau = t/rho0
+      if (scale(so->tau, K, 1.0 / rho0, c->stream) != hipSuccess) return cleanup(fail(TP_EHIP, "scale failed"));
+      so->err = e;
+    } else {
+      if (sinc_g_nodes(D.alpha, D.c_neg, D.c_pos, rho0, kl, kr, hh, so->tau, so->w, c->stream) != hipSuccess)
+        return cleanup(fail(TP_EHIP, "sinc kernel failed"));
+      so->err = -1;
+    }
+  }
+  // preconditioner
+  {
+    tp_symbol* sp = s[1];
+    int K = Kpre;
+    sp->K = K;
+    sp->R = K;
+    if (hipMalloc(&sp->tau, sizeof(double) * K) != hipSuccess || hipMalloc(&sp->w, sizeof(double) * K) != hipSuccess)
+      return cleanup(fail(TP_ENOMEM, "hipMalloc failed"));
+    sp->owned.push_back(sp->tau);
+    sp->owned.push_back(sp->w);
+    std::vector<FitCand> cands;
+    for (double a : {-3.5, -2.75, -2.0})
+      for (double b : {0.0, 0.5, 1.0}) cands.push_back({a, b});
+    double e = 0;
+    tp_status st = fit_expsum(c, 1, D.alpha, D.c_neg, D.c_pos, rho0, B, K, cands, sp->tau, sp->w, &e);
+    if (st != TP_OK) return cleanup(st);
+    if (scale(sp->tau, K, 1.0 / rho0, c->stream) != hipSuccess) return cleanup(fail(TP_EHIP, "scale failed"));
+    sp->err = e;
+  }
+  // measured error of the operator sum (also for the sinc rule): rho*g vs s on log samples
+  for (int i = 0; i < 2; ++i) {
+    tp_status st = D.prec == TP_FP64 ? build_factors<double>(c, s[i]) : build_factors<float>(c, s[i]);
+    if (st != TP_OK) return cleanup(st);
+  }
+  if (s[0]->err < 0) {
+    // evaluate rho*g(rho)/s(rho)-1 with fit_error in the unscaled variable (rho0 = 1 scaling: y = rho/rho0)
+    WsScope scope(c);
+    double *ts, *e;
+    if (wsalloc(c, (size_t)s[0]->K, &ts) != TP_OK || wsalloc(c, 1, &e) != TP_OK) return cleanup(TP_ENOMEM);
+    if (hipMemcpyAsync(ts, s[0]->tau, sizeof(double) * s[0]->K, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+        scale(ts, s[0]->K, rho0, c->stream) != hipSuccess)
+      return cleanup(fail(TP_EHIP, "scale failed"));
+    if (fit_error(0, D.alpha, D.c_neg, D.c_pos, rho0, B, s[0]->K, ts, s[0]->w, 1, 4096, e, c->stream) != hipSuccess)
+      return cleanup(fail(TP_EHIP, "error kernel failed"));
+    double he = 0;
+    if (sync_to_host(c, e, sizeof(double), &he) != TP_OK) return cleanup(TP_EHIP);
+    s[0]->err = he;
+  }
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return cleanup(fail(TP_EHIP, "stream sync failed"));
+  if (err) { err[0] = s[0]->err; err[1] = s[1]->err; }
+  *op = s[0];
+  *pre = s[1];
+  s[0] = s[1] = nullptr;
+  return TP_OK;
+}
+
+tp_status tp_symbol_free(tp_symbol* s) {
+  if (!s) return TP_OK;
+  (void)hipDeviceSynchronize();
+  for (void* p : s->owned) (void)hipFree(p);
+  delete s;
+  return TP_OK;
+}
+
+tp_status tp_symbol_info(const tp_symbol* s, int32_t* rank, double* err) {
+  if (!s) return fail(TP_EINVAL, "NULL symbol");
+  if (rank) *rank = s->R;
+  if (err) *err = s->err;
+  return TP_OK;
+}
+
+tp_status tp_symbol_eval(tp_ctx* c, const tp_symbol* s, int32_t count, const int32_t* idx, double* out) {
+  if (!c || !s || (count > 0 && (!idx || !out))) return fail(TP_EINVAL, "NULL argument");
+  if (count < 0) return fail(TP_EINVAL, "count < 0");
+  HIPCHK(symbol_eval(s->d, idx, count, s->lam[0], s->lam[1], s->d == 3 ? s->lam[2] : s->lam[1], s->kind, s->K,
+                     s->tau, s->w, out, c->stream));
+  return TP_OK;
+}
+
+tp_status tp_from_cp(tp_ctx* c, const tp_cp* b, tp_tensor* out, double tol) {
+  if (!c || !b || !out) return fail(TP_EINVAL, "NULL argument");
+  TPCHK(check_tensor(out, "out", false));
+  if (b->d != out->d) return fail(TP_EINVAL, "dimension mismatch");
+  for (int m = 0; m < b->d; ++m) {
+    if (b->n[m] != out->n[m]) return fail(TP_EINVAL, "grid mismatch in mode %d", m);
+    if (b->rank > 0 && !b->factor[m]) return fail(TP_EINVAL, "b.factor[%d] NULL", m);
+  }
+  if (b->rank < 0 || b->rank > kMaxRank) return fail(TP_EINVAL, "b.rank=%d must be in [0,%d]", b->rank, kMaxRank);
+  if (b->rank > 0 && !b->weight) return fail(TP_EINVAL, "b.weight NULL");
+  bool capped = false;
+  tp_status st = out->prec == TP_FP64 ? from_cp_impl<double>(c, b, out, tol, &capped)
+                                      : from_cp_impl<float>(c, b, out, tol, &capped);
+  if (st != TP_OK) return st;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return capped ? fail(TP_ERANK, "rank cap reached") : TP_OK;
+}
+
+tp_status tp_apply(tp_ctx* c, const tp_symbol* s, const tp_tensor* x, tp_tensor* y, double tol, int32_t cap,
+                   const tp_sketch* sk) {
+  if (!c || !s || !x || !y || !sk) return fail(TP_EINVAL, "NULL argument");
+  TPCHK(check_tensor(x, "x", true));
+  TPCHK(check_tensor(y, "y", false));
+  if (!same_shape(x, y)) return fail(TP_EINVAL, "x and y differ in shape or precision");
+  if (s->d != x->d || s->prec != x->prec) return fail(TP_EINVAL, "symbol does not match the tensor (d or precision)");
+  for (int m = 0; m < x->d; ++m)
+    if (s->n[m] != x->n[m]) return fail(TP_EINVAL, "symbol grid differs in mode %d", m);
+  if (cap < 1 || cap > y->cap) return fail(TP_EINVAL, "cap=%d must be in [1, y.cap=%d]", cap, y->cap);
+  if (!(tol >= 0.0)) return fail(TP_EINVAL, "tol must be >= 0");
+  if (sk->q < 2 || sk->q > kMaxSketch) return fail(TP_EINVAL, "sketch q=%d must be in [2,%d]", sk->q, kMaxSketch);
+  for (int m = 0; m < x->d; ++m)
+    if (!sk->omega[m]) return fail(TP_EINVAL, "sketch omega[%d] NULL", m);
+  bool capped = false;
+  tp_status st = x->prec == TP_FP64 ? apply_impl<double>(c, s, x, y, tol, cap, sk, &capped)
+                                    : apply_impl<float>(c, s, x, y, tol, cap, sk, &capped);
+  if (st != TP_OK) return st;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return capped ? fail(TP_ERANK, "rank cap reached") : TP_OK;
+}
+
+tp_status tp_truncate(tp_ctx* c, int32_t count, const double* coef, const tp_tensor* const* xs, tp_tensor* y,
+                      double tol, int32_t cap) {
+  if (!c || !y || (count > 0 && (!coef || !xs))) return fail(TP_EINVAL, "NULL argument");
+  if (count < 1 || count > 8) return fail(TP_EINVAL, "count=%d must be in [1,8]", count);
+  TPCHK(check_tensor(y, "y", false));
+  int tot[3] = {0, 0, 0};
+  for (int i = 0; i < count; ++i) {
+    TPCHK(check_tensor(xs[i], "xs[i]", true));
+    if (!same_shape(xs[i], y)) return fail(TP_EINVAL, "xs[%d] differs from y in shape or precision", i);
+    for (int m = 0; m < y->d; ++m) tot[m] += xs[i]->rank[m];
+  }
+  for (int m = 0; m < y->d; ++m)
+    if (tot[m] > kMaxRank) return fail(TP_ERANK, "sum of ranks %d in mode %d exceeds %d", tot[m], m, kMaxRank);
+  if (cap < 1 || cap > y->cap) return fail(TP_EINVAL, "cap=%d must be in [1, y.cap=%d]", cap, y->cap);
+  bool capped = false;
+  tp_status st = y->prec == TP_FP64 ? truncate_impl<double>(c, count, coef, xs, y, tol, cap, &capped)
+                                    : truncate_impl<float>(c, count, coef, xs, y, tol, cap, &capped);
+  if (st != TP_OK) return st;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return capped ? fail(TP_ERANK, "rank cap reached") : TP_OK;
+}
+
+tp_status tp_inner(tp_ctx* c, const tp_tensor* x, const tp_tensor* y, double* out) {
+  if (!c || !x || !y || !out) return fail(TP_EINVAL, "NULL argument");
+  TPCHK(check_tensor(x, "x", true));
+  TPCHK(check_tensor(y, "y", true));
+  if (!same_shape(x, y)) return fail(TP_EINVAL, "x and y differ in shape or precision");
+  return x->prec == TP_FP64 ? inner_impl<double>(c, x, y, out) : inner_impl<float>(c, x, y, out);
+}
+
+tp_status tp_eval_grid(tp_ctx* c, const tp_tensor* x, const int32_t* const* rows, const int32_t* mm_, double* out) {
+  if (!c || !x || !rows || !mm_ || !out) return fail(TP_EINVAL, "NULL argument");
+  TPCHK(check_tensor(x, "x", true));
+  const int d = x->d;
+  for (int m = 0; m < d; ++m)
+    if (mm_[m] < 1 || !rows[m]) return fail(TP_EINVAL, "rows[%d] empty", m);
+  WsScope scope(c);
+  size_t tot = (size_t)mm_[0] * mm_[1] * (d == 3 ? mm_[2] : 1);
+  if (is_zero(x)) {
+    HIPCHK(hipMemsetAsync(out, 0, sizeof(double) * tot, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return TP_OK;
+  }
+  double* Vr[3];
+  int r[3] = {x->rank[0], x->rank[1], d == 3 ? x->rank[2] : 1};
+  int p[3] = {mm_[0], mm_[1], d == 3 ? mm_[2] : 1};
+  for (int m = 0; m < d; ++m) {
+    TPCHK(wsalloc(c, (size_t)mm_[m] * r[m], &Vr[m]));
+    if (x->prec == TP_FP64)
+      HIPCHK(gather_rows<double>((const double*)x->factor[m], x->n[m], rows[m], mm_[m], r[m], Vr[m], c->stream));
+    else
+      HIPCHK(gather_rows<float>((const float*)x->factor[m], x->n[m], rows[m], mm_[m], r[m], Vr[m], c->stream));
+  }
+  size_t csz = (size_t)r[0] * r[1] * r[2];
+  double* Cd;
+  TPCHK(wsalloc(c, csz, &Cd));
+  if (x->prec == TP_FP64) HIPCHK((convert<double, double>((const double*)x->core, Cd, (long)csz, c->stream)));
+  else HIPCHK((convert<float, double>((const float*)x->core, Cd, (long)csz, c->stream)));
+  const double* A[3] = {Vr[0], Vr[1], d == 3 ? Vr[2] : nullptr};
+  int lda[3] = {p[0], p[1], p[2]};
+  bool tA[3] = {false, false, false};
+  TPCHK(tucker_contract(c, d, r, Cd, A, lda, tA, p, 1.0, 0.0, out));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return TP_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------ PCG
+namespace {
+
+struct Iter {
+  tp_tensor t;
+};
+
+template <typename T>
+tp_status make_tensor(tp_ctx* c, const tp_tensor* like, int cap, tp_tensor* out) {
+  *out = *like;
+  out->cap = cap;
+  for (int m = 0; m < 3; ++m) out->rank[m] = 0;
+  T* core;
+  size_t csz = (size_t)cap * cap * (like->d == 3 ? cap : 1);
+  TPCHK(wsalloc(c, csz, &core));
+  out->core = core;
+  for (int m = 0; m < like->d; ++m) {
+    T* f;
+    TPCHK(wsalloc(c, (size_t)like->n[m] * cap, &f));
+    out->factor[m] = f;
+  }
+  return TP_OK;
+}
+
+template <typename T>
+tp_status copy_tensor(tp_ctx* c, const tp_tensor* src, tp_tensor* dst) {
+  const int d = src->d;
+  size_t csz = (size_t)src->rank[0] * src->rank[1] * (d == 3 ? src->rank[2] : 1);
+  HIPCHK((convert<T, T>((const T*)src->core, (T*)dst->core, (long)csz, c->stream)));
+  for (int m = 0; m < d; ++m) {
+    HIPCHK((convert<T, T>((const T*)src->factor[m], (T*)dst->factor[m], (long)src->n[m] * src->rank[m], c->stream)));
+    dst->rank[m] = src->rank[m];
+  }
+  return TP_OK;
+}
+
+template <typename T>
+tp_status pcg_impl(tp_ctx* c, const tp_symbol* op, const tp_symbol* pre, const tp_cp* b, tp_tensor* x,
+                   const tp_pcg_opts* o, const tp_sketch* sk, tp_pcg_info* info) {
+  WsScope scope(c);
+  const int cap = o->cap;
+  const double eps = o->trunc_tol;
+  tp_tensor B, X, R, P, Z, S;
+  TPCHK(make_tensor<T>(c, x, cap, &B));
+  TPCHK(make_tensor<T>(c, x, cap, &X));
+  TPCHK(make_tensor<T>(c, x, cap, &R));
+  TPCHK(make_tensor<T>(c, x, cap, &P));
+  TPCHK(make_tensor<T>(c, x, cap, &Z));
+  TPCHK(make_tensor<T>(c, x, cap, &S));
+  info->iters = 0;
+  info->status = TP_OK;
+  info->rel_res = 0;
+  info->true_rel_res = -1;
+  info->op_applies = 0;
+  bool capped = false, anycap = false;
+  // B: exact Tucker form of the canonical right-hand side, truncated well below eps
+  TPCHK(from_cp_impl<T>(c, b, &B, eps * 1e-2, &capped));
+  anycap |= capped;
+  double nb2 = 0;
+  TPCHK(inner_impl<T>(c, &B, &B, &nb2));
+  if (!(nb2 > 0)) {
+    for (int m = 0; m < x->d; ++m) x->rank[m] = 0;
+    info->rank[0] = info->rank[1] = info->rank[2] = 0;
+    return TP_OK;
+  }
+  const double nb = std::sqrt(nb2);
+  TPCHK(copy_tensor<T>(c, &B, &R));  // R0 = B - fun(X0), X0 = 0
+  TPCHK(apply_impl<T>(c, pre, &R, &Z, eps, cap, sk, &capped));
+  anycap |= capped;
+  info->op_applies += 1;
+  TPCHK(copy_tensor<T>(c, &Z, &P));
+  double rz = 0;
+  TPCHK(inner_impl<T>(c, &R, &Z, &rz));
+  bool converged = false;
+  int k = 0;
+  for (; k < o->kmax; ++k) {
+    TPCHK(apply_impl<T>(c, op, &P, &S, eps, cap, sk, &capped));
+    anycap |= capped;
+    info->op_applies += 1;
+    double ps = 0;
+    TPCHK(inner_impl<T>(c, &P, &S, &ps));
+    if (!(ps > 0)) return fail(TP_ENOCONV, "PCG breakdown: <P,S> = %g", ps);
+    const double a = rz / ps;
+    {
+      const tp_tensor* xs[2] = {&X, &P};
+      double cf[2] = {1.0, a};
+      TPCHK(truncate_impl<T>(c, 2, cf, xs, &X, eps, cap, &capped));
+      anycap |= capped;
+    }
+    {
+      const tp_tensor* xs[2] = {&R, &S};
+      double cf[2] = {1.0, -a};
+      TPCHK(truncate_impl<T>(c, 2, cf, xs, &R, eps, cap, &capped));
+      anycap |= capped;
+    }
+    double rr = 0;
+    TPCHK(inner_impl<T>(c, &R, &R, &rr));
+    info->rel_res = std::sqrt(std::max(rr, 0.0)) / nb;
+    if (info->rel_res <= o->tau) { converged = true; ++k; break; }
+    TPCHK(apply_impl<T>(c, pre, &R, &Z, eps, cap, sk, &capped));
+    anycap |= capped;
+    info->op_applies += 1;
+    double rz_new = 0;
+    TPCHK(inner_impl<T>(c, &R, &Z, &rz_new));
+    const double beta = rz_new / rz;
+    rz = rz_new;
+    {
+      const tp_tensor* xs[2] = {&Z, &P};
+      double cf[2] = {1.0, beta};
+      TPCHK(truncate_impl<T>(c, 2, cf, xs, &P, eps, cap, &capped));
+      anycap |= capped;
+    }
+  }
+  info->iters = k;
+  TPCHK(copy_tensor<T>(c, &X, x));
+  for (int m = 0; m < 3; ++m) info->rank[m] = m < x->d ? x->rank[m] : 0;
+  if (o->true_residual) {
+    // ||B - A_2 X|| with a tight product truncation
+    TPCHK(apply_impl<T>(c, op, &X, &S, std::min(1e-3 * o->tau, 1e-10), cap, sk, &capped));
+    double bb = nb2, bs = 0, ss = 0;
+    TPCHK(inner_impl<T>(c, &B, &S, &bs));
+    TPCHK(inner_impl<T>(c, &S, &S, &ss));
+    info->true_rel_res = std::sqrt(std::max(bb - 2 * bs + ss, 0.0)) / nb;
+  }
+  if (!converged) {
+    info->status = TP_ENOCONV;
+    return fail(TP_ENOCONV, "PCG did not reach tau=%g in %d iterations (rel_res %g)", o->tau, o->kmax, info->rel_res);
+  }
+  info->status = anycap ? TP_ERANK : TP_OK;
+  return TP_OK;
+}
+
+}  // namespace
+
+extern "C" tp_status tp_pcg_solve(tp_ctx* c, const tp_symbol* op, const tp_symbol* pre, const tp_cp* b, tp_tensor* x,
+                                  const tp_pcg_opts* o, const tp_sketch* sk, tp_pcg_info* info) {
+  if (!c || !op || !pre || !b || !x || !o || !sk || !info) return fail(TP_EINVAL, "NULL argument");
+  TPCHK(check_tensor(x, "x", false));
+  if (op->kind != 0 || pre->kind != 1) return fail(TP_EINVAL, "op/pre symbols swapped");
+  if (op->prec != x->prec || pre->prec != x->prec) return fail(TP_EINVAL, "symbol precision differs from x");
+  if (b->d != x->d || op->d != x->d) return fail(TP_EINVAL, "dimension mismatch");
+  for (int m = 0; m < x->d; ++m)
+    if (b->n[m] != x->n[m] || op->n[m] != x->n[m] || pre->n[m] != x->n[m])
+      return fail(TP_EINVAL, "grid mismatch in mode %d", m);
+  if (o->cap < 1 || o->cap > x->cap) return fail(TP_EINVAL, "opts.cap=%d must be in [1, x.cap=%d]", o->cap, x->cap);
+  if (!(o->tau > 0) || o->kmax < 1 || !(o->trunc_tol > 0)) return fail(TP_EINVAL, "invalid PCG options");
+  if (sk->q < 2 || sk->q > kMaxSketch) return fail(TP_EINVAL, "sketch q=%d must be in [2,%d]", sk->q, kMaxSketch);
+  if (b->rank < 0 || b->rank > kMaxRank) return fail(TP_EINVAL, "b.rank=%d outside [0,%d]", b->rank, kMaxRank);
+  tp_status st = x->prec == TP_FP64 ? pcg_impl<double>(c, op, pre, b, x, o, sk, info)
+                                    : pcg_impl<float>(c, op, pre, b, x, o, sk, info);
+  if (st != TP_OK && st != TP_ENOCONV) info->status = st;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail(TP_EHIP, "stream sync: %s", hipGetErrorString(e));
+  if (st == TP_OK && info->status == TP_ERANK) return fail(TP_ERANK, "rank cap reached during the solve");
+  return st;
+}

@@ -1,0 +1,98 @@
+// Internal declarations shared by the kernel and host translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace tpk {
+
+// Face-split operand: F[row, c] = X1[row + ld1*(c % r1)] * X2[row + ld2*(c / r1)] * (w ? w[c / r1] : 1).
+// It stands for the Hadamard products u_k (.) x_j of the low-rank matrix-vector
+// product without forming them.
+template <typename T>
+struct FaceSplit {
+  const T* x1 = nullptr;
+  const T* x2 = nullptr;
+  const double* w = nullptr;
+  int ld1 = 0, ld2 = 0, r1 = 1;
+};
+
+// op(A) is M x K, op(B) is K x N, C is M x N, all column-major.
+// Batch b uses A + (b / divA) * sA, B + (b / divB) * sB, C + b * sC.
+template <typename TA, typename TB, typename TC, typename Tacc>
+struct GemmArgs {
+  int M = 0, N = 0, K = 0, batch = 1;
+  Tacc alpha = 1, beta = 0;
+  const TA* A = nullptr; int lda = 0; long sA = 0; int divA = 1; bool tA = false; bool fsA = false; FaceSplit<TA> FA;
+  const TB* B = nullptr; int ldb = 0; long sB = 0; int divB = 1; bool tB = false; bool fsB = false; FaceSplit<TB> FB;
+  TC* C = nullptr; int ldc = 0; long sC = 0;
+};
+
+template <typename TA, typename TB, typename TC, typename Tacc>
+hipError_t gemm(const GemmArgs<TA, TB, TC, Tacc>& g, hipStream_t s);
+
+// Orthonormal DST-I on `cols` columns of length n = N-1 (N a power of two).
+// tab holds cos(pi m/N), sin(pi m/N), m = 0..N-1, interleaved.
+template <typename T>
+hipError_t dst1(int N, int cols, const T* in, int ldin, T* out, int ldout, const T* tab, hipStream_t s);
+
+template <typename T>
+hipError_t dst_table(int N, T* tab, hipStream_t s);
+
+// Batched symmetric Jacobi eigensolver, FP64.  Matrix b: K[b] x K[b] at a[b] (ld K[b]);
+// eigenvalues (descending) to w[b], eigenvectors to v[b] (ld K[b]).
+// Matrices larger than 128 need `work` (Kp x Kp doubles, Kp = K rounded up to even) in global memory.
+struct EigJob { int K; const double* a; double* w; double* v; double* work; };
+hipError_t syev_batched(const EigJob* jobs_dev, int count, int Kmax, hipStream_t s);
+
+// Elementwise helpers.
+template <typename TI, typename TO>
+hipError_t convert(const TI* in, TO* out, long count, hipStream_t s);
+// Copy a rows x cols column-major block (lds in/out) with scale.
+template <typename TI, typename TO>
+hipError_t copy2d(int rows, int cols, const TI* in, int ldin, TO* out, int ldout, double scale, hipStream_t s);
+// out[i,j,l] (dims d0,d1,d2 packed) -> permuted: perm gives which input axis becomes output axis 0,1,2.
+template <typename T>
+hipError_t permute3(const T* in, int d0, int d1, int d2, T* out, int p0, int p1, int p2, hipStream_t s);
+// Columns scaled: out[:,j] = in[:,j] * scale[j] (rows x cols, ld), in place allowed.
+hipError_t scale_cols_d(double* a, int rows, int cols, int ld, const double* scale, hipStream_t s);
+// W = E[:, 0:q] * diag(1/sqrt(w)) for the leading q eigenpairs; K rows, ld K.
+hipError_t eig_inv_sqrt(const double* E, const double* w, int K, int q, double* W, hipStream_t s);
+// out = sum(a[i]*b[i]) in FP64 (single value, written to out[0]).
+template <typename T>
+hipError_t dot(const T* a, const T* b, long count, double* out, hipStream_t s);
+// Face-split dense materialisation: out[(b,c), k] = X2[b,k] * X3[c,k] (q2*q3 x R), used for CP cores.
+hipError_t khatri_rao_d(const double* X2, int q2, const double* X3, int q3, int R, double* out, hipStream_t s);
+// t[i, col] = sum_j T1[i + rm*(j + ro*col)] * A[j + ro*col]
+template <typename T>
+hipError_t contract_mid(const T* T1, const T* A, int rm, int ro, int ncol, T* t, hipStream_t s);
+// Gather rows: out[p, c] = in[rows[p] + ld*c]
+template <typename T>
+hipError_t gather_rows(const T* in, int ld, const int* rows, int m, int cols, double* out, hipStream_t s);
+
+// Symbol construction.
+hipError_t lambda_1d(int n, double* out, hipStream_t s);
+// exponential-sum factor columns for a mode with eigenvalues lam (n) and exponents tau (K):
+// E[:,k] = exp(-tau_k lam), times lam when withLam (the Lemma 4.1 factor).
+template <typename T>
+hipError_t expfactors(const double* lam, int n, const double* tau, int K, T* E, int ldE, int withLam, hipStream_t s);
+// least-squares design matrix for candidate c: rows y_j (m), columns t_k (K):
+// A[j,k] = exp(-t_k y_j) / f(y_j); f selected by kind (0: g, 1: 1/s).  Candidates stacked.
+struct FitCand { double a, b; };
+hipError_t fit_design(int kind, double alpha, double cneg, double cpos, double rho0, double B, int K, int m,
+                      const FitCand* cands_dev, int ncand, double* A, double* tvec, hipStream_t s);
+// Column norms (for scaling) and b = A^T 1 etc. handled with gemm; max error evaluation:
+hipError_t fit_error(int kind, double alpha, double cneg, double cpos, double rho0, double B, int K,
+                     const double* t, const double* w, int ncand, int m, double* err, hipStream_t s);
+hipError_t sinc_g_nodes(double alpha, double cneg, double cpos, double rho0, int kl, int kr, double hh,
+                        double* tau, double* w, hipStream_t s);
+hipError_t symbol_eval(int d, const int* idx, int count, const double* lam0, const double* lam1,
+                       const double* lam2, int opkind, int K, const double* tau, const double* w, double* out,
+                       hipStream_t s);
+
+hipError_t fit_scale(int K, int nc, double* G, double* b, double* D, hipStream_t s);
+hipError_t fit_solve(int K, int nc, const double* ev, const double* E, const double* b, const double* D, double cut,
+                     double* w, hipStream_t s);
+hipError_t scale(double* a, long n, double sc, hipStream_t s);
+
+}  // namespace tpk

@@ -1,0 +1,108 @@
+"""End-to-end parity of the GPU PCG control solve against the exact oracle O1."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import exact, spectral, tensor
+from tests.gpu_helpers import log, rel
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-6     # relative error vs the exact control, FP64 mode
+MIXED_TOL = 1e-4    # relative error vs the exact control, mixed precision
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1809_01971_amd as tp
+    c = tp.Context(0, workspace_bytes=8 << 30)
+    yield c
+    c.close()
+
+
+def solve(ctx, p, prec, eps, tau, cap=64, q=None, op_terms=32, pre_terms=12):
+    """The sketch width is the cap plus an oversampling of 16 columns."""
+    import paper_1809_01971_amd as tp
+    from paper_1809_01971_amd._tp import sketch_tensors
+    op, pre, errs = ctx.symbol_build(p.d, p.n, p.alpha, p.c_neg, p.c_pos, prec=prec, op_terms=op_terms,
+                                     pre_terms=pre_terms)
+    q = q or min(cap + 16, 192)
+    sk = sketch_tensors(workloads.sketch_matrices(p.n, p.d, q))
+    X = tp.Tensor(p.d, p.n, cap, prec)
+    st, info = ctx.pcg_solve(op, pre, p.weights, p.factors, X, tau=tau, kmax=100, trunc_tol=eps, cap=cap,
+                             sketch=sk, true_residual=True)
+    info["sym_err"] = errs
+    return X, st, info
+
+
+def test_cfg1_2d_fp64_against_full_grid_and_brute_force(ctx):
+    p = workloads.cfg1()
+    log("cfg1 fp64")
+    X, st, info = solve(ctx, p, 0, eps=1e-9, tau=1e-10, op_terms=40)
+    f = tensor.cp_full(p.weights, p.factors)
+    u = exact.solve_full(f, p.alpha, p.c_neg, p.c_pos)
+    got = ctx.eval_grid(X, [np.arange(p.n)] * 2)
+    err = rel(got, u)
+    log("  cfg1 err %.2e info %s" % (err, info))
+    assert err < FP64_TOL
+    assert info["iters"] <= 20
+
+
+def test_cfg1_2d_mixed(ctx):
+    p = workloads.cfg1()
+    log("cfg1 mixed")
+    X, st, info = solve(ctx, p, 1, eps=1e-6, tau=1e-6)
+    u = exact.solve_full(tensor.cp_full(p.weights, p.factors), p.alpha, p.c_neg, p.c_pos)
+    err = rel(ctx.eval_grid(X, [np.arange(p.n)] * 2), u)
+    log("  cfg1 mixed err %.2e info %s" % (err, info))
+    assert err < MIXED_TOL
+
+
+@pytest.mark.parametrize("n,ks", [(63, (3, 5)), (2047, (1, 2)), (2047, (700, 3))])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_single_sine_mode_closed_form(ctx, n, ks, prec):
+    d = len(ks)
+    p = workloads.sine_mode_problem(n, d, ks, 0.5, 1.0, 1e-2)
+    log("sine mode n=%d ks=%s prec=%d" % (n, ks, prec))
+    X, st, info = solve(ctx, p, prec, eps=1e-8 if prec == 0 else 1e-6, tau=1e-9 if prec == 0 else 1e-6, cap=8, q=16)
+    fac = exact.single_mode_factor((n,) * d, ks, 0.5, 1.0, 1e-2)
+    rows = [np.arange(0, n, max(1, n // 64))] * d
+    got = ctx.eval_grid(X, rows)
+    ref = fac * tensor.cp_full(p.weights, [f[r] for f, r in zip(p.factors, rows)])
+    err = rel(got, ref)
+    log("  err %.2e info %s" % (err, info))
+    assert err < (FP64_TOL if prec == 0 else MIXED_TOL)
+
+
+@pytest.mark.parametrize("alpha,gamma", [(0.5, 1e-2), (0.25, 1e-1), (0.75, 1e-3)])
+def test_cfg2_type_n63_fp64(ctx, alpha, gamma):
+    p = workloads.cfg2(alpha=alpha, gamma=gamma, n=63)
+    log("cfg2-type n=63 alpha=%g gamma=%g" % (alpha, gamma))
+    X, st, info = solve(ctx, p, 0, eps=1e-8, tau=1e-9)
+    u = exact.solve_full(tensor.cp_full(p.weights, p.factors), p.alpha, p.c_neg, p.c_pos)
+    err = rel(ctx.eval_grid(X, [np.arange(p.n)] * 3), u)
+    log("  err %.2e info %s" % (err, info))
+    assert err < FP64_TOL
+
+
+@pytest.mark.parametrize("alpha,gamma", [(0.5, 1e-1), (0.25, 1e-3), (0.75, 1e-1)])
+def test_cfg2_n255_fp64(ctx, alpha, gamma):
+    p = workloads.cfg2(alpha=alpha, gamma=gamma)
+    log("cfg2 n=255 alpha=%g gamma=%g" % (alpha, gamma))
+    assert p.n == 255
+    X, st, info = solve(ctx, p, 0, eps=2e-7, tau=2e-7, cap=96)
+    u = exact.solve_full(tensor.cp_full(p.weights, p.factors), p.alpha, p.c_neg, p.c_pos)
+    err = rel(ctx.eval_grid(X, [np.arange(p.n)] * 3), u)
+    log("  err %.2e info %s" % (err, info))
+    assert err < FP64_TOL
+
+
+@pytest.mark.parametrize("alpha,gamma", [(0.5, 1e-1), (0.25, 1e-3)])
+def test_cfg2_n255_mixed(ctx, alpha, gamma):
+    p = workloads.cfg2(alpha=alpha, gamma=gamma)
+    log("cfg2 mixed n=255 alpha=%g gamma=%g" % (alpha, gamma))
+    X, st, info = solve(ctx, p, 1, eps=2e-5, tau=2e-5, cap=64)
+    u = exact.solve_full(tensor.cp_full(p.weights, p.factors), p.alpha, p.c_neg, p.c_pos)
+    err = rel(ctx.eval_grid(X, [np.arange(p.n)] * 3), u)
+    log("  err %.2e info %s" % (err, info))
+    assert err < MIXED_TOL
