@@ -169,6 +169,20 @@ tp_status tp_from_cp(tp_ctx* ctx, const tp_cp* b, tp_tensor* out, double tol);
 tp_status tp_apply(tp_ctx* ctx, const tp_symbol* sym, const tp_tensor* x, tp_tensor* y,
                    double tol, int32_t cap, const tp_sketch* sketch);
 
+/* y = trunc(sum_i coef[i] F(s_i (.) F xs[i])) for count <= 8 terms; syms[i] == NULL stands
+ * for the identity.  The whole sum is truncated at once by the sketched HOSVD of tp_apply,
+ * so the truncation error is relative to the norm of the sum (the PCG residual update
+ * R - alpha fun(P) uses it).  syms, xs, coef: host arrays of count entries.  y may alias
+ * any xs[i]. */
+tp_status tp_apply_sum(tp_ctx* ctx, int32_t count, const tp_symbol* const* syms,
+                       const tp_tensor* const* xs, const double* coef, tp_tensor* y, double tol,
+                       int32_t cap, const tp_sketch* sketch);
+
+/* <x, F(s (.) F y)> without truncation, from the Gram matrices G_k = (F X)^T diag(s_k) (F Y)
+ * of every symbol term and the cores (out is host). */
+tp_status tp_inner_sym(tp_ctx* ctx, const tp_tensor* x, const tp_symbol* sym, const tp_tensor* y,
+                       double* out);
+
 /* y = trunc(sum_i coef[i] * xs[i]) by the exact HOSVD of the sum (Sec. 5, RHOSVD
  * step of Algorithm alg:pcg's trunc): factors are concatenated, orthonormalised,
  * the block core is projected and its mode Gram matrices are diagonalised in FP64.
@@ -190,7 +204,7 @@ tp_status tp_eval_grid(tp_ctx* ctx, const tp_tensor* x, const int32_t* const* ro
  * PCG  (Algorithm alg:pcg)
  * ------------------------------------------------------------------------- */
 typedef struct {
-  double tau;        /* stop when ||R||/||B|| <= tau */
+  double tau;        /* stop when ||Z|| <= tau ||X||, Z = trunc(pre(R)) the preconditioned residual */
   int32_t kmax;      /* iteration limit (paper: 100) */
   double trunc_tol;  /* relative truncation tolerance epsilon of trunc */
   int32_t cap;       /* mode-rank cap of every iterate (<= x->cap) */
@@ -204,10 +218,13 @@ typedef struct {
   double rel_res;    /* ||R||/||B|| of the recursive residual */
   double true_rel_res;  /* only if requested, else -1 */
   double op_applies; /* number of operator/preconditioner products */
+  double err_est;    /* ||Z||/||X|| at the last step (the stopping quantity) */
 } tp_pcg_info;
 
 /* Solve A_2 x = b with the operator symbol `op`, the preconditioner symbol `pre`
- * and X0 = 0.  Iterates are Tucker tensors (the mixed Tucker-canonical route of
+ * and X0 = 0.  Each step: alpha = <R,Z>/<P,fun(P)> with fun(P) kept exact, X = trunc(X + alpha P),
+ * R = trunc(B - fun(X)) (recomputed, one sketched sum), Z = trunc(pre(R)), stop when
+ * ||Z|| <= tau ||X||, P = trunc(Z + beta P).  Iterates are Tucker tensors (the mixed Tucker-canonical route of
  * Sec. 5); every update is truncated as in Algorithm alg:pcg.  x->prec selects
  * the arithmetic; op and pre must have been built with that precision. */
 tp_status tp_pcg_solve(tp_ctx* ctx, const tp_symbol* op, const tp_symbol* pre,
@@ -246,6 +263,10 @@ typedef enum {
   TP_PROF_DST_F32 = 5,
   TP_PROF_SYEV = 6
 } tp_prof_class;
+
+/* Contraction kernels: mfma != 0 (default) uses the FP32/FP64 matrix-core tiles, 0 the FMA
+ * tiles.  Process-wide; both give the same results up to rounding order. */
+tp_status tp_gemm_mode(int32_t mfma);
 
 /* enable != 0: record a HIP event pair around every launch of the classes above on the
  * context stream (and reset the totals); enable == 0: stop recording. */

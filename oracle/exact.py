@@ -106,3 +106,29 @@ def solve_cp_restricted_slabs(weights, factors, alpha, c_neg, c_pos, rows, slabs
         W = slab / (c_neg * rho ** (-alpha) + c_pos * rho**alpha)
         out += np.multiply.outer(Fr[0][:, i1], Fr[1] @ W @ Fr[2].T)
     return out
+
+
+def tucker_error_slabs(weights, factors, alpha, c_neg, c_pos, core, tfactors, slabs):
+    """Partial sums over first-index slabs of the spectral (Parseval) identity
+    ||X - u||^2 = sum_i (Xhat_i - fhat_i / s(rho_i))^2 and ||u||^2 = sum_i (fhat_i/s(rho_i))^2,
+    where u is the exact control for the canonical right-hand side (weights, factors) and
+    X = core x_1 T1 x_2 T2 x_3 T3 a Tucker tensor (any factors).  F is orthogonal, so the sums over
+    spectral indices equal the grid sums.  Returns (sum of squared errors, sum of squared u)."""
+    w = np.asarray(weights, dtype=np.float64)
+    ns = [f.shape[0] for f in factors]
+    lam = [spectral.eigenvalues(n) for n in ns]
+    Fh = [spectral.dst(f) for f in factors]
+    Th = [spectral.dst(np.asarray(t, dtype=np.float64)) for t in tfactors]
+    C = np.asarray(core, dtype=np.float64)
+    rho23 = lam[1][:, None] + lam[2][None, :]
+    err2 = 0.0
+    u2 = 0.0
+    for i1 in slabs:
+        fh = (Fh[1] * (w * Fh[0][i1])) @ Fh[2].T
+        rho = lam[0][i1] + rho23
+        uh = fh / (c_neg * rho ** (-alpha) + c_pos * rho**alpha)
+        Ca = np.tensordot(Th[0][i1], C, axes=([0], [0]))          # r2 x r3
+        xh = Th[1] @ Ca @ Th[2].T
+        err2 += float(np.sum((xh - uh) ** 2))
+        u2 += float(np.sum(uh * uh))
+    return err2, u2

@@ -50,7 +50,8 @@ class tp_pcg_opts(C.Structure):
 
 class tp_pcg_info(C.Structure):
     _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("rank", C.c_int32 * 3),
-                ("rel_res", C.c_double), ("true_rel_res", C.c_double), ("op_applies", C.c_double)]
+                ("rel_res", C.c_double), ("true_rel_res", C.c_double), ("op_applies", C.c_double),
+                ("err_est", C.c_double)]
 
 
 P = C.c_void_p
@@ -69,6 +70,9 @@ _SIGS = {
     "tp_truncate": ([P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.POINTER(tp_tensor)),
                      C.POINTER(tp_tensor), C.c_double, C.c_int32], C.c_int),
     "tp_inner": ([P, C.POINTER(tp_tensor), C.POINTER(tp_tensor), C.POINTER(C.c_double)], C.c_int),
+    "tp_inner_sym": ([P, C.POINTER(tp_tensor), P, C.POINTER(tp_tensor), C.POINTER(C.c_double)], C.c_int),
+    "tp_apply_sum": ([P, C.c_int32, C.POINTER(P), C.POINTER(C.POINTER(tp_tensor)), C.POINTER(C.c_double),
+                      C.POINTER(tp_tensor), C.c_double, C.c_int32, C.POINTER(tp_sketch)], C.c_int),
     "tp_eval_grid": ([P, C.POINTER(tp_tensor), C.POINTER(P), C.POINTER(C.c_int32), P], C.c_int),
     "tp_pcg_solve": ([P, P, P, C.POINTER(tp_cp), C.POINTER(tp_tensor), C.POINTER(tp_pcg_opts),
                       C.POINTER(tp_sketch), C.POINTER(tp_pcg_info)], C.c_int),
@@ -76,6 +80,7 @@ _SIGS = {
     "tp_syev": ([P, C.c_int32, C.c_int32, P, P, P], C.c_int),
     "tp_lambda": ([P, C.c_int32, P], C.c_int),
     "tp_profile": ([P, C.c_int32], C.c_int),
+    "tp_gemm_mode": ([C.c_int32], C.c_int),
     "tp_profile_read": ([P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
                          C.POINTER(C.c_double)], C.c_int),
 }
@@ -174,6 +179,9 @@ class Context:
         return out
 
     # ---- measurement
+    def gemm_mode(self, mfma=True):
+        _check(self.lib.tp_gemm_mode(1 if mfma else 0))
+
     def profile(self, enable=True):
         _check(self.lib.tp_profile(self.h, 1 if enable else 0))
 
@@ -225,6 +233,22 @@ class Context:
         y._sync_ranks()
         return st
 
+    def apply_sum(self, syms, xs, coefs, y, tol, cap, sketch, allow_erank=False):
+        n = len(xs)
+        sk, keep = sketch_struct(sketch)
+        sa = (P * n)(*[s.h if s is not None else None for s in syms])
+        arr = (C.POINTER(tp_tensor) * n)(*[C.pointer(x.s) for x in xs])
+        cf = (C.c_double * n)(*coefs)
+        st = _check(self.lib.tp_apply_sum(self.h, n, sa, arr, cf, C.byref(y.s), tol, cap, C.byref(sk)),
+                    allow=(TP_ERANK,) if allow_erank else ())
+        y._sync_ranks()
+        return st
+
+    def inner_sym(self, x, sym, y):
+        out = C.c_double()
+        _check(self.lib.tp_inner_sym(self.h, C.byref(x.s), sym.h, C.byref(y.s), C.byref(out)))
+        return out.value
+
     def inner(self, x, y):
         out = C.c_double()
         _check(self.lib.tp_inner(self.h, C.byref(x.s), C.byref(y.s), C.byref(out)))
@@ -252,7 +276,7 @@ class Context:
         x._sync_ranks()
         return st, {"iters": info.iters, "status": info.status, "rank": list(info.rank)[:x.d],
                     "rel_res": info.rel_res, "true_rel_res": info.true_rel_res,
-                    "applies": info.op_applies}
+                    "applies": info.op_applies, "err_est": info.err_est}
 
 
 class Symbol:

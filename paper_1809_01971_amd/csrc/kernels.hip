@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <type_traits>
+
 namespace tpk {
 
 // ---------------------------------------------------------------------------------------------
@@ -32,7 +34,10 @@ __global__ __launch_bounds__(GTHREADS) void k_gemm(GemmArgs<TA, TB, TC, Tacc> g)
   __shared__ Tacc Bs[GBK][GBN + 1];
   const int tid = threadIdx.x;
   const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
-  const int b = blockIdx.z;
+  const int b = blockIdx.z / g.splits;
+  const int sp = blockIdx.z - b * g.splits;
+  const int kbeg = sp * g.kchunk;
+  const int kend = min(g.K, kbeg + g.kchunk);
   const TA* A = g.A ? g.A + (long)(b / g.divA) * g.sA : nullptr;
   const TB* B = g.B ? g.B + (long)(b / g.divB) * g.sB : nullptr;
   FaceSplit<TA> FA = g.FA;
@@ -47,7 +52,7 @@ __global__ __launch_bounds__(GTHREADS) void k_gemm(GemmArgs<TA, TB, TC, Tacc> g)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = 0;
 
-  for (int k0 = 0; k0 < g.K; k0 += GBK) {
+  for (int k0 = kbeg; k0 < kend; k0 += GBK) {
     // A tile: op(A)[m0+m, k0+kk]
     if (!g.tA) {
 #pragma unroll
@@ -55,7 +60,7 @@ __global__ __launch_bounds__(GTHREADS) void k_gemm(GemmArgs<TA, TB, TC, Tacc> g)
         int m = tid % 64, kk = tid / 64 + 4 * i;
         int row = m0 + m, col = k0 + kk;
         Tacc v = 0;
-        if (row < g.M && col < g.K) v = g.fsA ? (Tacc)fs_load(FA, row, col) : (Tacc)A[row + (long)g.lda * col];
+        if (row < g.M && col < kend) v = g.fsA ? (Tacc)fs_load(FA, row, col) : (Tacc)A[row + (long)g.lda * col];
         As[kk][m] = v;
       }
     } else {
@@ -64,7 +69,7 @@ __global__ __launch_bounds__(GTHREADS) void k_gemm(GemmArgs<TA, TB, TC, Tacc> g)
         int kk = tid % 16, m = tid / 16 + 16 * i;
         int row = m0 + m, col = k0 + kk;
         Tacc v = 0;
-        if (row < g.M && col < g.K) v = (Tacc)A[col + (long)g.lda * row];
+        if (row < g.M && col < kend) v = (Tacc)A[col + (long)g.lda * row];
         As[kk][m] = v;
       }
     }
@@ -75,7 +80,7 @@ __global__ __launch_bounds__(GTHREADS) void k_gemm(GemmArgs<TA, TB, TC, Tacc> g)
         int kk = tid % 16, n = tid / 16 + 16 * i;
         int row = k0 + kk, col = n0 + n;
         Tacc v = 0;
-        if (row < g.K && col < g.N) v = g.fsB ? (Tacc)fs_load(FB, row, col) : (Tacc)B[row + (long)g.ldb * col];
+        if (row < kend && col < g.N) v = g.fsB ? (Tacc)fs_load(FB, row, col) : (Tacc)B[row + (long)g.ldb * col];
         Bs[kk][n] = v;
       }
     } else {
@@ -84,7 +89,7 @@ __global__ __launch_bounds__(GTHREADS) void k_gemm(GemmArgs<TA, TB, TC, Tacc> g)
         int n = tid % 64, kk = tid / 64 + 4 * i;
         int row = k0 + kk, col = n0 + n;
         Tacc v = 0;
-        if (row < g.K && col < g.N) v = (Tacc)B[col + (long)g.ldb * row];
+        if (row < kend && col < g.N) v = (Tacc)B[col + (long)g.ldb * row];
         Bs[kk][n] = v;
       }
     }
@@ -103,6 +108,21 @@ __global__ __launch_bounds__(GTHREADS) void k_gemm(GemmArgs<TA, TB, TC, Tacc> g)
     }
     __syncthreads();
   }
+  if (g.part) {
+    // split-K: raw partial sums, reduced by k_gemm_reduce
+    Tacc* Pp = g.part + (long)blockIdx.z * g.M * g.N;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      int row = m0 + tm + 16 * i;
+      if (row >= g.M) continue;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        int col = n0 + tn + 16 * j;
+        if (col < g.N) Pp[row + (long)g.M * col] = acc[i][j];
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     int row = m0 + tm + 16 * i;
@@ -119,14 +139,163 @@ __global__ __launch_bounds__(GTHREADS) void k_gemm(GemmArgs<TA, TB, TC, Tacc> g)
   }
 }
 
+// MFMA variant: the same tiling and loaders, and each of the 4 waves owns a 32x32 quarter of
+// the 64x64 tile as 2x2 MFMA 16x16x4 blocks (FP32 or FP64 matrix cores).  Operand layout of the
+// single-block 16x16x4 instructions: lane l supplies A[l%16][l/16] and B[l/16][l%16]; it
+// receives D[4*(l/16)+v][l%16], v = 0..3.
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f4_t mfma16(float a, float b, f4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ d4_t mfma16(double a, double b, d4_t c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <typename TA, typename TB, typename TC, typename Tacc>
+__global__ __launch_bounds__(GTHREADS) void k_gemm_mfma(GemmArgs<TA, TB, TC, Tacc> g) {
+  typedef typename std::conditional<std::is_same<Tacc, double>::value, d4_t, f4_t>::type V4;
+  __shared__ Tacc As[GBK][GBM + 4];
+  __shared__ Tacc Bs[GBK][GBN + 4];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
+  const int b = blockIdx.z / g.splits;
+  const int sp = blockIdx.z - b * g.splits;
+  const int kbeg = sp * g.kchunk;
+  const int kend = min(g.K, kbeg + g.kchunk);
+  const TA* A = g.A ? g.A + (long)(b / g.divA) * g.sA : nullptr;
+  const TB* B = g.B ? g.B + (long)(b / g.divB) * g.sB : nullptr;
+  FaceSplit<TA> FA = g.FA;
+  FaceSplit<TB> FB = g.FB;
+  if (g.fsA) { FA.x1 += (long)(b / g.divA) * g.sA; FA.x2 += (long)(b / g.divA) * g.sA; }
+  if (g.fsB) { FB.x1 += (long)(b / g.divB) * g.sB; FB.x2 += (long)(b / g.divB) * g.sB; }
+  TC* C = g.C + (long)b * g.sC;
+  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  V4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
+
+  for (int k0 = kbeg; k0 < kend; k0 += GBK) {
+    if (!g.tA) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        int m = tid % 64, kk = tid / 64 + 4 * i;
+        int row = m0 + m, col = k0 + kk;
+        Tacc v = 0;
+        if (row < g.M && col < kend) v = g.fsA ? (Tacc)fs_load(FA, row, col) : (Tacc)A[row + (long)g.lda * col];
+        As[kk][m] = v;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        int kk = tid % 16, m = tid / 16 + 16 * i;
+        int row = m0 + m, col = k0 + kk;
+        Tacc v = 0;
+        if (row < g.M && col < kend) v = (Tacc)A[col + (long)g.lda * row];
+        As[kk][m] = v;
+      }
+    }
+    if (!g.tB) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        int kk = tid % 16, n = tid / 16 + 16 * i;
+        int row = k0 + kk, col = n0 + n;
+        Tacc v = 0;
+        if (row < kend && col < g.N) v = g.fsB ? (Tacc)fs_load(FB, row, col) : (Tacc)B[row + (long)g.ldb * col];
+        Bs[kk][n] = v;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        int n = tid % 64, kk = tid / 64 + 4 * i;
+        int row = k0 + kk, col = n0 + n;
+        Tacc v = 0;
+        if (row < kend && col < g.N) v = (Tacc)B[col + (long)g.ldb * row];
+        Bs[kk][n] = v;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GBK; kk += 4) {
+      const int kr = kk + (lane >> 4), c16 = lane & 15;
+      Tacc a0 = As[kr][wm + c16], a1 = As[kr][wm + 16 + c16];
+      Tacc b0 = Bs[kr][wn + c16], b1 = Bs[kr][wn + 16 + c16];
+      acc[0][0] = mfma16(a0, b0, acc[0][0]);
+      acc[0][1] = mfma16(a0, b1, acc[0][1]);
+      acc[1][0] = mfma16(a1, b0, acc[1][0]);
+      acc[1][1] = mfma16(a1, b1, acc[1][1]);
+    }
+    __syncthreads();
+  }
+  const int rbase = 4 * (lane >> 4), cl = lane & 15;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int row = m0 + wm + 16 * i + rbase + v;
+        int col = n0 + wn + 16 * j + cl;
+        if (row >= g.M || col >= g.N) continue;
+        Tacc x = acc[i][j][v];
+        if (g.part) {
+          g.part[(long)blockIdx.z * g.M * g.N + row + (long)g.M * col] = x;
+        } else {
+          long o = row + (long)g.ldc * col;
+          Tacc y = g.alpha * x;
+          if (g.beta != (Tacc)0) y += g.beta * (Tacc)C[o];
+          C[o] = (TC)y;
+        }
+      }
+}
+
+template <typename TC, typename Tacc>
+__global__ void k_gemm_reduce(int M, int N, int splits, const Tacc* part, Tacc alpha, Tacc beta, TC* C, int ldc,
+                              long sC) {
+  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  int b = blockIdx.y;
+  long mn = (long)M * N;
+  if (e >= mn) return;
+  int row = (int)(e % M), col = (int)(e / M);
+  const Tacc* p = part + (long)b * splits * mn + e;
+  Tacc acc = 0;
+  for (int s = 0; s < splits; ++s) acc += p[(long)s * mn];
+  long o = (long)b * sC + row + (long)ldc * col;
+  Tacc v = alpha * acc;
+  if (beta != (Tacc)0) v += beta * (Tacc)C[o];
+  C[o] = (TC)v;
+}
+
+static int g_use_mfma = 1;
+bool gemm_use_mfma() { return g_use_mfma != 0; }
+void gemm_set_mfma(int on) { g_use_mfma = on; }
+
 template <typename TA, typename TB, typename TC, typename Tacc>
 hipError_t gemm(const GemmArgs<TA, TB, TC, Tacc>& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
   if (g.K <= 0) {
     // C = beta*C: handled by a degenerate launch with K = 0 (the loop body is skipped).
   }
-  dim3 grid((g.M + GBM - 1) / GBM, (g.N + GBN - 1) / GBN, g.batch);
-  hipLaunchKernelGGL((k_gemm<TA, TB, TC, Tacc>), grid, dim3(GTHREADS), 0, s, g);
+  GemmArgs<TA, TB, TC, Tacc> h = g;
+  if (h.splits < 1 || !h.part) { h.splits = 1; h.part = nullptr; }
+  h.kchunk = h.splits > 1 ? ((h.K + h.splits - 1) / h.splits + GBK - 1) / GBK * GBK : h.K;
+  dim3 grid((h.M + GBM - 1) / GBM, (h.N + GBN - 1) / GBN, h.batch * h.splits);
+  if (gemm_use_mfma())
+    hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TC, Tacc>), grid, dim3(GTHREADS), 0, s, h);
+  else
+    hipLaunchKernelGGL((k_gemm<TA, TB, TC, Tacc>), grid, dim3(GTHREADS), 0, s, h);
+  if (h.splits > 1) {
+    long mn = (long)h.M * h.N;
+    dim3 rg((mn + 255) / 256, h.batch);
+    hipLaunchKernelGGL((k_gemm_reduce<TC, Tacc>), rg, dim3(256), 0, s, h.M, h.N, h.splits, (const Tacc*)h.part,
+                       h.alpha, h.beta, h.C, h.ldc, h.sC);
+  }
   return hipGetLastError();
 }
 
@@ -316,6 +485,7 @@ __global__ __launch_bounds__(256) void k_syev(const EigJob* jobs) {
   int* pp = reinterpret_cast<int*>(cs + Kp);      // Kp/2 pairs: p, q
   double* red = reinterpret_cast<double*>(pp + Kp);  // 256 reduction slots
   __shared__ int done;
+  __shared__ double thr;
   double* V = J.v;
   for (int e = tid; e < Kp * Kp; e += 256) {
     int i = e % Kp, j = e / Kp;
@@ -345,7 +515,12 @@ __global__ __launch_bounds__(256) void k_syev(const EigJob* jobs) {
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) { if (tid < w) red[tid] += red[tid + w]; __syncthreads(); }
     double tots = red[0];
-    if (tid == 0) done = (offs <= 1e-30 * tots || tots == 0.0) ? 1 : 0;
+    // stop once the off-diagonal part is below 1e-14 ||A||_F (the FP64 rounding floor of the
+    // rotations is about K * 1e-16 ||A||_F); rotations smaller than 1e-16 ||A||_F are skipped
+    if (tid == 0) {
+      done = (offs <= 1e-28 * tots || tots == 0.0) ? 1 : 0;
+      thr = 1e-16 * sqrt(tots);
+    }
     __syncthreads();
     if (done) break;
     for (int st = 0; st < Kp - 1; ++st) {
@@ -354,7 +529,7 @@ __global__ __launch_bounds__(256) void k_syev(const EigJob* jobs) {
         if (p > q) { int t = p; p = q; q = t; }
         double apq = A[p + Kp * q], app = A[p + Kp * p], aqq = A[q + Kp * q];
         double c = 1.0, s = 0.0;
-        if (q < K && fabs(apq) > 1e-300 && fabs(apq) > 1e-18 * sqrt(fabs(app * aqq))) {
+        if (q < K && fabs(apq) > thr && fabs(apq) > 1e-300) {
           double tau = (aqq - app) / (2.0 * apq);
           double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
           c = 1.0 / sqrt(1.0 + t * t);
@@ -423,11 +598,131 @@ __global__ __launch_bounds__(256) void k_syev(const EigJob* jobs) {
   for (int i = tid; i < K; i += 256) J.w[rk[i]] = diag[i];
 }
 
+// Small matrices (K <= 96): A and V both resident in LDS (FP64), 512 threads, and every step
+// updates 2x2 blocks B_ij <- J_i^T B_ij J_j of the pair partition, so one barrier separates
+// the rotation parameters from the update and no element is touched by two threads.
+constexpr int EIG_SMALL = 96;
+constexpr int EIG_NT = 512;
+
+__global__ __launch_bounds__(EIG_NT) void k_syev_small(const EigJob* jobs) {
+  extern __shared__ double sm[];
+  const EigJob J = jobs[blockIdx.x];
+  const int K = J.K;
+  const int tid = threadIdx.x;
+  if (K <= 0) return;
+  const int Kp = (K + 1) & ~1;
+  const int np = Kp / 2;
+  double* A = sm;                    // Kp x Kp
+  double* V = A + Kp * Kp;           // Kp x Kp (rows = original basis)
+  double* cs = V + Kp * Kp;          // np pairs (c, s)
+  int* pp = reinterpret_cast<int*>(cs + 2 * np);  // np pairs (p, q)
+  double* red = reinterpret_cast<double*>(pp + 2 * np);
+  __shared__ int done;
+  __shared__ double thr;
+  for (int e = tid; e < Kp * Kp; e += EIG_NT) {
+    int i = e % Kp, j = e / Kp;
+    A[e] = (i < K && j < K) ? J.a[i + (long)K * j] : 0.0;
+    V[e] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int e = tid; e < Kp * Kp; e += EIG_NT) {
+      int i = e % Kp, j = e / Kp;
+      double v = A[e] * A[e];
+      tot += v;
+      if (i != j) off += v;
+    }
+    red[tid] = off;
+    red[tid + EIG_NT] = tot;
+    __syncthreads();
+    for (int w = EIG_NT / 2; w > 0; w >>= 1) {
+      if (tid < w) { red[tid] += red[tid + w]; red[tid + EIG_NT] += red[tid + EIG_NT + w]; }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      done = (red[0] <= 1e-28 * red[EIG_NT] || red[EIG_NT] == 0.0) ? 1 : 0;
+      thr = 1e-16 * sqrt(red[EIG_NT]);
+    }
+    __syncthreads();
+    if (done) break;
+    for (int st = 0; st < Kp - 1; ++st) {
+      for (int pr = tid; pr < np; pr += EIG_NT) {
+        int p = rr_index(pr, st, Kp), q = rr_index(Kp - 1 - pr, st, Kp);
+        if (p > q) { int t = p; p = q; q = t; }
+        double apq = A[p + Kp * q], app = A[p + Kp * p], aqq = A[q + Kp * q];
+        double c = 1.0, s = 0.0;
+        if (q < K && fabs(apq) > thr && fabs(apq) > 1e-300) {
+          double tau = (aqq - app) / (2.0 * apq);
+          double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + t * t);
+          s = t * c;
+        }
+        cs[2 * pr] = c; cs[2 * pr + 1] = s;
+        pp[2 * pr] = p; pp[2 * pr + 1] = q;
+      }
+      __syncthreads();
+      // blocks (i, j) of the pair partition: rows {p_i, q_i} x columns {p_j, q_j}
+      for (int e = tid; e < np * np; e += EIG_NT) {
+        int bi = e % np, bj = e / np;
+        double ci = cs[2 * bi], si = cs[2 * bi + 1], cj = cs[2 * bj], sj = cs[2 * bj + 1];
+        if (si == 0.0 && sj == 0.0) continue;
+        int pi = pp[2 * bi], qi = pp[2 * bi + 1], pj = pp[2 * bj], qj = pp[2 * bj + 1];
+        double a11 = A[pi + Kp * pj], a12 = A[pi + Kp * qj], a21 = A[qi + Kp * pj], a22 = A[qi + Kp * qj];
+        // left: rows p = c row_p - s row_q, q = s row_p + c row_q
+        double b11 = ci * a11 - si * a21, b12 = ci * a12 - si * a22;
+        double b21 = si * a11 + ci * a21, b22 = si * a12 + ci * a22;
+        // right: cols p = c col_p - s col_q, q = s col_p + c col_q
+        A[pi + Kp * pj] = cj * b11 - sj * b12;
+        A[pi + Kp * qj] = sj * b11 + cj * b12;
+        A[qi + Kp * pj] = cj * b21 - sj * b22;
+        A[qi + Kp * qj] = sj * b21 + cj * b22;
+      }
+      // V <- V G (columns p, q of every row)
+      for (int e = tid; e < np * Kp; e += EIG_NT) {
+        int pr = e / Kp, i = e - pr * Kp;
+        double c = cs[2 * pr], s = cs[2 * pr + 1];
+        if (s == 0.0) continue;
+        int p = pp[2 * pr], q = pp[2 * pr + 1];
+        double vp = V[i + Kp * p], vq = V[i + Kp * q];
+        V[i + Kp * p] = c * vp - s * vq;
+        V[i + Kp * q] = s * vp + c * vq;
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  double* diag = cs;
+  for (int i = tid; i < K; i += EIG_NT) diag[i] = A[i + Kp * i];
+  __syncthreads();
+  int* rk = pp;
+  for (int i = tid; i < K; i += EIG_NT) {
+    double di = diag[i];
+    int r = 0;
+    for (int j = 0; j < K; ++j) {
+      double dj = diag[j];
+      if (dj > di || (dj == di && j < i)) ++r;
+    }
+    rk[i] = r;
+  }
+  __syncthreads();
+  for (int e = tid; e < K * K; e += EIG_NT) {
+    int i = e % K, j = e / K;
+    J.v[i + (long)K * rk[j]] = V[i + Kp * j];
+  }
+  for (int i = tid; i < K; i += EIG_NT) J.w[rk[i]] = diag[i];
+}
+
 hipError_t syev_batched(const EigJob* jobs_dev, int count, int Kmax, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   if (Kmax > EIG_MAX) return hipErrorInvalidValue;
   int Kp = (Kmax + 1) & ~1;
-  if (Kmax <= EIG_LDS_MAX) {
+  if (Kmax <= EIG_SMALL) {
+    size_t shm = (size_t)Kp * Kp * 16 + (size_t)Kp * 8 + (size_t)Kp * 4 + 2 * EIG_NT * 8 + 64;
+    hipError_t e = hipFuncSetAttribute((const void*)k_syev_small, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_syev_small, dim3(count), dim3(EIG_NT), shm, s, jobs_dev);
+  } else if (Kmax <= EIG_LDS_MAX) {
     size_t shm = (size_t)Kp * Kp * 8 + (size_t)Kp * 8 + (size_t)Kp * 4 * 2 + 256 * 8 + 64;
     if (shm > 65536) {
       hipError_t e = hipFuncSetAttribute((const void*)k_syev<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);

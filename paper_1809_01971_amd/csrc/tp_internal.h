@@ -26,10 +26,16 @@ struct GemmArgs {
   const TA* A = nullptr; int lda = 0; long sA = 0; int divA = 1; bool tA = false; bool fsA = false; FaceSplit<TA> FA;
   const TB* B = nullptr; int ldb = 0; long sB = 0; int divB = 1; bool tB = false; bool fsB = false; FaceSplit<TB> FB;
   TC* C = nullptr; int ldc = 0; long sC = 0;
+  // split-K: `splits` workgroups share each output tile over K; partial sums go to `part`
+  // (batch * splits * M * N elements) and a second kernel reduces them.
+  int splits = 1; int kchunk = 0; Tacc* part = nullptr;
 };
 
 template <typename TA, typename TB, typename TC, typename Tacc>
 hipError_t gemm(const GemmArgs<TA, TB, TC, Tacc>& g, hipStream_t s);
+// Matrix-core (MFMA) tiles on (default) or the FMA tiles.
+bool gemm_use_mfma();
+void gemm_set_mfma(int on);
 
 // Orthonormal DST-I on `cols` columns of length n = N-1 (N a power of two).
 // tab holds cos(pi m/N), sin(pi m/N), m = 0..N-1, interleaved.

@@ -16,3 +16,24 @@ def tucker_to_full(core, factors):
 
 def log(*args):
     print(*args, flush=True)
+
+
+def _err_part(args):
+    from oracle import exact
+    (w, F, alpha, cn, cp, core, T, slabs) = args
+    return exact.tucker_error_slabs(w, F, alpha, cn, cp, core, T, slabs)
+
+
+def global_rel_error(p, core, tfactors, workers=None):
+    """Exact ||X - u|| / ||u|| over the whole grid (Parseval, slab-parallel over host cores)."""
+    import os
+    from concurrent.futures import ProcessPoolExecutor
+    workers = workers or min(12, os.cpu_count() or 1)
+    chunks = [list(range(i, p.n, workers)) for i in range(workers)]
+    args = [(p.weights, p.factors, p.alpha, p.c_neg, p.c_pos, core, tfactors, c) for c in chunks]
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    with ProcessPoolExecutor(workers) as ex:
+        parts = list(ex.map(_err_part, args))
+    e2 = sum(a for a, _ in parts)
+    u2 = sum(b for _, b in parts)
+    return float(np.sqrt(e2 / u2))

@@ -152,6 +152,32 @@ def test_inner_products(ctx, prec):
     assert abs(ctx.inner(A, B) - ref) <= (1e-13 if prec == 0 else 1e-6) * scale
 
 
+@pytest.mark.parametrize("mfma", [1, 0])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_inner_products_both_gemm_modes(ctx, mfma, prec):
+    """The matrix-core and the FMA contraction tiles give the same Gram inner products."""
+    import paper_1809_01971_amd as tp
+    log("inner gemm mode mfma=%d prec=%d" % (mfma, prec))
+    ctx.gemm_mode(bool(mfma))
+    try:
+        n, d = 255, 3
+        rng = np.random.default_rng(12)
+        Fa = [rng.standard_normal((n, 40)) for _ in range(d)]
+        Fb = [rng.standard_normal((n, 33)) for _ in range(d)]
+        wa, wb = rng.standard_normal(40), rng.standard_normal(33)
+        A, B = tp.Tensor(d, n, 64, prec), tp.Tensor(d, n, 64, prec)
+        ctx.from_cp(wa, Fa, A)
+        ctx.from_cp(wb, Fb, B)
+        G = np.ones((40, 33))
+        for a_, b_ in zip(Fa, Fb):
+            G = G * (a_.T @ b_)
+        ref = wa @ G @ wb
+        scale = np.sqrt((wa @ (np.prod([f.T @ f for f in Fa], axis=0)) @ wa) * (wb @ (np.prod([f.T @ f for f in Fb], axis=0)) @ wb))
+        assert abs(ctx.inner(A, B) - ref) <= (1e-12 if prec == 0 else 1e-5) * scale
+    finally:
+        ctx.gemm_mode(True)
+
+
 @pytest.mark.parametrize("eps", [1e-2, 1e-5, 1e-7])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_truncate_sum_hosvd_bound(ctx, eps, prec):
@@ -213,3 +239,35 @@ def test_apply_matches_spectral_product(ctx, d, n, alpha, prec):
     refp = exact.solve_full(f, alpha, cn, cp)
     errp = rel(ctx.eval_grid(Y, [np.arange(n)] * d), refp)
     assert errp <= ep + 3 * tol + (0 if prec == 0 else 1e-5)
+
+
+@pytest.mark.parametrize("d,n", [(3, 31), (2, 63)])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_apply_sum_and_structured_inner(ctx, d, n, prec):
+    """R - a F(s (.) F P) truncated as one sum, and <P, F(s (.) F P)> without truncation."""
+    import paper_1809_01971_amd as tp
+    from paper_1809_01971_amd._tp import sketch_tensors
+    log("apply_sum d=%d n=%d prec=%d" % (d, n, prec))
+    alpha, cn, cp = 0.5, 1.0, 1e-2
+    op, pre, (eo, ep) = ctx.symbol_build(d, n, alpha, cn, cp, prec=prec, op_terms=32, pre_terms=12)
+    rng = np.random.default_rng(3 * n + d)
+    F1 = [rng.standard_normal((n, 3)) for _ in range(d)]
+    F2 = [rng.standard_normal((n, 2)) for _ in range(d)]
+    w1, w2 = np.ones(3), np.ones(2)
+    R, P, Y = tp.Tensor(d, n, 64, prec), tp.Tensor(d, n, 64, prec), tp.Tensor(d, n, 64, prec)
+    ctx.from_cp(w1, F1, R)
+    ctx.from_cp(w2, F2, P)
+    sk = sketch_tensors(workloads.sketch_matrices(n, d, n))
+    tol = 1e-7 if prec == 0 else 1e-5
+    a = 0.37
+    ctx.apply_sum([None, op], [R, P], [1.0, -a], Y, tol, 64, sk, allow_erank=True)
+    r_full, p_full = tensor.cp_full(w1, F1), tensor.cp_full(w2, F2)
+    ap = exact.apply_full(p_full, alpha, cn, cp)
+    ref = r_full - a * ap
+    got = ctx.eval_grid(Y, [np.arange(n)] * d)
+    err = rel(got, ref)
+    log("  err %.2e" % err)
+    assert err <= (a * np.linalg.norm(ap) / np.linalg.norm(ref)) * eo + 3 * tol + (0 if prec == 0 else 1e-5)
+    ps = ctx.inner_sym(P, op, P)
+    ps_ref = tensor.inner(p_full, ap)
+    assert abs(ps - ps_ref) <= (eo + (1e-12 if prec == 0 else 2e-6)) * abs(ps_ref)

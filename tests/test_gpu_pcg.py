@@ -4,7 +4,7 @@ import pytest
 
 import workloads
 from oracle import exact, spectral, tensor
-from tests.gpu_helpers import log, rel
+from tests.gpu_helpers import global_rel_error, log, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -20,8 +20,9 @@ def ctx():
     c.close()
 
 
-def solve(ctx, p, prec, eps, tau, cap=64, q=None, op_terms=32, pre_terms=12):
-    """The sketch width is the cap plus an oversampling of 16 columns."""
+def solve(ctx, p, prec, eps, tau, cap=64, q=None, op_terms=32, pre_terms=28):
+    """The sketch width is the cap plus an oversampling of 16 columns.  tau is compared with the
+    error estimate ||Z||/||X||, whose floor is about 2-3 times the truncation tolerance eps."""
     import paper_1809_01971_amd as tp
     from paper_1809_01971_amd._tp import sketch_tensors
     op, pre, errs = ctx.symbol_build(p.d, p.n, p.alpha, p.c_neg, p.c_pos, prec=prec, op_terms=op_terms,
@@ -38,7 +39,7 @@ def solve(ctx, p, prec, eps, tau, cap=64, q=None, op_terms=32, pre_terms=12):
 def test_cfg1_2d_fp64_against_full_grid_and_brute_force(ctx):
     p = workloads.cfg1()
     log("cfg1 fp64")
-    X, st, info = solve(ctx, p, 0, eps=1e-9, tau=1e-10, op_terms=40)
+    X, st, info = solve(ctx, p, 0, eps=1e-8, tau=4e-8, op_terms=40, pre_terms=36)
     f = tensor.cp_full(p.weights, p.factors)
     u = exact.solve_full(f, p.alpha, p.c_neg, p.c_pos)
     got = ctx.eval_grid(X, [np.arange(p.n)] * 2)
@@ -51,7 +52,7 @@ def test_cfg1_2d_fp64_against_full_grid_and_brute_force(ctx):
 def test_cfg1_2d_mixed(ctx):
     p = workloads.cfg1()
     log("cfg1 mixed")
-    X, st, info = solve(ctx, p, 1, eps=1e-6, tau=1e-6)
+    X, st, info = solve(ctx, p, 1, eps=1e-6, tau=4e-6)
     u = exact.solve_full(tensor.cp_full(p.weights, p.factors), p.alpha, p.c_neg, p.c_pos)
     err = rel(ctx.eval_grid(X, [np.arange(p.n)] * 2), u)
     log("  cfg1 mixed err %.2e info %s" % (err, info))
@@ -64,7 +65,7 @@ def test_single_sine_mode_closed_form(ctx, n, ks, prec):
     d = len(ks)
     p = workloads.sine_mode_problem(n, d, ks, 0.5, 1.0, 1e-2)
     log("sine mode n=%d ks=%s prec=%d" % (n, ks, prec))
-    X, st, info = solve(ctx, p, prec, eps=1e-8 if prec == 0 else 1e-6, tau=1e-9 if prec == 0 else 1e-6, cap=8, q=16)
+    X, st, info = solve(ctx, p, prec, eps=1e-8 if prec == 0 else 1e-6, tau=4e-8 if prec == 0 else 4e-6, cap=8, q=16)
     fac = exact.single_mode_factor((n,) * d, ks, 0.5, 1.0, 1e-2)
     rows = [np.arange(0, n, max(1, n // 64))] * d
     got = ctx.eval_grid(X, rows)
@@ -78,7 +79,7 @@ def test_single_sine_mode_closed_form(ctx, n, ks, prec):
 def test_cfg2_type_n63_fp64(ctx, alpha, gamma):
     p = workloads.cfg2(alpha=alpha, gamma=gamma, n=63)
     log("cfg2-type n=63 alpha=%g gamma=%g" % (alpha, gamma))
-    X, st, info = solve(ctx, p, 0, eps=1e-8, tau=1e-9)
+    X, st, info = solve(ctx, p, 0, eps=1e-7, tau=4e-7, pre_terms=36)
     u = exact.solve_full(tensor.cp_full(p.weights, p.factors), p.alpha, p.c_neg, p.c_pos)
     err = rel(ctx.eval_grid(X, [np.arange(p.n)] * 3), u)
     log("  err %.2e info %s" % (err, info))
@@ -90,7 +91,7 @@ def test_cfg2_n255_fp64(ctx, alpha, gamma):
     p = workloads.cfg2(alpha=alpha, gamma=gamma)
     log("cfg2 n=255 alpha=%g gamma=%g" % (alpha, gamma))
     assert p.n == 255
-    X, st, info = solve(ctx, p, 0, eps=2e-7, tau=2e-7, cap=96)
+    X, st, info = solve(ctx, p, 0, eps=2e-7, tau=8e-7, cap=96, op_terms=36, pre_terms=36)
     u = exact.solve_full(tensor.cp_full(p.weights, p.factors), p.alpha, p.c_neg, p.c_pos)
     err = rel(ctx.eval_grid(X, [np.arange(p.n)] * 3), u)
     log("  err %.2e info %s" % (err, info))
@@ -101,8 +102,27 @@ def test_cfg2_n255_fp64(ctx, alpha, gamma):
 def test_cfg2_n255_mixed(ctx, alpha, gamma):
     p = workloads.cfg2(alpha=alpha, gamma=gamma)
     log("cfg2 mixed n=255 alpha=%g gamma=%g" % (alpha, gamma))
-    X, st, info = solve(ctx, p, 1, eps=2e-5, tau=2e-5, cap=64)
+    X, st, info = solve(ctx, p, 1, eps=2e-5, tau=8e-5, cap=64, op_terms=28, pre_terms=28)
     u = exact.solve_full(tensor.cp_full(p.weights, p.factors), p.alpha, p.c_neg, p.c_pos)
     err = rel(ctx.eval_grid(X, [np.arange(p.n)] * 3), u)
     log("  err %.2e info %s" % (err, info))
     assert err < MIXED_TOL
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_cfg3_n2047_global_error(ctx, prec):
+    """The benchmark workload at full size: exact relative error over all 2047^3 points by
+    Parseval (oracle.exact.tucker_error_slabs over every spectral slab)."""
+    p = workloads.cfg3()
+    log("cfg3 n=2047 prec=%d" % prec)
+    if prec == 1:
+        X, st, info = solve(ctx, p, 1, eps=3e-5, tau=1.2e-4, cap=48, q=64, op_terms=28, pre_terms=28)
+        tol = MIXED_TOL
+    else:
+        X, st, info = solve(ctx, p, 0, eps=1.5e-7, tau=6e-7, cap=96, q=112, op_terms=36, pre_terms=36)
+        tol = FP64_TOL
+    core, fs = X.numpy_parts()
+    err = global_rel_error(p, core, fs)
+    log("  global err %.2e info %s" % (err, info))
+    assert info["iters"] <= 5
+    assert err < tol

@@ -254,3 +254,18 @@ def test_lowrank_pcg_step_model_converges_to_exact_solution():
     X1, it1, _ = lowrank_pcg.pcg(s, 1.0 / s, f, eps=1e-12, tau=1e-9)
     assert it1 == 1
     assert np.linalg.norm(X1 - u) <= 1e-10 * np.linalg.norm(u)
+
+
+def test_tucker_error_by_parseval_matches_full_grid():
+    """The slab-wise spectral error equals the full-grid relative error of a Tucker tensor."""
+    p = workloads.cfg3(n=31)
+    f = tensor.cp_full(p.weights, p.factors)
+    u = exact.solve_full(f, p.alpha, p.c_neg, p.c_pos)
+    core, U, _ = tensor.hosvd_truncate(u, 1e-3)
+    X = tensor.tucker_full(core, U)
+    e2, u2 = exact.tucker_error_slabs(p.weights, p.factors, p.alpha, p.c_neg, p.c_pos, core, U, range(31))
+    assert np.sqrt(e2 / u2) == pytest.approx(np.linalg.norm(X - u) / np.linalg.norm(u), rel=1e-9)
+    assert u2 == pytest.approx(np.sum(u * u), rel=1e-12)
+    a, b = exact.tucker_error_slabs(p.weights, p.factors, p.alpha, p.c_neg, p.c_pos, core, U, range(0, 31, 2))
+    c2, d2 = exact.tucker_error_slabs(p.weights, p.factors, p.alpha, p.c_neg, p.c_pos, core, U, range(1, 31, 2))
+    assert a + c2 == pytest.approx(e2, rel=1e-12)
