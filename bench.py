@@ -97,6 +97,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fp64-steps", type=int, default=None)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first copy 256 MiB on the device (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs a single control problem per GPU and has no "
@@ -108,6 +110,12 @@ def main():
     from paper_1809_01971_amd._tp import sketch_tensors
 
     p = workloads.cfg3()
+    if args.calib_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ctx = tp.Context(0, workspace_bytes=24 << 30)
     qs = sorted({s["q"] for s in SETTINGS.values()})
     sk_by_q = {q: sketch_tensors(workloads.sketch_matrices(p.n, 3, q)) for q in qs}
@@ -115,9 +123,13 @@ def main():
     log("bench: mixed warmup=%d steps=%d" % (args.warmup, args.steps))
     Xm, dtm, infm, prof = run_solver(ctx, p, sk_by_q, SETTINGS["mixed"], args.steps, args.warmup, True)
     fsteps = args.fp64_steps if args.fp64_steps is not None else max(1, args.steps // 2)
-    log("bench: fp64 steps=%d" % fsteps)
-    Xd, dtd, infd, _ = run_solver(ctx, p, sk_by_q, SETTINGS["fp64"], fsteps, 1, False)
-    parts_m, parts_d = Xm.numpy_parts(), Xd.numpy_parts()
+    if fsteps > 0:
+        log("bench: fp64 steps=%d" % fsteps)
+        Xd, dtd, infd, _ = run_solver(ctx, p, sk_by_q, SETTINGS["fp64"], fsteps, 1, False)
+        parts_d = Xd.numpy_parts()
+    else:
+        dtd, infd, parts_d = None, [{"iters": None, "rank": None}], None
+    parts_m = Xm.numpy_parts()
 
     value = args.steps / dtm
     ms = 1000.0 * dtm / args.steps
@@ -154,7 +166,7 @@ def main():
         log("bench: oracle over %d of %d spectral slabs, %d workers" % (len(sample), p.n, workers))
         with threadpoolctl.threadpool_limits(1):
             t0 = time.perf_counter()
-            errs = oracle_errors(p, [parts_m, parts_d], sample, workers)
+            errs = oracle_errors(p, [parts_m] + ([parts_d] if parts_d else []), sample, workers) + [None]
             tc = time.perf_counter() - t0
         full_s = tc * p.n / len(sample)
         cpu = {"value": 1.0 / full_s, "unit": "solves/s", "cores": workers, "kind": "oracle",
@@ -169,8 +181,8 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "cfg3: 3D n=2047, alpha=1/2, beta=1, gamma=1e-2, rank-8 rhs z/(1+k)",
                    "mixed": SETTINGS["mixed"], "fp64": SETTINGS["fp64"]},
-        "fp64_solves_per_s": fsteps / dtd,
-        "speedup_mixed_over_fp64": value / (fsteps / dtd),
+        "fp64_solves_per_s": fsteps / dtd if dtd else None,
+        "speedup_mixed_over_fp64": value / (fsteps / dtd) if dtd else None,
         "rel_err_mixed_vs_oracle": errs[0],
         "rel_err_fp64_vs_oracle": errs[1],
         "rel_err_note": "||X-u||/||u|| by Parseval over every %dth spectral slab of the 2047^3 grid" % ERR_SLAB_STRIDE,

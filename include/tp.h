@@ -143,6 +143,13 @@ typedef struct {
 tp_status tp_symbol_build(tp_ctx* ctx, const tp_symbol_desc* desc, tp_symbol** op,
                           tp_symbol** pre, double* err);
 tp_status tp_symbol_free(tp_symbol* sym);
+
+/* State operator of eqn:State / eqn:L_alp_state, y = beta A^-alpha u: the exponential sum
+ * beta rho^-alpha ~ sum_k w_k exp(-tau_k rho) (canonical rank op_terms, least-squares fit; beta is
+ * desc->c_neg, desc->c_pos is ignored), for use with tp_apply.  err (host, may be NULL) receives
+ * its measured max relative error. */
+tp_status tp_state_symbol_build(tp_ctx* ctx, const tp_symbol_desc* desc, tp_symbol** state,
+                                double* err);
 /* rank (host): canonical rank of the symbol; err (host): its measured error. */
 tp_status tp_symbol_info(const tp_symbol* sym, int32_t* rank, double* err);
 /* Values of the symbol at `count` multi-indices idx (device, count x d int32,
@@ -230,6 +237,18 @@ typedef struct {
 tp_status tp_pcg_solve(tp_ctx* ctx, const tp_symbol* op, const tp_symbol* pre,
                        const tp_cp* b, tp_tensor* x, const tp_pcg_opts* opts,
                        const tp_sketch* sketch, tp_pcg_info* info);
+
+/* Many independent control problems (arrays of `count` entries, all host arrays of structs
+ * whose tensor/sketch pointers are device memory): problem i builds its symbols from descs[i]
+ * and solves into xs[i] with opts[i] and sks[i]; infos[i] receives its result.  The problems
+ * are spread over `streams` (1..16) concurrent HIP streams at default priority, each with its
+ * own workspace of workspace_per_stream bytes (0 = 2 GiB), allocated for the call and freed at
+ * its end.  Returns the first hard error (TP_ERANK / TP_ENOCONV of a problem are reported only
+ * in its info). */
+tp_status tp_pcg_solve_batched(tp_ctx* ctx, int32_t count, const tp_symbol_desc* descs,
+                               const tp_cp* bs, tp_tensor* xs, const tp_pcg_opts* opts,
+                               const tp_sketch* sks, tp_pcg_info* infos, int32_t streams,
+                               size_t workspace_per_stream);
 
 /* ---------------------------------------------------------------------------
  * Kernel-level entry points (for parity tests of single steps)

@@ -132,3 +132,16 @@ def tucker_error_slabs(weights, factors, alpha, c_neg, c_pos, core, tfactors, sl
         err2 += float(np.sum((xh - uh) ** 2))
         u2 += float(np.sum(uh * uh))
     return err2, u2
+
+
+def state_full(u, alpha, beta):
+    """State y = beta A^-alpha u (eqn:State, eqn:L_alp_state) on the full grid."""
+    u = np.asarray(u, dtype=np.float64)
+    uh = sfft.dstn(u, type=1, norm="ortho")
+    rho = spectral.rho_grid(u.shape)
+    return sfft.idstn(beta * rho ** (-alpha) * uh, type=1, norm="ortho")
+
+
+def cost_functional(y, u, y_omega, gamma):
+    """J(y,u) = 1/2 ||y - y_Omega||^2 + gamma/2 ||u||^2 (discrete cost of Sec. 3.1, M = I)."""
+    return 0.5 * float(np.sum((y - y_omega) ** 2)) + 0.5 * gamma * float(np.sum(u * u))

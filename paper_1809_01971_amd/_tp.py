@@ -62,6 +62,7 @@ _SIGS = {
     "tp_destroy": ([P], C.c_int),
     "tp_symbol_build": ([P, C.POINTER(tp_symbol_desc), C.POINTER(P), C.POINTER(P), C.POINTER(C.c_double)], C.c_int),
     "tp_symbol_free": ([P], C.c_int),
+    "tp_state_symbol_build": ([P, C.POINTER(tp_symbol_desc), C.POINTER(P), C.POINTER(C.c_double)], C.c_int),
     "tp_symbol_info": ([P, C.POINTER(C.c_int32), C.POINTER(C.c_double)], C.c_int),
     "tp_symbol_eval": ([P, P, C.c_int32, P, P], C.c_int),
     "tp_from_cp": ([P, C.POINTER(tp_cp), C.POINTER(tp_tensor), C.c_double], C.c_int),
@@ -77,6 +78,9 @@ _SIGS = {
     "tp_pcg_solve": ([P, P, P, C.POINTER(tp_cp), C.POINTER(tp_tensor), C.POINTER(tp_pcg_opts),
                       C.POINTER(tp_sketch), C.POINTER(tp_pcg_info)], C.c_int),
     "tp_dst": ([P, C.c_int32, C.c_int32, C.c_int32, P, P], C.c_int),
+    "tp_pcg_solve_batched": ([P, C.c_int32, C.POINTER(tp_symbol_desc), C.POINTER(tp_cp), C.POINTER(tp_tensor),
+                              C.POINTER(tp_pcg_opts), C.POINTER(tp_sketch), C.POINTER(tp_pcg_info), C.c_int32,
+                              C.c_size_t], C.c_int),
     "tp_syev": ([P, C.c_int32, C.c_int32, P, P, P], C.c_int),
     "tp_lambda": ([P, C.c_int32, P], C.c_int),
     "tp_profile": ([P, C.c_int32], C.c_int),
@@ -209,6 +213,18 @@ class Context:
         _check(self.lib.tp_symbol_build(self.h, C.byref(desc), C.byref(op), C.byref(pre), err))
         return Symbol(self, op, d, prec), Symbol(self, pre, d, prec), (err[0], err[1])
 
+    def state_symbol_build(self, d, n, alpha, beta, prec=TP_FP64, terms=0):
+        desc = tp_symbol_desc()
+        desc.d = d
+        for m in range(3):
+            desc.n[m] = n if m < d else 0
+        desc.alpha, desc.c_neg, desc.c_pos = alpha, beta, 0.0
+        desc.op_terms, desc.prec = terms, prec
+        h = P()
+        err = C.c_double()
+        _check(self.lib.tp_state_symbol_build(self.h, C.byref(desc), C.byref(h), C.byref(err)))
+        return Symbol(self, h, d, prec), err.value
+
     # ---- tensors
     def from_cp(self, weights, factors, out, tol=0.0, allow_erank=False):
         keep, cp = cp_struct(weights, factors)
@@ -277,6 +293,51 @@ class Context:
         return st, {"iters": info.iters, "status": info.status, "rank": list(info.rank)[:x.d],
                     "rel_res": info.rel_res, "true_rel_res": info.true_rel_res,
                     "applies": info.op_applies, "err_est": info.err_est}
+
+
+def _desc(d, n, alpha, c_neg, c_pos, prec, op_terms, pre_terms):
+    desc = tp_symbol_desc()
+    desc.d = d
+    for m in range(3):
+        desc.n[m] = n if m < d else 0
+    desc.alpha, desc.c_neg, desc.c_pos = alpha, c_neg, c_pos
+    desc.method, desc.op_terms, desc.pre_terms = TP_SYM_FIT, op_terms, pre_terms
+    desc.prec = prec
+    return desc
+
+
+def batch_solve(ctx, problems, settings, sketches, streams=8, workspace_per_stream=0):
+    """Solve independent problems concurrently (tp_pcg_solve_batched).  settings(p) -> dict with
+    prec, eps, tau, cap, op_terms, pre_terms; sketches[n] -> device sketch tensors for grid n."""
+    cnt = len(problems)
+    descs = (tp_symbol_desc * cnt)()
+    cps = (tp_cp * cnt)()
+    tens = (tp_tensor * cnt)()
+    opts = (tp_pcg_opts * cnt)()
+    sks = (tp_sketch * cnt)()
+    infos = (tp_pcg_info * cnt)()
+    keep, outs = [], []
+    for i, p in enumerate(problems):
+        s = settings(p)
+        descs[i] = _desc(p.d, p.n, p.alpha, p.c_neg, p.c_pos, s["prec"], s["op_terms"], s["pre_terms"])
+        k, cp = cp_struct(p.weights, p.factors)
+        keep.append(k)
+        cps[i] = cp
+        X = Tensor(p.d, p.n, s["cap"], s["prec"])
+        outs.append(X)
+        tens[i] = X.s
+        opts[i] = tp_pcg_opts(s["tau"], 100, s["eps"], s["cap"], 0)
+        sk, k2 = sketch_struct(sketches[p.n])
+        sks[i] = sk
+    _check(ctx.lib.tp_pcg_solve_batched(ctx.h, cnt, descs, cps, tens, opts, sks, infos, streams,
+                                         workspace_per_stream))
+    res = []
+    for i, X in enumerate(outs):
+        X.s = tens[i]
+        X._sync_ranks()
+        res.append({"iters": infos[i].iters, "status": infos[i].status, "rank": list(infos[i].rank)[:X.d],
+                    "err_est": infos[i].err_est})
+    return outs, res
 
 
 class Symbol:

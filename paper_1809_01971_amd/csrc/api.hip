@@ -11,7 +11,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
 #include <map>
+#include <thread>
 #include <string>
 #include <vector>
 
@@ -1329,6 +1331,64 @@ tp_status tp_symbol_build(tp_ctx* c, const tp_symbol_desc* desc, tp_symbol** op,
   return TP_OK;
 }
 
+tp_status tp_state_symbol_build(tp_ctx* c, const tp_symbol_desc* desc, tp_symbol** out, double* err) {
+  if (!c || !desc || !out) return fail(TP_EINVAL, "NULL argument");
+  *out = nullptr;
+  const tp_symbol_desc& D = *desc;
+  if (D.d != 2 && D.d != 3) return fail(TP_EINVAL, "d=%d must be 2 or 3", D.d);
+  if (!(D.alpha > 0.0 && D.alpha <= 1.0)) return fail(TP_EINVAL, "alpha=%g must be in (0,1]", D.alpha);
+  if (!(D.c_neg > 0.0)) return fail(TP_EINVAL, "c_neg (beta) must be > 0");
+  if (D.prec != TP_FP64 && D.prec != TP_MIXED) return fail(TP_EINVAL, "unknown precision %d", D.prec);
+  for (int m = 0; m < D.d; ++m) TPCHK(check_grid(D.n[m], D.prec));
+  int K = D.op_terms > 0 ? D.op_terms : 28;
+  if (K < 2 || K > 64) return fail(TP_EINVAL, "op_terms=%d must be in [2,64]", K);
+  tp_symbol* s = new tp_symbol();
+  auto cleanup = [&](tp_status st) {
+    for (void* p : s->owned) (void)hipFree(p);
+    delete s;
+    return st;
+  };
+  s->d = D.d;
+  s->prec = D.prec;
+  s->kind = 2;
+  s->K = K;
+  s->R = K;
+  double rmin = 0, rmax = 0;
+  for (int m = 0; m < D.d; ++m) {
+    s->n[m] = D.n[m];
+    double* l = nullptr;
+    if (hipMalloc(&l, sizeof(double) * D.n[m]) != hipSuccess) return cleanup(fail(TP_ENOMEM, "hipMalloc failed"));
+    s->owned.push_back(l);
+    s->lam[m] = l;
+    if (lambda_1d(D.n[m], l, c->stream) != hipSuccess) return cleanup(fail(TP_EHIP, "lambda kernel failed"));
+    double h = 1.0 / (D.n[m] + 1.0);
+    rmin += 4.0 / (h * h) * std::pow(std::sin(M_PI * h / 2), 2);
+    rmax += 4.0 / (h * h) * std::pow(std::sin(M_PI * D.n[m] * h / 2), 2);
+  }
+  const double rho0 = rmin, B = rmax / rmin * 1.0000001;
+  if (hipMalloc(&s->tau, sizeof(double) * K) != hipSuccess || hipMalloc(&s->w, sizeof(double) * K) != hipSuccess)
+    return cleanup(fail(TP_ENOMEM, "hipMalloc failed"));
+  s->owned.push_back(s->tau);
+  s->owned.push_back(s->w);
+  std::vector<FitCand> cands;
+  for (double a : {-1.5, -1.0, -0.5})
+    for (double b : {1.75, 2.25, 2.75}) cands.push_back({a, b});
+  double e = 0;
+  tp_status st = fit_expsum(c, 2, D.alpha, D.c_neg, 0.0, rho0, B, K, cands, s->tau, s->w, &e);
+  if (st != TP_OK) return cleanup(st);
+  if (scale(s->tau, K, 1.0 / rho0, c->stream) != hipSuccess) return cleanup(fail(TP_EHIP, "scale failed"));
+  s->err = e;
+  // kind 2 factors: exp(-tau_k lambda) in every mode (one exponential sum, rank K)
+  s->kind = 1;
+  st = D.prec == TP_FP64 ? build_factors<double>(c, s) : build_factors<float>(c, s);
+  s->kind = 2;
+  if (st != TP_OK) return cleanup(st);
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return cleanup(fail(TP_EHIP, "stream sync failed"));
+  if (err) *err = e;
+  *out = s;
+  return TP_OK;
+}
+
 tp_status tp_symbol_free(tp_symbol* s) {
   if (!s) return TP_OK;
   (void)hipDeviceSynchronize();
@@ -1663,4 +1723,67 @@ extern "C" tp_status tp_pcg_solve(tp_ctx* c, const tp_symbol* op, const tp_symbo
   if (e != hipSuccess) return fail(TP_EHIP, "stream sync: %s", hipGetErrorString(e));
   if (st == TP_OK && info->status == TP_ERANK) return fail(TP_ERANK, "rank cap reached during the solve");
   return st;
+}
+
+// ------------------------------------------------------------------------------ batched solves
+// Independent problems run concurrently on `streams` HIP streams (default priority), each
+// stream owned by a worker thread with its own context and workspace; workers take the next
+// problem from a shared counter, so uneven problems balance themselves.
+extern "C" tp_status tp_pcg_solve_batched(tp_ctx* c, int32_t count, const tp_symbol_desc* descs, const tp_cp* bs,
+                                          tp_tensor* xs, const tp_pcg_opts* opts, const tp_sketch* sks,
+                                          tp_pcg_info* infos, int32_t streams, size_t workspace_per_stream) {
+  if (!c || (count > 0 && (!descs || !bs || !xs || !opts || !sks || !infos))) return fail(TP_EINVAL, "NULL argument");
+  if (count < 0) return fail(TP_EINVAL, "count < 0");
+  if (streams < 1 || streams > 16) return fail(TP_EINVAL, "streams=%d must be in [1,16]", streams);
+  if (count == 0) return TP_OK;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  const int nw = std::min<int>(streams, count);
+  std::vector<tp_ctx*> ctxs(nw, nullptr);
+  std::vector<hipStream_t> strm(nw, nullptr);
+  for (int w = 0; w < nw; ++w) {
+    HIPCHK(hipStreamCreateWithFlags(&strm[w], hipStreamNonBlocking));
+    tp_status st = tp_create(c->device, strm[w], workspace_per_stream ? workspace_per_stream : (size_t(2) << 30), &ctxs[w]);
+    if (st != TP_OK) {
+      for (int v = 0; v <= w; ++v) {
+        if (ctxs[v]) tp_destroy(ctxs[v]);
+        if (strm[v]) (void)hipStreamDestroy(strm[v]);
+      }
+      return st;
+    }
+    ctxs[w]->prof = false;
+  }
+  std::atomic<int> next(0);
+  std::vector<tp_status> wst(nw, TP_OK);
+  std::vector<std::string> werr(nw);
+  auto worker = [&](int w) {
+    (void)hipSetDevice(c->device);
+    tp_ctx* cw = ctxs[w];
+    for (;;) {
+      int i = next.fetch_add(1);
+      if (i >= count) break;
+      tp_symbol *op = nullptr, *pre = nullptr;
+      double errs[2];
+      tp_status st = tp_symbol_build(cw, &descs[i], &op, &pre, errs);
+      if (st == TP_OK) st = tp_pcg_solve(cw, op, pre, &bs[i], &xs[i], &opts[i], &sks[i], &infos[i]);
+      else infos[i].status = st;
+      if (op) tp_symbol_free(op);
+      if (pre) tp_symbol_free(pre);
+      if (st != TP_OK && st != TP_ERANK && st != TP_ENOCONV && wst[w] == TP_OK) {
+        wst[w] = st;
+        werr[w] = g_err;
+      }
+    }
+  };
+  std::vector<std::thread> th;
+  for (int w = 0; w < nw; ++w) th.emplace_back(worker, w);
+  for (auto& t : th) t.join();
+  tp_status res = TP_OK;
+  std::string msg;
+  for (int w = 0; w < nw; ++w) {
+    if (wst[w] != TP_OK && res == TP_OK) { res = wst[w]; msg = werr[w]; }
+    tp_destroy(ctxs[w]);
+    (void)hipStreamDestroy(strm[w]);
+  }
+  if (res != TP_OK) return fail(res, "batched solve: %s", msg.c_str());
+  return TP_OK;
 }

@@ -141,8 +141,9 @@ __global__ __launch_bounds__(GTHREADS) void k_gemm(GemmArgs<TA, TB, TC, Tacc> g)
 
 // MFMA variant: the same tiling and loaders, and each of the 4 waves owns a 32x32 quarter of
 // the 64x64 tile as 2x2 MFMA 16x16x4 blocks (FP32 or FP64 matrix cores).  Operand layout of the
-// single-block 16x16x4 instructions: lane l supplies A[l%16][l/16] and B[l/16][l%16]; it
-// receives D[4*(l/16)+v][l%16], v = 0..3.
+// single-block 16x16x4 instructions: lane l supplies A[l%16][l/16] and B[l/16][l%16]; result
+// element v of lane l is D[4*(l/16)+v][l%16] for FP32 and D[l/16+4v][l%16] for FP64 (checked
+// on gfx950 with a one-wavefront probe).
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
@@ -233,14 +234,15 @@ __global__ __launch_bounds__(GTHREADS) void k_gemm_mfma(GemmArgs<TA, TB, TC, Tac
     }
     __syncthreads();
   }
-  const int rbase = 4 * (lane >> 4), cl = lane & 15;
+  const bool f64 = std::is_same<Tacc, double>::value;
+  const int rbase = f64 ? (lane >> 4) : 4 * (lane >> 4), rstep = f64 ? 4 : 1, cl = lane & 15;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        int row = m0 + wm + 16 * i + rbase + v;
+        int row = m0 + wm + 16 * i + rbase + rstep * v;
         int col = n0 + wn + 16 * j + cl;
         if (row >= g.M || col >= g.N) continue;
         Tacc x = acc[i][j][v];
@@ -943,10 +945,12 @@ template hipError_t expfactors<float>(const double*, int, const double*, int, fl
 // target function of the fits, in the scaled variable y = rho/rho0:
 //   kind 0: g(y) = c_neg rho^-(1+alpha) + c_pos rho^-(1-alpha), rho = rho0*y
 //   kind 1: p(y) = 1/s(rho) = 1/(c_neg rho^-alpha + c_pos rho^alpha)
+//   kind 2: c_neg rho^-alpha (the state operator beta A^-alpha)
 __device__ double fit_target(int kind, double alpha, double cn, double cp, double rho0, double y) {
   double rho = rho0 * y;
   double ra = pow(rho, alpha);
   if (kind == 0) return (cn / ra + cp * ra) / rho;
+  if (kind == 2) return cn / ra;
   return 1.0 / (cn / ra + cp * ra);
 }
 

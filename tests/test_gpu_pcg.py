@@ -126,3 +126,33 @@ def test_cfg3_n2047_global_error(ctx, prec):
     log("  global err %.2e info %s" % (err, info))
     assert info["iters"] <= 5
     assert err < tol
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_state_recovery_and_cost(ctx, prec):
+    """y = beta A^-alpha u (eqn:State) and J(y,u) = 1/2||y - y_Omega||^2 + gamma/2 ||u||^2 from the
+    GPU control, against the exact state and cost of the exact control."""
+    import paper_1809_01971_amd as tp
+    from paper_1809_01971_amd._tp import sketch_tensors
+    n, beta, gamma, alpha = 63, 2.0, 1e-2, 0.5
+    p = workloads.cfg2(alpha=alpha, gamma=gamma, n=n)
+    p.c_neg, p.c_pos = beta, gamma / beta          # paper form of eqn:forControl
+    log("state/cost prec=%d" % prec)
+    eps = 1e-7 if prec == 0 else 1e-5
+    X, st, info = solve(ctx, p, prec, eps=eps, tau=4 * eps, pre_terms=36 if prec == 0 else 28)
+    state, serr = ctx.state_symbol_build(3, n, alpha, beta, prec=prec, terms=36 if prec == 0 else 28)
+    sk = sketch_tensors(workloads.sketch_matrices(n, 3, 63))
+    Y = tp.Tensor(3, n, 64, prec)
+    ctx.apply(state, X, Y, eps, 64, sk, allow_erank=True)
+    f = tensor.cp_full(p.weights, p.factors)
+    u = exact.solve_full(f, alpha, p.c_neg, p.c_pos)
+    y = exact.state_full(u, alpha, beta)
+    err_y = rel(ctx.eval_grid(Y, [np.arange(n)] * 3), y)
+    B = tp.Tensor(3, n, 64, prec)
+    ctx.from_cp(p.weights, p.factors, B)
+    J = 0.5 * (ctx.inner(Y, Y) - 2 * ctx.inner(Y, B) + ctx.inner(B, B)) + 0.5 * gamma * ctx.inner(X, X)
+    J_ref = exact.cost_functional(y, u, f, gamma)
+    log("  state err %.2e (sym %.1e)  J %.10e ref %.10e" % (err_y, serr, J, J_ref))
+    tol = FP64_TOL if prec == 0 else MIXED_TOL
+    assert err_y < tol
+    assert abs(J - J_ref) <= tol * abs(J_ref)
