@@ -140,7 +140,8 @@ def main():
              "gemm_f32_f64": ("alu", PEAK["fp32_vector_tflops"], "TFLOP/s"),
              "gemm_f64_f32": ("alu", PEAK["fp64_vector_tflops"], "TFLOP/s"),
              "dst_f64": ("hbm", PEAK["hbm_gbs"], "GB/s"), "dst_f32": ("hbm", PEAK["hbm_gbs"], "GB/s"),
-             "syev": ("alu", PEAK["fp64_vector_tflops"], "TFLOP/s")}
+             "syev": ("alu", PEAK["fp64_vector_tflops"], "TFLOP/s"),
+             "chol": ("alu", PEAK["fp64_vector_tflops"], "TFLOP/s")}
     dom = max(prof, key=lambda k: prof[k]["ms"])
     pd = prof[dom]
     bound, peak, unit = peaks[dom]

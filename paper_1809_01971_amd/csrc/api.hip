@@ -63,6 +63,10 @@ struct tp_ctx {
   double* host = nullptr;        // pinned host scratch (kHost doubles)
   EigJob* jobs = nullptr;        // device eig job descriptors
   EigJob* jobs_host = nullptr;   // pinned staging
+  CholJob* cjobs = nullptr;      // device Cholesky job descriptors
+  CholJob* cjobs_host = nullptr; // pinned staging
+  int* qdev = nullptr;           // device ranks written by the Cholesky kernel
+  int* qhost = nullptr;          // pinned copy
   std::map<int, double*> tab64;
   std::map<int, float*> tab32;
   bool jobs_pending = false;     // jobs_host may still be read by an enqueued copy
@@ -119,7 +123,7 @@ struct WsScope {
 // ------------------------------------------------------------------------------ profiling
 // Kernel classes reported by tp_profile_read.
 enum { PC_GEMM_F64 = 0, PC_GEMM_F32 = 1, PC_GEMM_F32_F64 = 2, PC_GEMM_F64_F32 = 3, PC_DST_F64 = 4, PC_DST_F32 = 5,
-       PC_SYEV = 6, PC_COUNT = 7 };
+       PC_SYEV = 6, PC_CHOL = 7, PC_COUNT = 8 };
 
 tp_status prof_begin(tp_ctx* c, size_t* e0) {
   if (!c->prof) return TP_OK;
@@ -323,51 +327,67 @@ tp_status eig(tp_ctx* c, int cnt, const int* K, const double* const* A, double* 
   return TP_OK;
 }
 
-// Orthonormal bases of the column spans of cnt matrices V[i] (n[i] x K[i], double, ld n[i]),
-// two passes of Gram eigendecomposition, all matrices diagonalised in one batched launch per
-// pass (rank revealing: eigenvalues below reltol * max are dropped).  Q[i] is n[i] x q[i] in
-// the workspace; q[i] = 0 for a zero matrix.
+// Pivoted Cholesky of cnt Gram matrices G[i] (K[i] x K[i]): W[i] = P R^-1 (K[i] x q[i]) with the
+// numerical rank q[i] (pivots above tol * max diagonal) returned on the host.
+tp_status chol(tp_ctx* c, int cnt, const int* K, const double* const* G, double tol, double* const* W, int* q) {
+  if (cnt > tp_ctx::kJobs) return fail(TP_EINVAL, "too many Cholesky jobs");
+  int Kmax = 0;
+  for (int i = 0; i < cnt; ++i) Kmax = std::max(Kmax, K[i]);
+  if (Kmax > kMaxRank) return fail(TP_ERANK, "Gram matrix of size %d exceeds %d", Kmax, kMaxRank);
+  double* work = nullptr;
+  if (Kmax > 128) TPCHK(wsalloc(c, (size_t)Kmax * Kmax * cnt, &work));
+  for (int i = 0; i < cnt; ++i)
+    c->cjobs_host[i] = CholJob{K[i], tol, G[i], W[i], c->qdev + i, work ? work + (size_t)Kmax * Kmax * i : nullptr};
+  HIPCHK(hipMemcpyAsync(c->cjobs, c->cjobs_host, sizeof(CholJob) * cnt, hipMemcpyHostToDevice, c->stream));
+  size_t e0 = 0;
+  TPCHK(prof_begin(c, &e0));
+  HIPCHK(pchol_batched(c->cjobs, cnt, Kmax, c->stream));
+  {
+    double fl = 0, by = 0;
+    for (int i = 0; i < cnt; ++i) { fl += 2.0 * K[i] * K[i] * K[i] / 3.0; by += 8.0 * 2.0 * K[i] * K[i]; }
+    TPCHK(prof_end(c, PC_CHOL, e0, fl, by));
+  }
+  HIPCHK(hipMemcpyAsync(c->qhost, c->qdev, sizeof(int) * cnt, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (int i = 0; i < cnt; ++i) q[i] = c->qhost[i];
+  return TP_OK;
+}
+
+// Orthonormal bases of the column spans of cnt matrices V[i] (n[i] x K[i], double, ld n[i]) by
+// two passes of Cholesky QR: the first pass pivots and drops columns whose residual norm falls
+// below sqrt(reltol) of the largest (rank revealing), the second restores orthogonality.  All
+// matrices share one launch per pass.  Q[i] is n[i] x q[i] in the workspace; q[i] = 0 for a zero
+// matrix.
 tp_status ortho_batch(tp_ctx* c, int cnt, const int* n, const int* K, const double* const* V, double reltol,
                       double** Qout, int* qout) {
-  double *G[3], *w[3], *E[3], *W[3], *Q1[3];
-  int Ks[3], q1[3];
+  double *G[3], *W[3], *Q1[3];
+  int q1[3];
   for (int i = 0; i < cnt; ++i) {
     qout[i] = 0;
     Qout[i] = nullptr;
-    Ks[i] = K[i];
     TPCHK(wsalloc(c, (size_t)K[i] * K[i], &G[i]));
-    TPCHK(wsalloc(c, (size_t)K[i], &w[i]));
-    TPCHK(wsalloc(c, (size_t)K[i] * K[i], &E[i]));
     TPCHK(wsalloc(c, (size_t)K[i] * K[i], &W[i]));
     if (K[i] > 0)
       TPCHK(mm<double, double, double, double>(c, true, false, K[i], K[i], n[i], 1.0, V[i], n[i], V[i], n[i], 0.0, G[i], K[i]));
   }
-  std::vector<std::vector<double>> hw;
-  const double* Ap[3] = {G[0], G[1], G[2]};
-  TPCHK(eig(c, cnt, Ks, Ap, w, E, &hw));
+  const double* Gc[3] = {G[0], G[1], G[2]};
+  TPCHK(chol(c, cnt, K, Gc, reltol, W, q1));
+  int q1c[3];
   for (int i = 0; i < cnt; ++i) {
-    double mx = hw[i].empty() ? 0.0 : hw[i][0];
-    int q = 0;
-    while (q < K[i] && hw[i][q] > reltol * mx && hw[i][q] > 0) ++q;
-    q1[i] = q;
+    q1c[i] = q1[i];
     Q1[i] = nullptr;
-    if (q == 0) continue;
-    HIPCHK(eig_inv_sqrt(E[i], w[i], K[i], q, W[i], c->stream));
-    TPCHK(wsalloc(c, (size_t)n[i] * q, &Q1[i]));
-    TPCHK(mm<double, double, double, double>(c, false, false, n[i], q, K[i], 1.0, V[i], n[i], W[i], K[i], 0.0, Q1[i], n[i]));
-    // second pass on Q1 (q x q Gram close to the identity)
-    TPCHK(mm<double, double, double, double>(c, true, false, q, q, n[i], 1.0, Q1[i], n[i], Q1[i], n[i], 0.0, G[i], q));
+    if (q1[i] == 0) continue;
+    TPCHK(wsalloc(c, (size_t)n[i] * q1[i], &Q1[i]));
+    TPCHK(mm<double, double, double, double>(c, false, false, n[i], q1[i], K[i], 1.0, V[i], n[i], W[i], K[i], 0.0, Q1[i], n[i]));
+    TPCHK(mm<double, double, double, double>(c, true, false, q1[i], q1[i], n[i], 1.0, Q1[i], n[i], Q1[i], n[i], 0.0, G[i], q1[i]));
   }
-  TPCHK(eig(c, cnt, q1, Ap, w, E, &hw));
+  int q2[3];
+  TPCHK(chol(c, cnt, q1c, Gc, 1e-14, W, q2));
   for (int i = 0; i < cnt; ++i) {
-    int q = q1[i];
-    if (q == 0) continue;
-    int q2 = 0;
-    while (q2 < q && hw[i][q2] > 1e-14 * hw[i][0] && hw[i][q2] > 0) ++q2;
-    HIPCHK(eig_inv_sqrt(E[i], w[i], q, q2, W[i], c->stream));
-    TPCHK(wsalloc(c, (size_t)n[i] * q2, &Qout[i]));
-    TPCHK(mm<double, double, double, double>(c, false, false, n[i], q2, q, 1.0, Q1[i], n[i], W[i], q, 0.0, Qout[i], n[i]));
-    qout[i] = q2;
+    if (q1[i] == 0 || q2[i] == 0) continue;
+    TPCHK(wsalloc(c, (size_t)n[i] * q2[i], &Qout[i]));
+    TPCHK(mm<double, double, double, double>(c, false, false, n[i], q2[i], q1[i], 1.0, Q1[i], n[i], W[i], q1[i], 0.0, Qout[i], n[i]));
+    qout[i] = q2[i];
   }
   return TP_OK;
 }
@@ -1131,6 +1151,10 @@ tp_status tp_create(int device, void* stream, size_t workspace_bytes, tp_ctx** o
   HIPCHK(hipHostMalloc(&c->host, sizeof(double) * tp_ctx::kHost, hipHostMallocDefault));
   HIPCHK(hipHostMalloc(&c->jobs_host, sizeof(EigJob) * tp_ctx::kJobs, hipHostMallocDefault));
   HIPCHK(hipMalloc(&c->jobs, sizeof(EigJob) * tp_ctx::kJobs));
+  HIPCHK(hipHostMalloc(&c->cjobs_host, sizeof(CholJob) * tp_ctx::kJobs, hipHostMallocDefault));
+  HIPCHK(hipMalloc(&c->cjobs, sizeof(CholJob) * tp_ctx::kJobs));
+  HIPCHK(hipMalloc(&c->qdev, sizeof(int) * tp_ctx::kJobs));
+  HIPCHK(hipHostMalloc(&c->qhost, sizeof(int) * tp_ctx::kJobs, hipHostMallocDefault));
   *out = c;
   return TP_OK;
 }
@@ -1147,6 +1171,10 @@ tp_status tp_destroy(tp_ctx* c) {
   for (auto& kv : c->tab32) (void)hipFree(kv.second);
   (void)hipFree(c->ws);
   (void)hipFree(c->jobs);
+  (void)hipFree(c->cjobs);
+  (void)hipFree(c->qdev);
+  (void)hipHostFree(c->cjobs_host);
+  (void)hipHostFree(c->qhost);
   (void)hipHostFree(c->host);
   (void)hipHostFree(c->jobs_host);
   delete c;

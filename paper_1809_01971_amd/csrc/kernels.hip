@@ -715,6 +715,138 @@ __global__ __launch_bounds__(EIG_NT) void k_syev_small(const EigJob* jobs) {
   for (int i = tid; i < K; i += EIG_NT) J.w[rk[i]] = diag[i];
 }
 
+// Rank-revealing pivoted Cholesky of a Gram matrix G (K x K), one workgroup per job:
+// G[p,p] = R^T R with pivots chosen by the largest remaining diagonal; it stops when the largest
+// remaining diagonal is <= tol * max diag(G).  Output W (K x q, ld K) = P[:, :q] R^-1, so that
+// V W has orthonormal columns spanning V's numerically independent columns; q written to *qout.
+// G is copied into S (LDS when K <= 128, else the job's global scratch).
+template <bool SMEM>
+__global__ __launch_bounds__(EIG_NT) void k_pchol(const CholJob* jobs) {
+  extern __shared__ double sm[];
+  const CholJob J = jobs[blockIdx.x];
+  const int K = J.K;
+  const int tid = threadIdx.x;
+  if (K <= 0) { if (tid == 0 && J.q) *J.q = 0; return; }
+  double* S = SMEM ? sm : J.work;                 // K x K Schur complement / R (row k holds R[k][:])
+  double* red = SMEM ? sm + K * K : sm;           // EIG_NT values + EIG_NT indices
+  int* redi = reinterpret_cast<int*>(red + EIG_NT);
+  int* perm = redi + EIG_NT;                      // K
+  __shared__ double dmax0, piv, dk;
+  __shared__ int pidx, qfinal;
+  for (int e = tid; e < K * K; e += EIG_NT) S[e] = J.g[e];
+  for (int i = tid; i < K; i += EIG_NT) perm[i] = i;
+  __syncthreads();
+  // largest initial diagonal
+  {
+    double m = 0.0;
+    for (int i = tid; i < K; i += EIG_NT) m = fmax(m, S[i + K * i]);
+    red[tid] = m;
+    __syncthreads();
+    for (int w = EIG_NT / 2; w > 0; w >>= 1) { if (tid < w) red[tid] = fmax(red[tid], red[tid + w]); __syncthreads(); }
+    if (tid == 0) { dmax0 = red[0]; qfinal = K; }
+    __syncthreads();
+  }
+  for (int k = 0; k < K; ++k) {
+    // pivot: largest remaining diagonal (ties: lowest index)
+    double m = -1.0;
+    int mi = k;
+    for (int i = k + tid; i < K; i += EIG_NT) {
+      double v = S[i + K * i];
+      if (v > m) { m = v; mi = i; }
+    }
+    red[tid] = m;
+    redi[tid] = mi;
+    __syncthreads();
+    for (int w = EIG_NT / 2; w > 0; w >>= 1) {
+      if (tid < w) {
+        double a = red[tid], b = red[tid + w];
+        int ia = redi[tid], ib = redi[tid + w];
+        if (b > a || (b == a && ib < ia)) { red[tid] = b; redi[tid] = ib; }
+      }
+      __syncthreads();
+    }
+    if (tid == 0) { piv = red[0]; pidx = redi[0]; }
+    __syncthreads();
+    if (!(piv > J.tol * dmax0) || dmax0 <= 0.0) {
+      if (tid == 0) qfinal = k;
+      __syncthreads();
+      break;
+    }
+    const int p = pidx;
+    if (p != k) {
+      // symmetric swap of rows/columns k and p (full storage)
+      for (int i = tid; i < K; i += EIG_NT) {
+        double t = S[k + K * i]; S[k + K * i] = S[p + K * i]; S[p + K * i] = t;
+      }
+      __syncthreads();
+      for (int i = tid; i < K; i += EIG_NT) {
+        double t = S[i + K * k]; S[i + K * k] = S[i + K * p]; S[i + K * p] = t;
+      }
+      if (tid == 0) { int t = perm[k]; perm[k] = perm[p]; perm[p] = t; }
+      __syncthreads();
+    }
+    // d is read once and published before row k is overwritten (the thread that handles
+    // column k writes d into S[k][k])
+    if (tid == 0) dk = sqrt(S[k + K * k]);
+    __syncthreads();
+    const double d = dk;
+    // row k of R: R[k][j] = S[k][j] / d for j >= k (stored in S's row k)
+    for (int j = k + tid; j < K; j += EIG_NT) S[k + K * j] = (j == k) ? d : S[k + K * j] / d;
+    __syncthreads();
+    // trailing update S[i][j] -= R[k][i] R[k][j], i, j > k
+    const int rem = K - k - 1;
+    for (int e = tid; e < rem * rem; e += EIG_NT) {
+      int i = k + 1 + e % rem, j = k + 1 + e / rem;
+      S[i + K * j] -= S[k + K * i] * S[k + K * j];
+    }
+    __syncthreads();
+  }
+  const int q = qfinal;
+  // X = R^-1 (upper triangular), row by row from the bottom:
+  // X[i][j] = (delta_ij - sum_{i<l<=j} R[i][l] X[l][j]) / R[i][i].
+  // X[i][j], j > i, is kept at S[j][i] (the free lower triangle), its diagonal in xd.
+  double* xd = reinterpret_cast<double*>(perm + K + (K & 1));
+  for (int i = q - 1; i >= 0; --i) {
+    const double rii = S[i + K * i];
+    for (int j = i + tid; j < q; j += EIG_NT) {
+      double acc = (j == i) ? 1.0 : 0.0;
+      for (int l = i + 1; l <= j; ++l) {
+        double xlj = (l == j) ? xd[l] : S[j + K * l];
+        acc -= S[i + K * l] * xlj;
+      }
+      if (j == i) xd[i] = acc / rii;
+      else S[j + K * i] = acc / rii;
+    }
+    __syncthreads();
+  }
+  // W = P[:, :q] X: row perm[i] of W is row i of X
+  for (int e = tid; e < K * q; e += EIG_NT) {
+    int r = e % K, j = e / K;
+    J.w[r + (long)K * j] = 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < q * q; e += EIG_NT) {
+    int i = e % q, j = e / q;
+    if (j >= i) J.w[perm[i] + (long)K * j] = (j == i) ? xd[i] : S[j + K * i];
+  }
+  if (tid == 0 && J.q) *J.q = q;
+}
+
+hipError_t pchol_batched(const CholJob* jobs_dev, int count, int Kmax, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (Kmax > EIG_MAX) return hipErrorInvalidValue;
+  if (Kmax <= EIG_LDS_MAX) {
+    size_t shm = (size_t)Kmax * Kmax * 8 + EIG_NT * 12 + (size_t)Kmax * 12 + 64;
+    hipError_t e = hipFuncSetAttribute((const void*)k_pchol<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pchol<true>, dim3(count), dim3(EIG_NT), shm, s, jobs_dev);
+  } else {
+    size_t shm = EIG_NT * 12 + (size_t)Kmax * 12 + 64;
+    hipLaunchKernelGGL(k_pchol<false>, dim3(count), dim3(EIG_NT), shm, s, jobs_dev);
+  }
+  return hipGetLastError();
+}
+
 hipError_t syev_batched(const EigJob* jobs_dev, int count, int Kmax, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   if (Kmax > EIG_MAX) return hipErrorInvalidValue;

@@ -51,6 +51,11 @@ hipError_t dst_table(int N, T* tab, hipStream_t s);
 struct EigJob { int K; const double* a; double* w; double* v; double* work; };
 hipError_t syev_batched(const EigJob* jobs_dev, int count, int Kmax, hipStream_t s);
 
+// Batched rank-revealing pivoted Cholesky of Gram matrices: W = P R^-1 (K x q, ld K), q to *q.
+// Matrices larger than 128 need `work` (K x K doubles) in global memory.
+struct CholJob { int K; double tol; const double* g; double* w; int* q; double* work; };
+hipError_t pchol_batched(const CholJob* jobs_dev, int count, int Kmax, hipStream_t s);
+
 // Elementwise helpers.
 template <typename TI, typename TO>
 hipError_t convert(const TI* in, TO* out, long count, hipStream_t s);
