@@ -38,7 +38,7 @@ typedef enum {
   TP_OK = 0,
   TP_EINVAL = 1,    /* invalid argument (shape, rank, parameter, precision mismatch) */
   TP_ENOMEM = 2,    /* workspace or device allocation too small / failed */
-  TP_ENOCONV = 3,   /* PCG reached kmax; x holds the last iterate (the tables' '---') */
+  TP_ENOCONV = 3,   /* PCG did not reach tau; x holds its best iterate (the tables' '---') */
   TP_ERANK = 4,     /* a truncation hit the rank cap with the tolerance unmet */
   TP_EHIP = 5       /* a HIP runtime call failed */
 } tp_status;
@@ -225,7 +225,7 @@ typedef struct {
   double rel_res;    /* ||R||/||B|| of the recursive residual */
   double true_rel_res;  /* only if requested, else -1 */
   double op_applies; /* number of operator/preconditioner products */
-  double err_est;    /* ||Z||/||X|| at the last step (the stopping quantity) */
+  double err_est;    /* ||Z||/||X|| of the returned X (the stopping quantity) */
 } tp_pcg_info;
 
 /* Solve A_2 x = b with the operator symbol `op`, the preconditioner symbol `pre`
@@ -233,7 +233,10 @@ typedef struct {
  * R = trunc(B - fun(X)) (recomputed, one sketched sum), Z = trunc(pre(R)), stop when
  * ||Z|| <= tau ||X||, P = trunc(Z + beta P).  Iterates are Tucker tensors (the mixed Tucker-canonical route of
  * Sec. 5); every update is truncated as in Algorithm alg:pcg.  x->prec selects
- * the arithmetic; op and pre must have been built with that precision. */
+ * the arithmetic; op and pre must have been built with that precision.
+ * Without convergence (kmax reached, or the estimate grown 8-fold over its minimum, the
+ * rounding floor of the working precision) the call returns TP_ENOCONV and x holds the
+ * iterate with the smallest estimate; TP_ERANK: converged but some truncation hit the cap. */
 tp_status tp_pcg_solve(tp_ctx* ctx, const tp_symbol* op, const tp_symbol* pre,
                        const tp_cp* b, tp_tensor* x, const tp_pcg_opts* opts,
                        const tp_sketch* sketch, tp_pcg_info* info);

@@ -279,7 +279,7 @@ tp_status mm(tp_ctx* c, bool tA, bool tB, int M, int N, int K, double alpha, con
 // ------------------------------------------------------------------------------ eigen
 // Diagonalise `cnt` symmetric matrices (device, double), returning eigenvalues on the host.
 tp_status eig(tp_ctx* c, int cnt, const int* K, const double* const* A, double* const* W, double* const* V,
-              std::vector<std::vector<double>>* host_w) {
+              std::vector<std::vector<double>>* host_w, double tol = 0.0) {
   if (cnt > tp_ctx::kJobs) return fail(TP_EINVAL, "too many eigen jobs");
   if (c->jobs_pending) {
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -295,7 +295,7 @@ tp_status eig(tp_ctx* c, int cnt, const int* K, const double* const* A, double* 
   for (int i = 0; i < cnt; ++i) {
     if (K[i] > kMaxRank) return fail(TP_ERANK, "Gram matrix of size %d exceeds the eigensolver limit %d", K[i], kMaxRank);
     int Kp = (Kmax + 1) & ~1;
-    c->jobs_host[i] = EigJob{K[i], A[i], W[i], V[i], work ? work + (size_t)Kp * Kp * i : nullptr};
+    c->jobs_host[i] = EigJob{K[i], A[i], W[i], V[i], work ? work + (size_t)Kp * Kp * i : nullptr, tol};
   }
   if (Kmax == 0) return TP_OK;
   HIPCHK(hipMemcpyAsync(c->jobs, c->jobs_host, sizeof(EigJob) * cnt, hipMemcpyHostToDevice, c->stream));
@@ -458,7 +458,9 @@ tp_status hosvd(tp_ctx* c, int d, const int* q, const T* M, double tol, int cap,
   }
   std::vector<std::vector<double>> hw;
   const double* Ap[3] = {G[0], G[1], d == 3 ? G[2] : nullptr};
-  TPCHK(eig(c, d, q, Ap, w, E, &hw));
+  // The rank rule compares tail sums of eigenvalues with tol^2 ||M||^2 / d; an off-diagonal
+  // remainder of 1e-2 tol^2 ||G||_F moves every eigenvalue by less than a hundredth of that.
+  TPCHK(eig(c, d, q, Ap, w, E, &hw, std::max(1e-14, 1e-2 * tol * tol)));
   *capped = false;
   for (int m = 0; m < d; ++m) {
     double tot = 0;
@@ -1631,9 +1633,10 @@ tp_status pcg_impl(tp_ctx* c, const tp_symbol* op, const tp_symbol* pre, const t
   WsScope scope(c);
   const int cap = o->cap;
   const double eps = o->trunc_tol;
-  tp_tensor B, X, R, P, Z;
+  tp_tensor B, X, R, P, Z, Xb;
   TPCHK(make_tensor<T>(c, x, cap, &B));
   TPCHK(make_tensor<T>(c, x, cap, &X));
+  TPCHK(make_tensor<T>(c, x, cap, &Xb));
   TPCHK(make_tensor<T>(c, x, cap, &R));
   TPCHK(make_tensor<T>(c, x, cap, &P));
   TPCHK(make_tensor<T>(c, x, cap, &Z));
@@ -1662,7 +1665,8 @@ tp_status pcg_impl(tp_ctx* c, const tp_symbol* op, const tp_symbol* pre, const t
   TPCHK(copy_tensor<T>(c, &Z, &P));
   double rz = 0;
   TPCHK(inner_impl<T>(c, &R, &Z, &rz));
-  bool converged = false;
+  bool converged = false, stalled = false;
+  double best = HUGE_VAL;  // smallest error estimate so far; its iterate is kept in Xb
   int k = 0;
   for (; k < o->kmax; ++k) {
     // S = fun(P) stays in exact factored form (canonical symbol times P): <P,S> is computed
@@ -1698,6 +1702,17 @@ tp_status pcg_impl(tp_ctx* c, const tp_symbol* op, const tp_symbol* pre, const t
     TPCHK(inner_impl<T>(c, &X, &X, &xx));
     info->err_est = std::sqrt(std::max(zz, 0.0) / std::max(xx, 1e-300));
     if (info->err_est <= o->tau) { converged = true; ++k; break; }
+    // Safeguard (not part of the method): once the truncated iteration has reached the floor
+    // set by the working precision, further steps only amplify rounding noise.  The iterate
+    // with the smallest estimate is kept, and the loop stops when the estimate has grown 8-fold.
+    if (info->err_est < best) {
+      best = info->err_est;
+      TPCHK(copy_tensor<T>(c, &X, &Xb));
+    } else if (info->err_est > 8.0 * best) {
+      stalled = true;
+      ++k;
+      break;
+    }
     double rz_new = 0;
     TPCHK(inner_impl<T>(c, &R, &Z, &rz_new));
     const double beta = rz_new / rz;
@@ -1710,6 +1725,10 @@ tp_status pcg_impl(tp_ctx* c, const tp_symbol* op, const tp_symbol* pre, const t
     }
   }
   info->iters = k;
+  if (!converged && best < info->err_est) {
+    TPCHK(copy_tensor<T>(c, &Xb, &X));
+    info->err_est = best;
+  }
   TPCHK(copy_tensor<T>(c, &X, x));
   for (int m = 0; m < 3; ++m) info->rank[m] = m < x->d ? x->rank[m] : 0;
   if (o->true_residual) {
@@ -1722,7 +1741,11 @@ tp_status pcg_impl(tp_ctx* c, const tp_symbol* op, const tp_symbol* pre, const t
   }
   if (!converged) {
     info->status = TP_ENOCONV;
-    return fail(TP_ENOCONV, "PCG did not reach tau=%g in %d iterations (rel_res %g)", o->tau, o->kmax, info->rel_res);
+    if (stalled)
+      return fail(TP_ENOCONV, "PCG stalled at error estimate %g > tau=%g after %d iterations (precision floor); "
+                  "x holds the best iterate", info->err_est, o->tau, k);
+    return fail(TP_ENOCONV, "PCG did not reach tau=%g in %d iterations (error estimate %g); x holds the best iterate",
+                o->tau, o->kmax, info->err_est);
   }
   info->status = anycap ? TP_ERANK : TP_OK;
   return TP_OK;

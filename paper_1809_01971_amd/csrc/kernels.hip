@@ -517,10 +517,11 @@ __global__ __launch_bounds__(256) void k_syev(const EigJob* jobs) {
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) { if (tid < w) red[tid] += red[tid + w]; __syncthreads(); }
     double tots = red[0];
-    // stop once the off-diagonal part is below 1e-14 ||A||_F (the FP64 rounding floor of the
-    // rotations is about K * 1e-16 ||A||_F); rotations smaller than 1e-16 ||A||_F are skipped
+    // stop once the off-diagonal part is below J.tol ||A||_F (default 1e-14; the FP64 rounding
+    // floor of the rotations is about K * 1e-16 ||A||_F); rotations below 1e-16 ||A||_F are skipped
     if (tid == 0) {
-      done = (offs <= 1e-28 * tots || tots == 0.0) ? 1 : 0;
+      const double t2 = J.tol > 0 ? J.tol * J.tol : 1e-28;
+      done = (offs <= t2 * tots || tots == 0.0) ? 1 : 0;
       thr = 1e-16 * sqrt(tots);
     }
     __syncthreads();
@@ -643,7 +644,8 @@ __global__ __launch_bounds__(EIG_NT) void k_syev_small(const EigJob* jobs) {
       __syncthreads();
     }
     if (tid == 0) {
-      done = (red[0] <= 1e-28 * red[EIG_NT] || red[EIG_NT] == 0.0) ? 1 : 0;
+      const double t2 = J.tol > 0 ? J.tol * J.tol : 1e-28;
+      done = (red[0] <= t2 * red[EIG_NT] || red[EIG_NT] == 0.0) ? 1 : 0;
       thr = 1e-16 * sqrt(red[EIG_NT]);
     }
     __syncthreads();

@@ -48,7 +48,8 @@ hipError_t dst_table(int N, T* tab, hipStream_t s);
 // Batched symmetric Jacobi eigensolver, FP64.  Matrix b: K[b] x K[b] at a[b] (ld K[b]);
 // eigenvalues (descending) to w[b], eigenvectors to v[b] (ld K[b]).
 // Matrices larger than 128 need `work` (Kp x Kp doubles, Kp = K rounded up to even) in global memory.
-struct EigJob { int K; const double* a; double* w; double* v; double* work; };
+// tol: the sweeps stop once the off-diagonal Frobenius norm is <= tol * ||A||_F (0 = 1e-14).
+struct EigJob { int K; const double* a; double* w; double* v; double* work; double tol; };
 hipError_t syev_batched(const EigJob* jobs_dev, int count, int Kmax, hipStream_t s);
 
 // Batched rank-revealing pivoted Cholesky of Gram matrices: W = P R^-1 (K x q, ld K), q to *q.
