@@ -63,6 +63,8 @@ struct tp_ctx {
   double* host = nullptr;        // pinned host scratch (kHost doubles)
   EigJob* jobs = nullptr;        // device eig job descriptors
   EigJob* jobs_host = nullptr;   // pinned staging
+  PsdJob* pjobs = nullptr;       // device Gram eigensolver job descriptors
+  PsdJob* pjobs_host = nullptr;  // pinned staging
   CholJob* cjobs = nullptr;      // device Cholesky job descriptors
   CholJob* cjobs_host = nullptr; // pinned staging
   int* qdev = nullptr;           // device ranks written by the Cholesky kernel
@@ -232,11 +234,12 @@ int gemm_class() {
 template <typename TA, typename TB, typename TC, typename Tacc>
 tp_status run(tp_ctx* c, const GemmArgs<TA, TB, TC, Tacc>& g0) {
   GemmArgs<TA, TB, TC, Tacc> g = g0;
-  // few output tiles and a long contraction: split K over workgroups so the launch fills the GPU
+  // few output tiles and a long contraction: split K over workgroups (chunks of at least 64)
+  // so that about 512 workgroups share the launch; the partial sums are added by a second kernel
   const long tiles = (long)((g.M + 63) / 64) * ((g.N + 63) / 64) * g.batch;
   size_t mark = c->ws_top;
-  if (tiles < 128 && g.K >= 1024) {
-    int splits = (int)std::min<long>((g.K + 511) / 512, std::max<long>(1, 512 / tiles));
+  if (tiles < 256 && g.K >= 128) {
+    int splits = (int)std::min<long>((g.K + 63) / 64, std::max<long>(1, 512 / tiles));
     if (splits > 1) {
       Tacc* part = nullptr;
       if (wsalloc(c, (size_t)g.batch * splits * g.M * g.N, &part) == TP_OK) {
@@ -335,9 +338,9 @@ tp_status chol(tp_ctx* c, int cnt, const int* K, const double* const* G, double 
   for (int i = 0; i < cnt; ++i) Kmax = std::max(Kmax, K[i]);
   if (Kmax > kMaxRank) return fail(TP_ERANK, "Gram matrix of size %d exceeds %d", Kmax, kMaxRank);
   double* work = nullptr;
-  if (Kmax > 128) TPCHK(wsalloc(c, (size_t)Kmax * Kmax * cnt, &work));
+  if (Kmax > kGramLds) TPCHK(wsalloc(c, (size_t)2 * Kmax * Kmax * cnt, &work));
   for (int i = 0; i < cnt; ++i)
-    c->cjobs_host[i] = CholJob{K[i], tol, G[i], W[i], c->qdev + i, work ? work + (size_t)Kmax * Kmax * i : nullptr};
+    c->cjobs_host[i] = CholJob{K[i], tol, G[i], W[i], c->qdev + i, work ? work + (size_t)2 * Kmax * Kmax * i : nullptr};
   HIPCHK(hipMemcpyAsync(c->cjobs, c->cjobs_host, sizeof(CholJob) * cnt, hipMemcpyHostToDevice, c->stream));
   size_t e0 = 0;
   TPCHK(prof_begin(c, &e0));
@@ -350,6 +353,64 @@ tp_status chol(tp_ctx* c, int cnt, const int* K, const double* const* G, double 
   HIPCHK(hipMemcpyAsync(c->qhost, c->qdev, sizeof(int) * cnt, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   for (int i = 0; i < cnt; ++i) q[i] = c->qhost[i];
+  return TP_OK;
+}
+
+// Eigenpairs of cnt positive semidefinite Gram matrices (pivoted Cholesky + one-sided Jacobi):
+// eigenvalues (descending) on the host in host_w, numerical ranks in q, and the trace the
+// Cholesky left unresolved in rest (it belongs to the discarded tail).
+tp_status psd_eig(tp_ctx* c, int cnt, const int* K, const double* const* G, double* const* W, double* const* V,
+                  double jtol, std::vector<std::vector<double>>* host_w, int* q, double* rest) {
+  if (cnt > tp_ctx::kJobs) return fail(TP_EINVAL, "too many eigen jobs");
+  int Kmax = 0;
+  size_t tot = 0;
+  for (int i = 0; i < cnt; ++i) {
+    if (K[i] > kMaxRank) return fail(TP_ERANK, "Gram matrix of size %d exceeds the eigensolver limit %d", K[i], kMaxRank);
+    Kmax = std::max(Kmax, K[i]);
+    tot += K[i];
+  }
+  if (tot + 2 * cnt > tp_ctx::kHost) return fail(TP_EINVAL, "eigenvalue staging too small");
+  double* work = nullptr;
+  if (Kmax > kGramLds) TPCHK(wsalloc(c, (size_t)2 * Kmax * Kmax * cnt, &work));
+  double* dres;  // cnt traces then cnt ranks (as int)
+  TPCHK(wsalloc(c, (size_t)2 * cnt, &dres));
+  int* dq = reinterpret_cast<int*>(dres + cnt);
+  for (int i = 0; i < cnt; ++i)
+    c->pjobs_host[i] = PsdJob{K[i], G[i], W[i], V[i], dq + i, dres + i,
+                              work ? work + (size_t)2 * Kmax * Kmax * i : nullptr, 1e-16, jtol};
+  if (Kmax == 0) {
+    host_w->assign(cnt, {});
+    for (int i = 0; i < cnt; ++i) { q[i] = 0; rest[i] = 0.0; }
+    return TP_OK;
+  }
+  HIPCHK(hipMemcpyAsync(c->pjobs, c->pjobs_host, sizeof(PsdJob) * cnt, hipMemcpyHostToDevice, c->stream));
+  size_t e0 = 0;
+  TPCHK(prof_begin(c, &e0));
+  HIPCHK(psd_eig_batched(c->pjobs, cnt, Kmax, c->stream));
+  {
+    // algorithmic work: Cholesky K^3/3 plus about 4 sweeps of 3 K^3 (one-sided Jacobi)
+    double fl = 0, by = 0;
+    for (int i = 0; i < cnt; ++i) { fl += 12.5 * K[i] * K[i] * K[i]; by += 8.0 * (2.0 * K[i] * K[i] + K[i]); }
+    TPCHK(prof_end(c, PC_SYEV, e0, fl, by));
+  }
+  size_t off = 0;
+  for (int i = 0; i < cnt; ++i) {
+    HIPCHK(hipMemcpyAsync(c->host + off, W[i], sizeof(double) * K[i], hipMemcpyDeviceToHost, c->stream));
+    off += K[i];
+  }
+  HIPCHK(hipMemcpyAsync(c->host + off, dres, sizeof(double) * 2 * cnt, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  host_w->assign(cnt, {});
+  const int* hq = reinterpret_cast<const int*>(c->host + off + cnt);
+  for (int i = 0; i < cnt; ++i) {
+    rest[i] = c->host[off + i];
+    q[i] = hq[i];
+  }
+  off = 0;
+  for (int i = 0; i < cnt; ++i) {
+    (*host_w)[i].assign(c->host + off, c->host + off + K[i]);
+    off += K[i];
+  }
   return TP_OK;
 }
 
@@ -458,18 +519,20 @@ tp_status hosvd(tp_ctx* c, int d, const int* q, const T* M, double tol, int cap,
   }
   std::vector<std::vector<double>> hw;
   const double* Ap[3] = {G[0], G[1], d == 3 ? G[2] : nullptr};
-  // The rank rule compares tail sums of eigenvalues with tol^2 ||M||^2 / d; an off-diagonal
-  // remainder of 1e-2 tol^2 ||G||_F moves every eigenvalue by less than a hundredth of that.
-  TPCHK(eig(c, d, q, Ap, w, E, &hw, std::max(1e-14, 1e-2 * tol * tol)));
+  int qr[3] = {0, 0, 0};
+  double rest[3] = {0, 0, 0};
+  // The rank rule compares tail sums of eigenvalues with tol^2 ||M||^2 / d; Jacobi rotations stop
+  // once every column pair is orthogonal to 1e-2 tol^2 (relative), far below what moves that sum.
+  TPCHK(psd_eig(c, d, q, Ap, w, E, std::max(1e-14, 1e-2 * tol * tol), &hw, qr, rest));
   *capped = false;
   for (int m = 0; m < d; ++m) {
-    double tot = 0;
+    double tot = rest[m];
     for (double v : hw[m]) tot += std::max(v, 0.0);
     double thr = tol * tol * tot / d;
-    int r = q[m];
-    double tail = 0;
-    // smallest r with sum_{i >= r} w_i <= thr
-    for (int i = q[m] - 1; i >= 1; --i) {
+    // smallest r <= numerical rank with rest + sum_{i >= r} w_i <= thr
+    int r = std::max(qr[m], 1);
+    double tail = rest[m];
+    for (int i = qr[m] - 1; i >= 1; --i) {
       double v = std::max(hw[m][i], 0.0);
       if (tail + v > thr) break;
       tail += v;
@@ -899,7 +962,7 @@ tp_status inner_sym_impl(tp_ctx* c, const tp_tensor* x, const tp_symbol* S, cons
   TPCHK(wsalloc(c, cx, &Cx));
   TPCHK(wsalloc(c, cy, &Cy));
   TPCHK(wsalloc(c, cx, &Z));
-  TPCHK(wsalloc(c, 1, &res));
+  TPCHK(wsalloc(c, 257, &res));  // result + per-workgroup partial sums
   HIPCHK((convert<T, double>((const T*)x->core, Cx, (long)cx, c->stream)));
   HIPCHK((convert<T, double>((const T*)y->core, Cy, (long)cy, c->stream)));
   // Z = sum_k Cy x_1 G1_k x_2 G2_k x_3 G3_k  (rx1 x rx2 x rx3)
@@ -931,7 +994,7 @@ tp_status inner_sym_impl(tp_ctx* c, const tp_tensor* x, const tp_symbol* S, cons
     TPCHK(run(c, g1));
     TPCHK((mm<double, double, double, double>(c, false, true, rx[0], rx[1], ry[1] * R, 1.0, D, rx[0], G[1], rx[1], 0.0, Z, rx[0])));
   }
-  HIPCHK(dot<double>(Cx, Z, (long)cx, res, c->stream));
+  HIPCHK(dot<double>(Cx, Z, (long)cx, res, res + 1, c->stream));
   TPCHK(sync_to_host(c, res, sizeof(double), c->host));
   *out = c->host[0];
   return TP_OK;
@@ -979,14 +1042,14 @@ tp_status inner_impl(tp_ctx* c, const tp_tensor* x, const tp_tensor* y, double* 
   TPCHK(wsalloc(c, cy, &Cy));
   TPCHK(wsalloc(c, cx, &Cx));
   TPCHK(wsalloc(c, cx, &Z));
-  TPCHK(wsalloc(c, 1, &res));
+  TPCHK(wsalloc(c, 257, &res));  // result + per-workgroup partial sums
   HIPCHK((convert<T, double>((const T*)y->core, Cy, (long)cy, c->stream)));
   HIPCHK((convert<T, double>((const T*)x->core, Cx, (long)cx, c->stream)));
   const double* A[3] = {G[0], G[1], G[2]};
   int lda[3] = {px[0], px[1], px[2]};
   bool tA[3] = {false, false, false};
   TPCHK(tucker_contract(c, d, ry, Cy, A, lda, tA, px, 1.0, 0.0, Z));
-  HIPCHK(dot<double>(Cx, Z, (long)cx, res, c->stream));
+  HIPCHK(dot<double>(Cx, Z, (long)cx, res, res + 1, c->stream));
   TPCHK(sync_to_host(c, res, sizeof(double), c->host));
   *out = c->host[0];
   return TP_OK;
@@ -1153,6 +1216,8 @@ tp_status tp_create(int device, void* stream, size_t workspace_bytes, tp_ctx** o
   HIPCHK(hipHostMalloc(&c->host, sizeof(double) * tp_ctx::kHost, hipHostMallocDefault));
   HIPCHK(hipHostMalloc(&c->jobs_host, sizeof(EigJob) * tp_ctx::kJobs, hipHostMallocDefault));
   HIPCHK(hipMalloc(&c->jobs, sizeof(EigJob) * tp_ctx::kJobs));
+  HIPCHK(hipHostMalloc(&c->pjobs_host, sizeof(PsdJob) * tp_ctx::kJobs, hipHostMallocDefault));
+  HIPCHK(hipMalloc(&c->pjobs, sizeof(PsdJob) * tp_ctx::kJobs));
   HIPCHK(hipHostMalloc(&c->cjobs_host, sizeof(CholJob) * tp_ctx::kJobs, hipHostMallocDefault));
   HIPCHK(hipMalloc(&c->cjobs, sizeof(CholJob) * tp_ctx::kJobs));
   HIPCHK(hipMalloc(&c->qdev, sizeof(int) * tp_ctx::kJobs));
@@ -1174,6 +1239,8 @@ tp_status tp_destroy(tp_ctx* c) {
   (void)hipFree(c->ws);
   (void)hipFree(c->jobs);
   (void)hipFree(c->cjobs);
+  (void)hipFree(c->pjobs);
+  (void)hipHostFree(c->pjobs_host);
   (void)hipFree(c->qdev);
   (void)hipHostFree(c->cjobs_host);
   (void)hipHostFree(c->qhost);
@@ -1627,6 +1694,16 @@ tp_status copy_tensor(tp_ctx* c, const tp_tensor* src, tp_tensor* dst) {
   return TP_OK;
 }
 
+// dst = a * src (the core is scaled, factors copied).
+template <typename T>
+tp_status scaled_copy(tp_ctx* c, double a, const tp_tensor* src, tp_tensor* dst) {
+  TPCHK(copy_tensor<T>(c, src, dst));
+  const int d = src->d;
+  const int csz = src->rank[0] * src->rank[1] * (d == 3 ? src->rank[2] : 1);
+  HIPCHK((copy2d<T, T>(csz, 1, (const T*)src->core, csz, (T*)dst->core, csz, a, c->stream)));
+  return TP_OK;
+}
+
 template <typename T>
 tp_status pcg_impl(tp_ctx* c, const tp_symbol* op, const tp_symbol* pre, const tp_cp* b, tp_tensor* x,
                    const tp_pcg_opts* o, const tp_sketch* sk, tp_pcg_info* info) {
@@ -1676,7 +1753,10 @@ tp_status pcg_impl(tp_ctx* c, const tp_symbol* op, const tp_symbol* pre, const t
     TPCHK(inner_sym_impl<T>(c, &P, op, &P, &ps));
     if (!(ps > 0)) return fail(TP_ENOCONV, "PCG breakdown: <P,S> = %g", ps);
     const double a = rz / ps;
-    {
+    if (k == 0) {
+      // X0 = 0: X1 = a P exactly (P is already truncated, a sum with zero adds nothing to cut)
+      TPCHK(scaled_copy<T>(c, a, &P, &X));
+    } else {
       const tp_tensor* xs[2] = {&X, &P};
       double cf[2] = {1.0, a};
       TPCHK(truncate_impl<T>(c, 2, cf, xs, &X, eps, cap, &capped));

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
 #include <type_traits>
 
 namespace tpk {
@@ -154,11 +155,60 @@ __device__ __forceinline__ d4_t mfma16(double a, double b, d4_t c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// One stage of the MFMA kernel covers MBK contraction indices; each thread holds 8 elements of
+// the A tile and 8 of the B tile in registers, so the next stage's global loads are in flight
+// while the current stage is multiplied out of LDS.
+constexpr int MBK = 32;
+
+template <typename TA, typename TB, typename TC, typename Tacc>
+__device__ __forceinline__ void mfma_fetch(const GemmArgs<TA, TB, TC, Tacc>& g, const TA* A, const TB* B,
+                                           const FaceSplit<TA>& FA, const FaceSplit<TB>& FB, int m0, int n0,
+                                           int k0, int kend, int tid, Tacc (&ra)[8], Tacc (&rb)[8]) {
+  if (!g.tA) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      int m = tid & 63, kk = (tid >> 6) + 4 * i;
+      int row = m0 + m, col = k0 + kk;
+      Tacc v = 0;
+      if (row < g.M && col < kend) v = g.fsA ? (Tacc)fs_load(FA, row, col) : (Tacc)A[row + (long)g.lda * col];
+      ra[i] = v;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      int kk = tid & 31, m = (tid >> 5) + 8 * i;
+      int row = m0 + m, col = k0 + kk;
+      Tacc v = 0;
+      if (row < g.M && col < kend) v = (Tacc)A[col + (long)g.lda * row];
+      ra[i] = v;
+    }
+  }
+  if (!g.tB) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      int kk = tid & 31, n = (tid >> 5) + 8 * i;
+      int row = k0 + kk, col = n0 + n;
+      Tacc v = 0;
+      if (row < kend && col < g.N) v = g.fsB ? (Tacc)fs_load(FB, row, col) : (Tacc)B[row + (long)g.ldb * col];
+      rb[i] = v;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      int n = tid & 63, kk = (tid >> 6) + 4 * i;
+      int row = k0 + kk, col = n0 + n;
+      Tacc v = 0;
+      if (row < kend && col < g.N) v = (Tacc)B[col + (long)g.ldb * row];
+      rb[i] = v;
+    }
+  }
+}
+
 template <typename TA, typename TB, typename TC, typename Tacc>
 __global__ __launch_bounds__(GTHREADS) void k_gemm_mfma(GemmArgs<TA, TB, TC, Tacc> g) {
   typedef typename std::conditional<std::is_same<Tacc, double>::value, d4_t, f4_t>::type V4;
-  __shared__ Tacc As[GBK][GBM + 4];
-  __shared__ Tacc Bs[GBK][GBN + 4];
+  __shared__ Tacc As[MBK][GBM + 4];
+  __shared__ Tacc Bs[MBK][GBN + 4];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
@@ -182,48 +232,27 @@ __global__ __launch_bounds__(GTHREADS) void k_gemm_mfma(GemmArgs<TA, TB, TC, Tac
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
 
-  for (int k0 = kbeg; k0 < kend; k0 += GBK) {
+  Tacc ra[8], rb[8];
+  if (kbeg < kend) mfma_fetch(g, A, B, FA, FB, m0, n0, kbeg, kend, tid, ra, rb);
+  for (int k0 = kbeg; k0 < kend; k0 += MBK) {
     if (!g.tA) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        int m = tid % 64, kk = tid / 64 + 4 * i;
-        int row = m0 + m, col = k0 + kk;
-        Tacc v = 0;
-        if (row < g.M && col < kend) v = g.fsA ? (Tacc)fs_load(FA, row, col) : (Tacc)A[row + (long)g.lda * col];
-        As[kk][m] = v;
-      }
+      for (int i = 0; i < 8; ++i) As[(tid >> 6) + 4 * i][tid & 63] = ra[i];
     } else {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        int kk = tid % 16, m = tid / 16 + 16 * i;
-        int row = m0 + m, col = k0 + kk;
-        Tacc v = 0;
-        if (row < g.M && col < kend) v = (Tacc)A[col + (long)g.lda * row];
-        As[kk][m] = v;
-      }
+      for (int i = 0; i < 8; ++i) As[tid & 31][(tid >> 5) + 8 * i] = ra[i];
     }
     if (!g.tB) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        int kk = tid % 16, n = tid / 16 + 16 * i;
-        int row = k0 + kk, col = n0 + n;
-        Tacc v = 0;
-        if (row < kend && col < g.N) v = g.fsB ? (Tacc)fs_load(FB, row, col) : (Tacc)B[row + (long)g.ldb * col];
-        Bs[kk][n] = v;
-      }
+      for (int i = 0; i < 8; ++i) Bs[tid & 31][(tid >> 5) + 8 * i] = rb[i];
     } else {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        int n = tid % 64, kk = tid / 64 + 4 * i;
-        int row = k0 + kk, col = n0 + n;
-        Tacc v = 0;
-        if (row < kend && col < g.N) v = (Tacc)B[col + (long)g.ldb * row];
-        Bs[kk][n] = v;
-      }
+      for (int i = 0; i < 8; ++i) Bs[(tid >> 6) + 4 * i][tid & 63] = rb[i];
     }
     __syncthreads();
+    if (k0 + MBK < kend) mfma_fetch(g, A, B, FA, FB, m0, n0, k0 + MBK, kend, tid, ra, rb);
 #pragma unroll
-    for (int kk = 0; kk < GBK; kk += 4) {
+    for (int kk = 0; kk < MBK; kk += 4) {
       const int kr = kk + (lane >> 4), c16 = lane & 15;
       Tacc a0 = As[kr][wm + c16], a1 = As[kr][wm + 16 + c16];
       Tacc b0 = Bs[kr][wn + c16], b1 = Bs[kr][wn + 16 + c16];
@@ -286,7 +315,8 @@ hipError_t gemm(const GemmArgs<TA, TB, TC, Tacc>& g, hipStream_t s) {
   }
   GemmArgs<TA, TB, TC, Tacc> h = g;
   if (h.splits < 1 || !h.part) { h.splits = 1; h.part = nullptr; }
-  h.kchunk = h.splits > 1 ? ((h.K + h.splits - 1) / h.splits + GBK - 1) / GBK * GBK : h.K;
+  // split chunks are multiples of both kernels' stage depths
+  h.kchunk = h.splits > 1 ? ((h.K + h.splits - 1) / h.splits + MBK - 1) / MBK * MBK : h.K;
   dim3 grid((h.M + GBM - 1) / GBM, (h.N + GBN - 1) / GBN, h.batch * h.splits);
   if (gemm_use_mfma())
     hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TC, Tacc>), grid, dim3(GTHREADS), 0, s, h);
@@ -465,7 +495,7 @@ template hipError_t dst1<float>(int, int, const float*, int, float*, int, const 
 // ---------------------------------------------------------------------------------------------
 // Cyclic Jacobi eigensolver (FP64), round-robin parallel ordering, A in LDS, V in global.
 // ---------------------------------------------------------------------------------------------
-constexpr int EIG_LDS_MAX = 128;   // matrices up to this size live in LDS
+constexpr int EIG_LDS_MAX = kGramLds;  // matrices up to this size live in LDS
 constexpr int EIG_MAX = 256;       // larger ones (up to this) live in global scratch
 
 __device__ __forceinline__ int rr_index(int j, int s, int Kp) {
@@ -717,136 +747,447 @@ __global__ __launch_bounds__(EIG_NT) void k_syev_small(const EigJob* jobs) {
   for (int i = tid; i < K; i += EIG_NT) J.w[rk[i]] = diag[i];
 }
 
-// Rank-revealing pivoted Cholesky of a Gram matrix G (K x K), one workgroup per job:
-// G[p,p] = R^T R with pivots chosen by the largest remaining diagonal; it stops when the largest
-// remaining diagonal is <= tol * max diag(G).  Output W (K x q, ld K) = P[:, :q] R^-1, so that
-// V W has orthonormal columns spanning V's numerically independent columns; q written to *qout.
-// G is copied into S (LDS when K <= 128, else the job's global scratch).
-template <bool SMEM>
-__global__ __launch_bounds__(EIG_NT) void k_pchol(const CholJob* jobs) {
+// ---------------------------------------------------------------------------------------------
+// Pivoted Cholesky of Gram matrices, shared by the orthonormalisation (k_pchol) and the Gram
+// eigensolver (k_psd_eig).  G[P,P] = R^T R, the pivot of each step being the largest remaining
+// diagonal entry; it stops once that entry is <= ctol * max diag(G).  The Schur complement is
+// kept in original index order, upper triangle only (element (a, b), a <= b, at S[a + K b]).
+// Step k with pivot p updates S[i][j] -= S[p][i] S[p][j] / S[p][p] over the unpivoted i <= j;
+// row p is never written again, so R(k, l) = S[p, perm_l] / sqrt(S[p][p]).
+// The threads form a TX x TY grid: thread (tx, ty) owns the elements (tx + TX a, ty + TY b) and
+// keeps which of its rows and columns are pivoted in registers.  Each wave reduces the
+// candidate keys of the diagonal entries it updated into a double-buffered slot, so one
+// barrier per step suffices; every wave then reads the next pivot from the slots by itself.
+// The workgroup is sized to the matrix (256 threads up to K = 64, 512 up to 128, 1024 beyond):
+// every thread runs the whole step sequence, so idle lanes would only cost issue slots.
+// ---------------------------------------------------------------------------------------------
+struct CholShared { double rest; int q; };
+
+template <int NT> struct ChGrid;
+template <> struct ChGrid<256> { static constexpr int TX = 16, NBI = 4, NBJ = 4, KMAX = 64; };
+template <> struct ChGrid<512> { static constexpr int TX = 32, NBI = 4, NBJ = 8, KMAX = 128; };
+template <> struct ChGrid<1024> { static constexpr int TX = 32, NBI = 8, NBJ = 8, KMAX = 256; };
+
+// Pivot candidates travel as 64-bit keys: a positive double orders like its bit pattern, and
+// its lowest 8 bits are replaced by 255 - index, so the maximum key is the largest value with
+// ties (to 2^-44 relative) going to the lowest index.  Non-positive values give key 0.
+__device__ __forceinline__ unsigned long long pivot_key(double v, int i) {
+  return v > 0.0 ? (((unsigned long long)__double_as_longlong(v) & ~0xFFull) | (unsigned long long)(255 - i)) : 0ull;
+}
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v) {
+  const int lo = __builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(v >> 32), CTRL, 0xF, 0xF, false);
+  return (unsigned long long)(unsigned)lo | ((unsigned long long)(unsigned)hi << 32);
+}
+__device__ __forceinline__ unsigned long long umax64(unsigned long long a, unsigned long long b) { return a > b ? a : b; }
+__device__ __forceinline__ unsigned long long readlane64(unsigned long long v, int lane) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)v, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(v >> 32), lane);
+  return (unsigned long long)lo | ((unsigned long long)hi << 32);
+}
+// Maximum key over the wave (DPP within rows of 16 lanes, then the four row results are read
+// into scalars); the result is uniform.
+__device__ __forceinline__ unsigned long long wave_max_key(unsigned long long v) {
+  v = umax64(v, dpp_u64<0xB1>(v));
+  v = umax64(v, dpp_u64<0x4E>(v));
+  v = umax64(v, dpp_u64<0x141>(v));
+  v = umax64(v, dpp_u64<0x140>(v));
+  return umax64(umax64(readlane64(v, 0), readlane64(v, 16)), umax64(readlane64(v, 32), readlane64(v, 48)));
+}
+
+// Returns the rank q (the same in every thread).  dk[k] = sqrt(pivot k); perm holds the pivots,
+// then the unpivoted indices in increasing order; sh.rest = trace left in the Schur complement.
+// slot: 2 x NT/64 keys; mark: K ints of scratch.  K <= ChGrid<NT>::KMAX.
+template <int NT>
+__device__ __forceinline__ int chol_phase(const double* G, int K, double ctol, double* S, double* dk, int* perm,
+                                          unsigned long long* slot, int* mark, CholShared& sh) {
+  constexpr int TX = ChGrid<NT>::TX, TY = NT / TX, NBI = ChGrid<NT>::NBI, NBJ = ChGrid<NT>::NBJ, NW = NT / 64;
+  // up to 512 threads the owned entries also live in registers (the LDS copy serves the
+  // pivot-row reads of the other threads)
+  constexpr bool REG = NT <= 512;
+  constexpr int NR = REG ? NBI * NBJ : 1;
+  const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX, lane = tid & 63, wave = tid >> 6;
+  unsigned piv_i = 0, piv_j = 0;  // bit a: row tx + TX a / column ty + TY b pivoted
+  double sv[NR];
+  unsigned long long best = 0ull;
+#pragma unroll
+  for (int b = 0; b < NBJ; ++b)
+#pragma unroll
+    for (int a = 0; a < NBI; ++a) {
+      const int i = tx + TX * a, j = ty + TY * b;
+      double v = 0.0;
+      if (i <= j && j < K) {
+        v = G[i + (long)K * j];
+        S[i + K * j] = v;
+        if (i == j) best = umax64(best, pivot_key(v, i));
+      }
+      if (REG) sv[(a + NBI * b) % NR] = v;
+    }
+  best = wave_max_key(best);
+  if (lane == 0) slot[wave] = best;
+  __syncthreads();
+  const unsigned long long k0 = wave_max_key(lane < NW ? slot[lane] : 0ull);
+  const double dmax0 = k0 ? S[(255 - (int)(k0 & 0xFF)) * (K + 1)] : 0.0;
+  const double stop = ctol * dmax0;
+  int q = K;
+  for (int k = 0; k < K; ++k) {
+    const int buf = (k & 1) * NW;
+    const unsigned long long key = wave_max_key(lane < NW ? slot[buf + lane] : 0ull);
+    const int p = 255 - (int)(key & 0xFF);
+    // the pivot row S[p][.] (and S[p][p]) is read in one batch of independent loads
+    double spi[NBI], spj[NBJ];
+#pragma unroll
+    for (int a = 0; a < NBI; ++a) {
+      const int i = tx + TX * a;
+      spi[a] = (key && i < K) ? S[min(p, i) + K * max(p, i)] : 0.0;
+    }
+#pragma unroll
+    for (int b = 0; b < NBJ; ++b) {
+      const int j = ty + TY * b;
+      spj[b] = (key && j < K) ? S[min(p, j) + K * max(p, j)] : 0.0;
+    }
+    const double pv = key ? S[p * (K + 1)] : 0.0;
+    if (!key || !(pv > stop) || !(dmax0 > 0.0)) { q = k; break; }  // uniform
+    if (tid == 0) { perm[k] = p; dk[k] = sqrt(pv); }
+    if (p % TX == tx) piv_i |= 1u << (p / TX);
+    if (p % TY == ty) piv_j |= 1u << (p / TY);
+    const double inv = 1.0 / pv;
+    best = 0ull;
+#pragma unroll
+    for (int b = 0; b < NBJ; ++b)
+#pragma unroll
+      for (int a = 0; a < NBI; ++a) {
+        const int i = tx + TX * a, j = ty + TY * b;
+        if (i <= j && j < K && !((piv_i >> a) & 1) && !((piv_j >> b) & 1)) {
+          const double old = REG ? sv[(a + NBI * b) % NR] : S[i + K * j];
+          const double v = old - spi[a] * (spj[b] * inv);
+          if (REG) sv[(a + NBI * b) % NR] = v;
+          S[i + K * j] = v;
+          if (i == j) best = umax64(best, pivot_key(v, i));
+        }
+      }
+    best = wave_max_key(best);
+    if (lane == 0) slot[NW - buf + wave] = best;
+    __syncthreads();
+  }
+  __syncthreads();
+  // unpivoted indices (in increasing order) after the pivots, and their remaining trace
+  for (int i = tid; i < K; i += NT) mark[i] = 0;
+  __syncthreads();
+  for (int k = tid; k < q; k += NT) mark[perm[k]] = 1;
+  __syncthreads();
+  for (int i = tid; i < K; i += NT)
+    if (!mark[i]) {
+      int c = 0;
+      for (int j = 0; j < i; ++j) c += mark[j] ? 0 : 1;
+      perm[q + c] = i;
+    }
+  if (tid < 64) {
+    double r = 0.0;
+    for (int i = tid; i < K; i += 64)
+      if (!mark[i]) r += fmax(S[i + K * i], 0.0);
+    for (int o = 32; o > 0; o >>= 1) r += __shfl_xor(r, o);
+    if (tid == 0) { sh.rest = r; sh.q = q; }
+  }
+  __syncthreads();
+  return q;
+}
+
+// R(i, l) in pivot order from the Cholesky storage (i <= l < K).
+__device__ __forceinline__ double chol_r(const double* S, const double* dk, const int* perm, int K, int i, int l) {
+  if (i == l) return dk[i];
+  const int a = perm[i], b = perm[l];
+  return S[min(a, b) + K * max(a, b)] / dk[i];
+}
+
+// DPP row permutations on doubles and sums over aligned lane groups of 4, 8 and 16 (quad
+// xor 1, quad xor 2, half-row mirror, row mirror); every lane of a group receives its sum.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+__device__ __forceinline__ double group_sum(double v, int lanes) {
+  v += dpp_f64<0xB1>(v);
+  v += dpp_f64<0x4E>(v);
+  if (lanes >= 8) v += dpp_f64<0x141>(v);
+  if (lanes >= 16) v += dpp_f64<0x140>(v);
+  return v;
+}
+// Largest power of two <= v, capped at 16 (lanes per group for the DPP sums; >= 4 here).
+__device__ __forceinline__ int lanes_for(int nt, int groups) {
+  int l = 16;
+  while (l > 4 && l * groups > nt) l >>= 1;
+  return l;
+}
+
+// Rank-revealing orthonormalisation factor: W (K x q, ld K) = P[:, :q] R^-1, so that V W has
+// orthonormal columns spanning V's numerically independent columns (G = V^T V); q to *J.q.
+// R is gathered into pivot order (through registers when it overwrites the LDS copy of S).
+// X = R^-1 column by column, 4 to 16 lanes per column: row i of column j needs
+// sum_{i<l<=j} R(i, l) X(l, j), which the lanes split by l mod (lanes) and add with DPP; each
+// lane keeps the X(l, j) of its own residue class, so no barrier is needed.
+template <bool SMEM, int NT>
+__global__ __launch_bounds__(NT) void k_pchol(const CholJob* jobs) {
   extern __shared__ double sm[];
+  constexpr int KMAX = ChGrid<NT>::KMAX, NW = NT / 64;
   const CholJob J = jobs[blockIdx.x];
   const int K = J.K;
   const int tid = threadIdx.x;
   if (K <= 0) { if (tid == 0 && J.q) *J.q = 0; return; }
-  double* S = SMEM ? sm : J.work;                 // K x K Schur complement / R (row k holds R[k][:])
-  double* red = SMEM ? sm + K * K : sm;           // EIG_NT values + EIG_NT indices
-  int* redi = reinterpret_cast<int*>(red + EIG_NT);
-  int* perm = redi + EIG_NT;                      // K
-  __shared__ double dmax0, piv, dk;
-  __shared__ int pidx, qfinal;
-  for (int e = tid; e < K * K; e += EIG_NT) S[e] = J.g[e];
-  for (int i = tid; i < K; i += EIG_NT) perm[i] = i;
+  double* S = SMEM ? sm : J.work;
+  double* Rp = SMEM ? sm : J.work + (size_t)K * K;  // R (q x q, ld K, upper) then X = R^-1 below it
+  double* base = SMEM ? sm + (size_t)K * K : sm;
+  double* dk = base;
+  double* xd = dk + K;
+  unsigned long long* slot = reinterpret_cast<unsigned long long*>(xd + K);  // 2 x NW keys
+  int* perm = reinterpret_cast<int*>(slot + 2 * NW);
+  __shared__ CholShared sh;
+  int* mark = reinterpret_cast<int*>(xd);  // free until the inverse
+  const int q = chol_phase<NT>(J.g, K, J.tol, S, dk, perm, slot, mark, sh);
+  if (SMEM) {
+    constexpr int GMAX = (KMAX * KMAX + NT - 1) / NT;
+    double reg[GMAX];
+#pragma unroll
+    for (int t = 0; t < GMAX; ++t) {
+      const int e = tid + t * NT;
+      double v = 0.0;
+      if (e < q * q) {
+        const int i = e % q, l = e / q;
+        if (i <= l) v = chol_r(S, dk, perm, K, i, l);
+      }
+      reg[t] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < GMAX; ++t) {
+      const int e = tid + t * NT;
+      if (e < q * q) Rp[e % q + K * (e / q)] = reg[t];
+    }
+  } else {
+    for (int e = tid; e < q * q; e += NT) {
+      const int i = e % q, l = e / q;
+      Rp[i + K * l] = i <= l ? chol_r(S, dk, perm, K, i, l) : 0.0;
+    }
+  }
   __syncthreads();
-  // largest initial diagonal
+  // X(i, j) = -(sum_{i<l<=j} R(i, l) X(l, j)) / R(i, i), bottom-up; X(l, j), l < j, at Rp[j + K l]
   {
-    double m = 0.0;
-    for (int i = tid; i < K; i += EIG_NT) m = fmax(m, S[i + K * i]);
-    red[tid] = m;
-    __syncthreads();
-    for (int w = EIG_NT / 2; w > 0; w >>= 1) { if (tid < w) red[tid] = fmax(red[tid], red[tid + w]); __syncthreads(); }
-    if (tid == 0) { dmax0 = red[0]; qfinal = K; }
-    __syncthreads();
-  }
-  for (int k = 0; k < K; ++k) {
-    // pivot: largest remaining diagonal (ties: lowest index)
-    double m = -1.0;
-    int mi = k;
-    for (int i = k + tid; i < K; i += EIG_NT) {
-      double v = S[i + K * i];
-      if (v > m) { m = v; mi = i; }
-    }
-    red[tid] = m;
-    redi[tid] = mi;
-    __syncthreads();
-    for (int w = EIG_NT / 2; w > 0; w >>= 1) {
-      if (tid < w) {
-        double a = red[tid], b = red[tid + w];
-        int ia = redi[tid], ib = redi[tid + w];
-        if (b > a || (b == a && ib < ia)) { red[tid] = b; redi[tid] = ib; }
+    const int lc = lanes_for(NT, q);
+    const int lg = lc == 16 ? 4 : (lc == 8 ? 3 : 2);
+    for (int j0 = 0; j0 < q; j0 += NT / lc) {
+      const int j = j0 + (tid >> lg), li = tid & (lc - 1);
+      if (j < q) {
+        const double xjj = 1.0 / Rp[j + K * j];
+        if (li == 0) xd[j] = xjj;
+        for (int i = j - 1; i >= 0; --i) {
+          // lane li takes the l = i+1 .. j with l = li (mod lc): exactly the X(l, j) it wrote
+          double part = 0.0;
+#pragma unroll 4
+          for (int l = i + 1 + ((li - i - 1) & (lc - 1)); l <= j; l += lc)
+            part += Rp[i + K * l] * (l == j ? xjj : Rp[j + K * l]);
+          const double acc = group_sum(part, lc);
+          if ((i & (lc - 1)) == li) Rp[j + K * i] = -acc / Rp[i + K * i];
+        }
       }
-      __syncthreads();
     }
-    if (tid == 0) { piv = red[0]; pidx = redi[0]; }
-    __syncthreads();
-    if (!(piv > J.tol * dmax0) || dmax0 <= 0.0) {
-      if (tid == 0) qfinal = k;
-      __syncthreads();
-      break;
-    }
-    const int p = pidx;
-    if (p != k) {
-      // symmetric swap of rows/columns k and p (full storage)
-      for (int i = tid; i < K; i += EIG_NT) {
-        double t = S[k + K * i]; S[k + K * i] = S[p + K * i]; S[p + K * i] = t;
-      }
-      __syncthreads();
-      for (int i = tid; i < K; i += EIG_NT) {
-        double t = S[i + K * k]; S[i + K * k] = S[i + K * p]; S[i + K * p] = t;
-      }
-      if (tid == 0) { int t = perm[k]; perm[k] = perm[p]; perm[p] = t; }
-      __syncthreads();
-    }
-    // d is read once and published before row k is overwritten (the thread that handles
-    // column k writes d into S[k][k])
-    if (tid == 0) dk = sqrt(S[k + K * k]);
-    __syncthreads();
-    const double d = dk;
-    // row k of R: R[k][j] = S[k][j] / d for j >= k (stored in S's row k)
-    for (int j = k + tid; j < K; j += EIG_NT) S[k + K * j] = (j == k) ? d : S[k + K * j] / d;
-    __syncthreads();
-    // trailing update S[i][j] -= R[k][i] R[k][j], i, j > k
-    const int rem = K - k - 1;
-    for (int e = tid; e < rem * rem; e += EIG_NT) {
-      int i = k + 1 + e % rem, j = k + 1 + e / rem;
-      S[i + K * j] -= S[k + K * i] * S[k + K * j];
-    }
-    __syncthreads();
   }
-  const int q = qfinal;
-  // X = R^-1 (upper triangular), row by row from the bottom:
-  // X[i][j] = (delta_ij - sum_{i<l<=j} R[i][l] X[l][j]) / R[i][i].
-  // X[i][j], j > i, is kept at S[j][i] (the free lower triangle), its diagonal in xd.
-  double* xd = reinterpret_cast<double*>(perm + K + (K & 1));
-  for (int i = q - 1; i >= 0; --i) {
-    const double rii = S[i + K * i];
-    for (int j = i + tid; j < q; j += EIG_NT) {
-      double acc = (j == i) ? 1.0 : 0.0;
-      for (int l = i + 1; l <= j; ++l) {
-        double xlj = (l == j) ? xd[l] : S[j + K * l];
-        acc -= S[i + K * l] * xlj;
-      }
-      if (j == i) xd[i] = acc / rii;
-      else S[j + K * i] = acc / rii;
-    }
-    __syncthreads();
-  }
-  // W = P[:, :q] X: row perm[i] of W is row i of X
-  for (int e = tid; e < K * q; e += EIG_NT) {
-    int r = e % K, j = e / K;
-    J.w[r + (long)K * j] = 0.0;
-  }
+  for (int e = tid; e < K * q; e += NT) J.w[e] = 0.0;
   __syncthreads();
-  for (int e = tid; e < q * q; e += EIG_NT) {
-    int i = e % q, j = e / q;
-    if (j >= i) J.w[perm[i] + (long)K * j] = (j == i) ? xd[i] : S[j + K * i];
+  for (int e = tid; e < q * q; e += NT) {
+    const int l = e % q, j = e / q;
+    if (l > j) continue;
+    J.w[perm[l] + (long)K * j] = (l == j) ? xd[l] : Rp[j + K * l];
   }
   if (tid == 0 && J.q) *J.q = q;
+}
+
+template <bool SMEM, int NT, typename Job>
+hipError_t launch_gram(void (*kern)(const Job*), const Job* jobs, int count, size_t shm, hipStream_t s) {
+  if (SMEM) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(kern, dim3(count), dim3(NT), shm, s, jobs);
+  return hipGetLastError();
 }
 
 hipError_t pchol_batched(const CholJob* jobs_dev, int count, int Kmax, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   if (Kmax > EIG_MAX) return hipErrorInvalidValue;
-  if (Kmax <= EIG_LDS_MAX) {
-    size_t shm = (size_t)Kmax * Kmax * 8 + EIG_NT * 12 + (size_t)Kmax * 12 + 64;
-    hipError_t e = hipFuncSetAttribute((const void*)k_pchol<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_pchol<true>, dim3(count), dim3(EIG_NT), shm, s, jobs_dev);
-  } else {
-    size_t shm = EIG_NT * 12 + (size_t)Kmax * 12 + 64;
-    hipLaunchKernelGGL(k_pchol<false>, dim3(count), dim3(EIG_NT), shm, s, jobs_dev);
+  const size_t extra = (size_t)Kmax * 16 + 32 * 8 + (size_t)Kmax * 4 + 64;
+  const size_t shm = (size_t)Kmax * Kmax * 8 + extra;
+  if (Kmax <= 64) return launch_gram<true, 256>(k_pchol<true, 256>, jobs_dev, count, shm, s);
+  if (Kmax <= EIG_LDS_MAX) return launch_gram<true, 512>(k_pchol<true, 512>, jobs_dev, count, shm, s);
+  return launch_gram<false, 1024>(k_pchol<false, 1024>, jobs_dev, count, extra, s);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Eigenpairs of a positive semidefinite Gram matrix G (K x K) by the preconditioned one-sided
+// Jacobi method: pivoted Cholesky G[P,P] = R^T R, then Jacobi rotations orthogonalise the
+// columns of X = R^T (K x q).  At convergence X = V Sigma with V the eigenvectors of G[P,P]
+// and Sigma^2 its eigenvalues, so no rotation needs to be accumulated.  One barrier per
+// Jacobi step: the column pairs of a step are disjoint, the 4 to 16 lanes that share a pair
+// hold its rows in registers and add their partial dot products with DPP.
+// ---------------------------------------------------------------------------------------------
+template <bool SMEM, int NT>
+__global__ __launch_bounds__(NT) void k_psd_eig(const PsdJob* jobs) {
+  extern __shared__ double sm[];
+  constexpr int KMAX = ChGrid<NT>::KMAX, NW = NT / 64;
+  const PsdJob J = jobs[blockIdx.x];
+  const int K = J.K;
+  const int tid = threadIdx.x;
+  if (K <= 0) {
+    if (tid == 0) { *J.q = 0; *J.rest = 0.0; }
+    return;
   }
-  return hipGetLastError();
+  double* S = SMEM ? sm : J.work;
+  double* X = SMEM ? sm : J.work + (size_t)K * K;      // K x q, ld K
+  double* base = SMEM ? sm + (size_t)K * K : sm;
+  double* dk = base;                                   // K pivots; later column norms^2
+  unsigned long long* slot = reinterpret_cast<unsigned long long*>(dk + K);  // 2 x NW keys
+  int* perm = reinterpret_cast<int*>(slot + 2 * NW);   // K
+  int* rank = perm + K;                                // K: output position of each column
+  __shared__ CholShared sh;
+  __shared__ int changed[3];
+  if (tid == 0) changed[0] = changed[1] = changed[2] = 0;
+  const int q = chol_phase<NT>(J.g, K, J.ctol, S, dk, perm, slot, rank, sh);
+  // X = R^T in pivot order: X[l][k] = R(k, l) (l >= k), 0 above the diagonal
+  if (SMEM) {
+    constexpr int GMAX = (KMAX * KMAX + NT - 1) / NT;
+    double reg[GMAX];
+#pragma unroll
+    for (int t = 0; t < GMAX; ++t) {
+      const int e = tid + t * NT;
+      double v = 0.0;
+      if (e < K * q) {
+        const int l = e % K, k = e / K;
+        if (l >= k) v = chol_r(S, dk, perm, K, k, l);
+      }
+      reg[t] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < GMAX; ++t) {
+      const int e = tid + t * NT;
+      if (e < K * q) X[e] = reg[t];
+    }
+  } else {
+    for (int e = tid; e < K * q; e += NT) {
+      const int l = e % K, k = e / K;
+      X[e] = l >= k ? chol_r(S, dk, perm, K, k, l) : 0.0;
+    }
+  }
+  __syncthreads();
+  // one-sided Jacobi on the q columns of X (round-robin pairs, L lanes per pair)
+  const int qp = q + (q & 1), np = qp / 2;
+  const int L = lanes_for(NT, np);
+  const int lg = L == 16 ? 4 : (L == 8 ? 3 : 2);
+  const int pr = tid >> lg, li = tid & (L - 1);
+  constexpr int RMAX = SMEM ? (KMAX * KMAX + 2 * NT - 1) / (2 * NT) : 1;  // rows per lane in registers
+  for (int sweep = 0; sweep < 40 && q > 1; ++sweep) {
+    int* chg = &changed[sweep % 3];
+    if (tid == 0) changed[(sweep + 1) % 3] = 0;  // last read two sweeps ago
+    for (int st = 0; st < qp - 1; ++st) {
+      int p = 0, r = 0;
+      bool valid = pr < np;
+      if (valid) {
+        p = rr_index(pr, st, qp);
+        r = rr_index(qp - 1 - pr, st, qp);
+        if (p > r) { const int t = p; p = r; r = t; }
+        valid = r < q;
+      }
+      double al = 0.0, be = 0.0, ga = 0.0;
+      double xa[RMAX], xb[RMAX];
+      if (SMEM) {
+#pragma unroll
+        for (int t = 0; t < RMAX; ++t) {
+          const int i = li + L * t;
+          const bool in = valid && i < K;
+          xa[t] = in ? X[i + K * p] : 0.0;
+          xb[t] = in ? X[i + K * r] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < RMAX; ++t) { al += xa[t] * xa[t]; be += xb[t] * xb[t]; ga += xa[t] * xb[t]; }
+      } else if (valid) {
+        for (int i = li; i < K; i += L) {
+          const double a = X[i + K * p], b = X[i + K * r];
+          al += a * a; be += b * b; ga += a * b;
+        }
+      }
+      al = group_sum(al, L);
+      be = group_sum(be, L);
+      ga = group_sum(ga, L);
+      if (valid && ga != 0.0 && fabs(ga) > J.jtol * sqrt(al * be)) {
+        const double zeta = (be - al) / (2.0 * ga);
+        const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+        if (SMEM) {
+#pragma unroll
+          for (int u = 0; u < RMAX; ++u) {
+            const int i = li + L * u;
+            if (i < K) {
+              X[i + K * p] = c * xa[u] - sn * xb[u];
+              X[i + K * r] = sn * xa[u] + c * xb[u];
+            }
+          }
+        } else {
+          for (int i = li; i < K; i += L) {
+            const double a = X[i + K * p], b = X[i + K * r];
+            X[i + K * p] = c * a - sn * b;
+            X[i + K * r] = sn * a + c * b;
+          }
+        }
+        if (li == 0) *chg = 1;
+      }
+      __syncthreads();
+    }
+    if (!*chg) break;  // read by every thread after the sweep's last barrier
+  }
+  __syncthreads();
+  // eigenvalues = squared column norms (16 lanes per column), sorted descending;
+  // eigenvectors = normalised columns
+  for (int c0 = 0; c0 < q; c0 += NT / 16) {
+    const int i = c0 + (tid >> 4), l0 = tid & 15;
+    double s2 = 0.0;
+    if (i < q)
+      for (int l = l0; l < K; l += 16) s2 += X[l + K * i] * X[l + K * i];
+    s2 = group_sum(s2, 16);
+    if (i < q && l0 == 0) dk[i] = s2;
+  }
+  __syncthreads();
+  for (int i = tid; i < q; i += NT) {
+    const double di = dk[i];
+    int rk = 0;
+    for (int j = 0; j < q; ++j) {
+      const double dj = dk[j];
+      if (dj > di || (dj == di && j < i)) ++rk;
+    }
+    rank[i] = rk;
+  }
+  for (int i = tid; i < K; i += NT) J.w[i] = 0.0;
+  __syncthreads();
+  for (int e = tid; e < K * K; e += NT) {
+    const int l = e % K, i = e / K;
+    if (i >= q) { J.v[e] = 0.0; continue; }
+    const double nrm = sqrt(dk[i]);
+    J.v[perm[l] + (long)K * rank[i]] = nrm > 0.0 ? X[l + K * i] / nrm : 0.0;
+  }
+  for (int i = tid; i < q; i += NT) J.w[rank[i]] = dk[i];
+  if (tid == 0) { *J.q = q; *J.rest = sh.rest; }
+}
+
+hipError_t psd_eig_batched(const PsdJob* jobs_dev, int count, int Kmax, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (Kmax > EIG_MAX) return hipErrorInvalidValue;
+  const size_t extra = (size_t)Kmax * 8 + 32 * 8 + (size_t)Kmax * 8 + 64;
+  const size_t shm = (size_t)Kmax * Kmax * 8 + extra;
+  if (Kmax <= 64) return launch_gram<true, 256>(k_psd_eig<true, 256>, jobs_dev, count, shm, s);
+  if (Kmax <= EIG_LDS_MAX) return launch_gram<true, 512>(k_psd_eig<true, 512>, jobs_dev, count, shm, s);
+  return launch_gram<false, 1024>(k_psd_eig<false, 1024>, jobs_dev, count, extra, s);
 }
 
 hipError_t syev_batched(const EigJob* jobs_dev, int count, int Kmax, hipStream_t s) {
@@ -963,12 +1304,25 @@ hipError_t eig_inv_sqrt(const double* E, const double* w, int K, int q, double* 
   return hipGetLastError();
 }
 
+// <a, b> accumulated in double: up to 256 workgroups write partial sums to `part`, a
+// single workgroup adds them (fixed order, so the result does not depend on timing).
 template <typename T>
-__global__ __launch_bounds__(256) void k_dot(const T* a, const T* b, long count, double* out) {
+__global__ __launch_bounds__(256) void k_dot(const T* a, const T* b, long count, double* part) {
   __shared__ double red[256];
   double acc = 0.0;
-  for (long i = threadIdx.x; i < count; i += 256) acc += (double)a[i] * (double)b[i];
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < count; i += (long)gridDim.x * 256)
+    acc += (double)a[i] * (double)b[i];
   red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+__global__ __launch_bounds__(256) void k_sum(const double* part, int cnt, double* out) {
+  __shared__ double red[256];
+  red[threadIdx.x] = (int)threadIdx.x < cnt ? part[threadIdx.x] : 0.0;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
@@ -977,12 +1331,18 @@ __global__ __launch_bounds__(256) void k_dot(const T* a, const T* b, long count,
   if (threadIdx.x == 0) out[0] = red[0];
 }
 template <typename T>
-hipError_t dot(const T* a, const T* b, long count, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_dot<T>, dim3(1), dim3(256), 0, s, a, b, count, out);
+hipError_t dot(const T* a, const T* b, long count, double* out, double* part, hipStream_t s) {
+  int nb = (int)std::min<long>(256, std::max<long>(1, (count + 2047) / 2048));
+  if (nb == 1) {
+    hipLaunchKernelGGL(k_dot<T>, dim3(1), dim3(256), 0, s, a, b, count, out);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_dot<T>, dim3(nb), dim3(256), 0, s, a, b, count, part);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, (const double*)part, nb, out);
   return hipGetLastError();
 }
-template hipError_t dot<double>(const double*, const double*, long, double*, hipStream_t);
-template hipError_t dot<float>(const float*, const float*, long, double*, hipStream_t);
+template hipError_t dot<double>(const double*, const double*, long, double*, double*, hipStream_t);
+template hipError_t dot<float>(const float*, const float*, long, double*, double*, hipStream_t);
 
 __global__ void k_khatri_rao(const double* X2, int q2, const double* X3, int q3, int R, double* out) {
   long e = (long)blockIdx.x * blockDim.x + threadIdx.x;

@@ -45,6 +45,9 @@ hipError_t dst1(int N, int cols, const T* in, int ldin, T* out, int ldout, const
 template <typename T>
 hipError_t dst_table(int N, T* tab, hipStream_t s);
 
+// Gram and eigen problems up to this size are kept in LDS; larger ones (up to 256) use global scratch.
+constexpr int kGramLds = 128;
+
 // Batched symmetric Jacobi eigensolver, FP64.  Matrix b: K[b] x K[b] at a[b] (ld K[b]);
 // eigenvalues (descending) to w[b], eigenvectors to v[b] (ld K[b]).
 // Matrices larger than 128 need `work` (Kp x Kp doubles, Kp = K rounded up to even) in global memory.
@@ -53,9 +56,18 @@ struct EigJob { int K; const double* a; double* w; double* v; double* work; doub
 hipError_t syev_batched(const EigJob* jobs_dev, int count, int Kmax, hipStream_t s);
 
 // Batched rank-revealing pivoted Cholesky of Gram matrices: W = P R^-1 (K x q, ld K), q to *q.
-// Matrices larger than 128 need `work` (K x K doubles) in global memory.
+// Matrices larger than 128 need `work` (2 K^2 doubles) in global memory.
 struct CholJob { int K; double tol; const double* g; double* w; int* q; double* work; };
 hipError_t pchol_batched(const CholJob* jobs_dev, int count, int Kmax, hipStream_t s);
+
+// Batched eigendecomposition of positive semidefinite Gram matrices (pivoted Cholesky, then
+// one-sided Jacobi on R^T).  Per job: eigenvalues descending to w (K entries, zero past the
+// numerical rank q), eigenvectors to v (K x K, ld K, zero columns past q), q to *q and the
+// trace left in the Schur complement when the Cholesky stopped to *rest.  Cholesky stops at
+// pivots <= ctol * max diag(G); a column pair is rotated while |x_p.x_r| > jtol |x_p||x_r|.
+// Matrices larger than 128 need `work` (2 K^2 doubles) in global memory.
+struct PsdJob { int K; const double* g; double* w; double* v; int* q; double* rest; double* work; double ctol; double jtol; };
+hipError_t psd_eig_batched(const PsdJob* jobs_dev, int count, int Kmax, hipStream_t s);
 
 // Elementwise helpers.
 template <typename TI, typename TO>
@@ -70,9 +82,9 @@ hipError_t permute3(const T* in, int d0, int d1, int d2, T* out, int p0, int p1,
 hipError_t scale_cols_d(double* a, int rows, int cols, int ld, const double* scale, hipStream_t s);
 // W = E[:, 0:q] * diag(1/sqrt(w)) for the leading q eigenpairs; K rows, ld K.
 hipError_t eig_inv_sqrt(const double* E, const double* w, int K, int q, double* W, hipStream_t s);
-// out = sum(a[i]*b[i]) in FP64 (single value, written to out[0]).
+// out[0] = sum(a[i]*b[i]) in FP64; part: device scratch of 256 doubles for per-workgroup sums.
 template <typename T>
-hipError_t dot(const T* a, const T* b, long count, double* out, hipStream_t s);
+hipError_t dot(const T* a, const T* b, long count, double* out, double* part, hipStream_t s);
 // Face-split dense materialisation: out[(b,c), k] = X2[b,k] * X3[c,k] (q2*q3 x R), used for CP cores.
 hipError_t khatri_rao_d(const double* X2, int q2, const double* X3, int q3, int R, double* out, hipStream_t s);
 // t[i, col] = sum_j T1[i + rm*(j + ro*col)] * A[j + ro*col]
