@@ -89,7 +89,8 @@ _SIGS = {
                          C.POINTER(C.c_double)], C.c_int),
 }
 
-PROF_CLASSES = ["gemm_f64", "gemm_f32", "gemm_f32_f64", "gemm_f64_f32", "dst_f64", "dst_f32", "syev", "chol"]
+PROF_CLASSES = ["gemm_f64", "gemm_f32", "gemm_f32_f64", "gemm_f64_f32", "dst_f64", "dst_f32", "syev", "chol",
+                "gram_eig"]
 
 
 def load_library():

@@ -125,7 +125,7 @@ struct WsScope {
 // ------------------------------------------------------------------------------ profiling
 // Kernel classes reported by tp_profile_read.
 enum { PC_GEMM_F64 = 0, PC_GEMM_F32 = 1, PC_GEMM_F32_F64 = 2, PC_GEMM_F64_F32 = 3, PC_DST_F64 = 4, PC_DST_F32 = 5,
-       PC_SYEV = 6, PC_CHOL = 7, PC_COUNT = 8 };
+       PC_SYEV = 6, PC_CHOL = 7, PC_GRAM_EIG = 8, PC_COUNT = 9 };
 
 tp_status prof_begin(tp_ctx* c, size_t* e0) {
   if (!c->prof) return TP_OK;
@@ -388,10 +388,11 @@ tp_status psd_eig(tp_ctx* c, int cnt, const int* K, const double* const* G, doub
   TPCHK(prof_begin(c, &e0));
   HIPCHK(psd_eig_batched(c->pjobs, cnt, Kmax, c->stream));
   {
-    // algorithmic work: Cholesky K^3/3 plus about 4 sweeps of 3 K^3 (one-sided Jacobi)
+    // algorithmic work: that of a symmetric eigendecomposition with vectors, about 9 K^3 flops
+    // (tridiagonal reduction, implicit QR, back transformation); bytes: G in, V and w out
     double fl = 0, by = 0;
-    for (int i = 0; i < cnt; ++i) { fl += 12.5 * K[i] * K[i] * K[i]; by += 8.0 * (2.0 * K[i] * K[i] + K[i]); }
-    TPCHK(prof_end(c, PC_SYEV, e0, fl, by));
+    for (int i = 0; i < cnt; ++i) { fl += 9.0 * K[i] * K[i] * K[i]; by += 8.0 * (2.0 * K[i] * K[i] + K[i]); }
+    TPCHK(prof_end(c, PC_GRAM_EIG, e0, fl, by));
   }
   size_t off = 0;
   for (int i = 0; i < cnt; ++i) {
