@@ -234,9 +234,10 @@ typedef struct {
  * ||Z|| <= tau ||X||, P = trunc(Z + beta P).  Iterates are Tucker tensors (the mixed Tucker-canonical route of
  * Sec. 5); every update is truncated as in Algorithm alg:pcg.  x->prec selects
  * the arithmetic; op and pre must have been built with that precision.
- * Without convergence (kmax reached, or the estimate grown 8-fold over its minimum, the
- * rounding floor of the working precision) the call returns TP_ENOCONV and x holds the
- * iterate with the smallest estimate; TP_ERANK: converged but some truncation hit the cap. */
+ * Without convergence (kmax reached, or the estimate grown 8-fold over its minimum or not
+ * improved for 5 steps: the floor set by the working precision or by the rank cap) the call
+ * returns TP_ENOCONV and x holds the iterate with the smallest estimate; TP_ERANK: converged
+ * but some truncation hit the cap. */
 tp_status tp_pcg_solve(tp_ctx* ctx, const tp_symbol* op, const tp_symbol* pre,
                        const tp_cp* b, tp_tensor* x, const tp_pcg_opts* opts,
                        const tp_sketch* sketch, tp_pcg_info* info);

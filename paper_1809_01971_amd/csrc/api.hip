@@ -205,9 +205,18 @@ tp_status dst_cols(tp_ctx* c, int n, int cols, const T* in, T* out) {
   if (cols <= 0) return TP_OK;
   const T* tab = nullptr;
   TPCHK(get_table<T>(c, n + 1, &tab));
+  const double* tab64 = nullptr;
+  TPCHK(get_table<double>(c, n + 1, &tab64));
+  WsScope scope(c);
+  void* work = nullptr;
+  if (n + 1 > 16384) {
+    double* w = nullptr;
+    TPCHK(wsalloc(c, (size_t)cols * (n + 1), &w));  // cols * (N/2) complex doubles
+    work = w;
+  }
   size_t e0 = 0;
   TPCHK(prof_begin(c, &e0));
-  HIPCHK(dst1<T>(n + 1, cols, in, n, out, n, tab, c->stream));
+  HIPCHK(dst1<T>(n + 1, cols, in, n, out, n, tab, tab64, work, c->stream));
   // algorithmic work of a real FFT-based DST: ~2.5 N log2(2N) flops per column; bytes: in + out
   double lg = std::log2(2.0 * (n + 1));
   TPCHK(prof_end(c, std::is_same<T, double>::value ? PC_DST_F64 : PC_DST_F32, e0, 2.5 * (n + 1) * lg * cols,
@@ -1745,6 +1754,7 @@ tp_status pcg_impl(tp_ctx* c, const tp_symbol* op, const tp_symbol* pre, const t
   TPCHK(inner_impl<T>(c, &R, &Z, &rz));
   bool converged = false, stalled = false;
   double best = HUGE_VAL;  // smallest error estimate so far; its iterate is kept in Xb
+  int kbest = 0;
   int k = 0;
   for (; k < o->kmax; ++k) {
     // S = fun(P) stays in exact factored form (canonical symbol times P): <P,S> is computed
@@ -1784,12 +1794,14 @@ tp_status pcg_impl(tp_ctx* c, const tp_symbol* op, const tp_symbol* pre, const t
     info->err_est = std::sqrt(std::max(zz, 0.0) / std::max(xx, 1e-300));
     if (info->err_est <= o->tau) { converged = true; ++k; break; }
     // Safeguard (not part of the method): once the truncated iteration has reached the floor
-    // set by the working precision, further steps only amplify rounding noise.  The iterate
-    // with the smallest estimate is kept, and the loop stops when the estimate has grown 8-fold.
+    // set by the working precision or by the rank cap, further steps only amplify rounding
+    // noise or repeat the truncation error.  The iterate with the smallest estimate is kept, and
+    // the loop stops when the estimate has grown 8-fold or has not improved for 5 steps.
     if (info->err_est < best) {
       best = info->err_est;
+      kbest = k;
       TPCHK(copy_tensor<T>(c, &X, &Xb));
-    } else if (info->err_est > 8.0 * best) {
+    } else if (info->err_est > 8.0 * best || k - kbest >= 5) {
       stalled = true;
       ++k;
       break;
@@ -1823,8 +1835,8 @@ tp_status pcg_impl(tp_ctx* c, const tp_symbol* op, const tp_symbol* pre, const t
   if (!converged) {
     info->status = TP_ENOCONV;
     if (stalled)
-      return fail(TP_ENOCONV, "PCG stalled at error estimate %g > tau=%g after %d iterations (precision floor); "
-                  "x holds the best iterate", info->err_est, o->tau, k);
+      return fail(TP_ENOCONV, "PCG stalled at error estimate %g > tau=%g after %d iterations (precision or rank-cap "
+                  "floor); x holds the best iterate", info->err_est, o->tau, k);
     return fail(TP_ENOCONV, "PCG did not reach tau=%g in %d iterations (error estimate %g); x holds the best iterate",
                 o->tau, o->kmax, info->err_est);
   }

@@ -366,22 +366,27 @@ hipError_t dst_table(int N, T* tab, hipStream_t s) {
 template hipError_t dst_table<double>(int, double*, hipStream_t);
 template hipError_t dst_table<float>(int, float*, hipStream_t);
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_dst1(int N, int logL, int cols, int cpw, const T* in,
-                                              int ldin, T* out, int ldout,
-                                              const T* __restrict__ tab, T scale) {
+// TI: storage type of the columns; T: arithmetic type of the transform (T = double for FP32
+// columns where the FP64 work array fits in LDS, see dst1).
+// GLOBAL: the work array lives in `work` (one slice of cpw * N/2 complex values per workgroup,
+// L2 resident) instead of LDS; the barriers order those global accesses within the workgroup.
+template <typename TI, typename T, bool GLOBAL>
+__global__ __launch_bounds__(256) void k_dst1(int N, int logL, int cols, int cpw, const TI* in,
+                                              int ldin, TI* out, int ldout,
+                                              const T* __restrict__ tab, T scale, C2<T>* work) {
   extern __shared__ char smem_raw[];
-  C2<T>* X = reinterpret_cast<C2<T>*>(smem_raw);
   const int L = N >> 1;
   const int tot = cpw * L;
-  T* partial = reinterpret_cast<T*>(X + tot);  // 256 chunk totals
+  C2<T>* X = GLOBAL ? work + (long)blockIdx.x * tot : reinterpret_cast<C2<T>*>(smem_raw);
+  double* partial = GLOBAL ? reinterpret_cast<double*>(smem_raw)
+                           : reinterpret_cast<double*>(reinterpret_cast<C2<T>*>(smem_raw) + tot);  // 256 chunk totals
   const int tid = threadIdx.x;
   const int col0 = blockIdx.x * cpw;
 
   auto xval = [&](int c, int j) -> T {  // x_j, 1-based, zero outside 1..N-1
     int col = col0 + c;
     if (j <= 0 || j >= N || col >= cols) return (T)0;
-    return in[(j - 1) + (long)ldin * col];
+    return (T)in[(j - 1) + (long)ldin * col];
   };
   // pre-processing and bit-reversed load
   for (int e = tid; e < tot; e += 256) {
@@ -445,12 +450,15 @@ __global__ __launch_bounds__(256) void k_dst1(int N, int logL, int cols, int cpw
     }
   }
   __syncthreads();
-  // segmented inclusive scan of X[].re per column (odd outputs)
+  // segmented inclusive scan of X[].re per column (odd outputs).  The running sum is kept in
+  // double and each output is rounded once: in FP32 a running sum rounded at every step
+  // carries the rounding of its largest partial sums into every later output (a random walk of
+  // eps * max|y| over up to N/2 steps, 4e-4 relative at N = 32768 for a single high mode).
   const int chunk = tot / 256;  // >= 1, divides L
   {
     int beg = tid * chunk;
-    T run = 0;
-    for (int i = 0; i < chunk; ++i) { run += X[beg + i].re; X[beg + i].re = run; }
+    double run = 0.0;
+    for (int i = 0; i < chunk; ++i) run += (double)X[beg + i].re;
     partial[tid] = run;
   }
   __syncthreads();
@@ -458,39 +466,63 @@ __global__ __launch_bounds__(256) void k_dst1(int N, int logL, int cols, int cpw
     int beg = tid * chunk;
     int cstart = (beg / L) * L;  // first element of this column
     int t0 = cstart / chunk;
-    T off = 0;
-    for (int t = t0; t < tid; ++t) off += partial[t];
-    for (int i = 0; i < chunk; ++i) X[beg + i].re += off;
+    double run = 0.0;
+    for (int t = t0; t < tid; ++t) run += partial[t];
+    for (int i = 0; i < chunk; ++i) { run += (double)X[beg + i].re; X[beg + i].re = (T)run; }
   }
   __syncthreads();
   for (int e = tid; e < tot; e += 256) {
     int c = e / L, k = e - c * L;
     int col = col0 + c;
     if (col >= cols) continue;
-    out[2 * k + (long)ldout * col] = scale * X[e].re;              // y_{2k+1}
-    if (k >= 1) out[2 * k - 1 + (long)ldout * col] = scale * X[e].im;  // y_{2k}
+    out[2 * k + (long)ldout * col] = (TI)(scale * X[e].re);              // y_{2k+1}
+    if (k >= 1) out[2 * k - 1 + (long)ldout * col] = (TI)(scale * X[e].im);  // y_{2k}
   }
 }
 
-template <typename T>
-hipError_t dst1(int N, int cols, const T* in, int ldin, T* out, int ldout, const T* tab, hipStream_t s) {
-  if (cols <= 0) return hipSuccess;
+template <typename TI, typename T>
+hipError_t dst1_launch(int N, int cols, const TI* in, int ldin, TI* out, int ldout, const T* tab, void* work,
+                       hipStream_t s) {
   int L = N / 2;
   int logL = 0;
   while ((1 << logL) < L) ++logL;
   int cpw = L >= 256 ? 1 : 256 / L;
-  size_t shm = (size_t)cpw * L * sizeof(C2<T>) + 256 * sizeof(T);
-  if (shm > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_dst1<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    if (e != hipSuccess) return e;
-  }
   T scale = (T)sqrt(2.0 / (double)N);
   int blocks = (cols + cpw - 1) / cpw;
-  hipLaunchKernelGGL(k_dst1<T>, dim3(blocks), dim3(256), shm, s, N, logL, cols, cpw, in, ldin, out, ldout, tab, scale);
+  if (work) {
+    hipLaunchKernelGGL((k_dst1<TI, T, true>), dim3(blocks), dim3(256), 256 * sizeof(double), s, N, logL, cols, cpw,
+                       in, ldin, out, ldout, tab, scale, reinterpret_cast<C2<T>*>(work));
+    return hipGetLastError();
+  }
+  size_t shm = (size_t)cpw * L * sizeof(C2<T>) + 256 * sizeof(double);
+  if (shm > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_dst1<TI, T, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)shm);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_dst1<TI, T, false>), dim3(blocks), dim3(256), shm, s, N, logL, cols, cpw, in, ldin, out, ldout,
+                     tab, scale, (C2<T>*)nullptr);
   return hipGetLastError();
 }
-template hipError_t dst1<double>(int, int, const double*, int, double*, int, const double*, hipStream_t);
-template hipError_t dst1<float>(int, int, const float*, int, float*, int, const float*, hipStream_t);
+
+// FP32 columns are transformed in FP64 arithmetic.  The pre-processing adds the small
+// sin(pi j/N)-weighted symmetric part of x to its antisymmetric part, so in FP32 arithmetic the
+// transform of a vector whose spectrum sits at either end (the smooth factors of the iterates)
+// loses about eps N / pi relative accuracy (measured: 5e-5 for the inverse of the first mode at
+// N = 8192, 7e-5 at N = 32768); the FP64 work array removes it.  It fits in LDS up to N = 16384;
+// at N = 32768 it lives in `work` (cols * N/2 complex doubles, global).
+template <typename T>
+hipError_t dst1(int N, int cols, const T* in, int ldin, T* out, int ldout, const T* tab, const double* tab64,
+                void* work, hipStream_t s) {
+  if (cols <= 0) return hipSuccess;
+  if (std::is_same<T, float>::value && tab64 && (N <= 16384 || work))
+    return dst1_launch<T, double>(N, cols, in, ldin, out, ldout, tab64, N <= 16384 ? nullptr : work, s);
+  return dst1_launch<T, T>(N, cols, in, ldin, out, ldout, tab, N <= 16384 ? nullptr : work, s);
+}
+template hipError_t dst1<double>(int, int, const double*, int, double*, int, const double*, const double*, void*,
+                                 hipStream_t);
+template hipError_t dst1<float>(int, int, const float*, int, float*, int, const float*, const double*, void*,
+                                hipStream_t);
 
 // ---------------------------------------------------------------------------------------------
 // Cyclic Jacobi eigensolver (FP64), round-robin parallel ordering, A in LDS, V in global.

@@ -38,9 +38,12 @@ bool gemm_use_mfma();
 void gemm_set_mfma(int on);
 
 // Orthonormal DST-I on `cols` columns of length n = N-1 (N a power of two).
-// tab holds cos(pi m/N), sin(pi m/N), m = 0..N-1, interleaved.
+// tab holds cos(pi m/N), sin(pi m/N), m = 0..N-1, interleaved (tab64 the same in double; FP32
+// columns are transformed in FP64 arithmetic with it).  N > 16384 needs `work`: cols * N/2
+// complex values of the arithmetic type (16 bytes each for FP32 columns) in global memory.
 template <typename T>
-hipError_t dst1(int N, int cols, const T* in, int ldin, T* out, int ldout, const T* tab, hipStream_t s);
+hipError_t dst1(int N, int cols, const T* in, int ldin, T* out, int ldout, const T* tab, const double* tab64,
+                void* work, hipStream_t s);
 
 template <typename T>
 hipError_t dst_table(int N, T* tab, hipStream_t s);

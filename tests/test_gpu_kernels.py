@@ -34,9 +34,10 @@ def test_dst_matches_definition(ctx, n, cols, prec):
     xt = torch.as_tensor(x, dtype=dt, device="cuda")
     got = ctx.dst(xt).double().cpu().numpy()
     ref = spectral.dst(x.astype(np.float32).astype(np.float64) if prec else x)
-    # the odd outputs come from a running sum over n/2 terms: rounding grows with n
+    # FP64: rounding grows like eps log2(N); FP32 columns are transformed in FP64 arithmetic, so
+    # only their rounding to FP32 remains
     lg = np.log2(n + 1)
-    tol = 4e-14 * lg if prec == 0 else 3e-7 * lg
+    tol = 4e-14 * lg if prec == 0 else 3e-7
     assert rel(got, ref) < tol
     # F is an involution
     back = ctx.dst(torch.as_tensor(got, dtype=dt, device="cuda")).double().cpu().numpy()
@@ -51,7 +52,28 @@ def test_dst_large_fp32(ctx):
     got = ctx.dst(torch.as_tensor(x, dtype=torch.float32, device="cuda")).double().cpu().numpy()
     import scipy.fft as sfft
     ref = sfft.dst(x.astype(np.float32).astype(np.float64), type=1, norm="ortho", axis=0)
-    assert rel(got, ref) < 1e-5
+    log("  rel %.2e" % rel(got, ref))
+    assert rel(got, ref) < 3e-7
+
+
+@pytest.mark.parametrize("n,k", [(2047, 1), (2047, 190), (8191, 1), (16383, 1500), (16383, 16383), (32767, 1),
+                                 (32767, 3000), (32767, 30000), (32767, 32767)])
+def test_dst_single_mode_fp32(ctx, n, k):
+    """A single sine mode maps to one spike and back (F is orthonormal and its own inverse).  Modes at
+    either end of the spectrum are the ill-conditioned case of the FFT-based DST-I: its
+    pre-processing adds a sin(pi j/N)-weighted symmetric part to an antisymmetric one, which FP32
+    arithmetic resolves only to about eps N / pi (7e-5 for the first mode at N = 32768).  FP32 columns
+    are therefore transformed in FP64 arithmetic, and only the rounding of input and output to FP32
+    remains."""
+    import torch
+    x = np.sin(k * np.pi * np.arange(1, n + 1) / (n + 1.0))[:, None]
+    got = ctx.dst(torch.as_tensor(x, dtype=torch.float32, device="cuda")).double().cpu().numpy()
+    ref = spectral.dst(x.astype(np.float32).astype(np.float64))
+    e1 = rel(got, ref)
+    back = ctx.dst(torch.as_tensor(got, dtype=torch.float32, device="cuda")).double().cpu().numpy()
+    e2 = rel(back, x)
+    log("dst single mode n=%d k=%d fp32: %.2e, round trip %.2e" % (n, k, e1, e2))
+    assert e1 < 3e-7 and e2 < 6e-7
 
 
 @pytest.mark.parametrize("K", [1, 2, 17, 64, 100, 128, 129, 200, 256])
