@@ -61,17 +61,10 @@ struct tp_ctx {
   char* ws = nullptr;
   size_t ws_size = 0, ws_top = 0;
   double* host = nullptr;        // pinned host scratch (kHost doubles)
-  EigJob* jobs = nullptr;        // device eig job descriptors
-  EigJob* jobs_host = nullptr;   // pinned staging
-  PsdJob* pjobs = nullptr;       // device Gram eigensolver job descriptors
-  PsdJob* pjobs_host = nullptr;  // pinned staging
-  CholJob* cjobs = nullptr;      // device Cholesky job descriptors
-  CholJob* cjobs_host = nullptr; // pinned staging
-  int* qdev = nullptr;           // device ranks written by the Cholesky kernel
-  int* qhost = nullptr;          // pinned copy
+  double* hmap = nullptr;        // mapped, coherent pinned host memory (kMap doubles) that small
+  double* dmap = nullptr;        //   kernel results (ranks, eigenvalues, inner products) go to; its device address
   std::map<int, double*> tab64;
   std::map<int, float*> tab32;
-  bool jobs_pending = false;     // jobs_host may still be read by an enqueued copy
   std::map<int, double*> ones64;  // all-ones columns (identity symbol), per grid size
   std::map<int, float*> ones32;
   double* unit_w = nullptr;
@@ -83,6 +76,7 @@ struct tp_ctx {
   std::vector<Rec> recs;
   double prof_ms[16] = {0}, prof_n[16] = {0}, prof_flops[16] = {0}, prof_bytes[16] = {0};
   static constexpr size_t kHost = 1 << 16;
+  static constexpr size_t kMap = 4096;
   static constexpr int kJobs = 64;
 };
 
@@ -289,47 +283,48 @@ tp_status mm(tp_ctx* c, bool tA, bool tB, int M, int N, int K, double alpha, con
 }
 
 // ------------------------------------------------------------------------------ eigen
-// Diagonalise `cnt` symmetric matrices (device, double), returning eigenvalues on the host.
+// Diagonalise `cnt` symmetric matrices (device, double), eigenvalues to W (device) and, when
+// host_w is given, also to the host.  Job descriptors travel in the kernel arguments.
 tp_status eig(tp_ctx* c, int cnt, const int* K, const double* const* A, double* const* W, double* const* V,
               std::vector<std::vector<double>>* host_w, double tol = 0.0) {
-  if (cnt > tp_ctx::kJobs) return fail(TP_EINVAL, "too many eigen jobs");
-  if (c->jobs_pending) {
-    HIPCHK(hipStreamSynchronize(c->stream));
-    c->jobs_pending = false;
-  }
   int Kmax = 0;
-  for (int i = 0; i < cnt; ++i) Kmax = std::max(Kmax, K[i]);
-  double* work = nullptr;
-  if (Kmax > 128) {
-    int Kp = (Kmax + 1) & ~1;
-    TPCHK(wsalloc(c, (size_t)Kp * Kp * cnt, &work));  // released with the caller's scope
-  }
   for (int i = 0; i < cnt; ++i) {
     if (K[i] > kMaxRank) return fail(TP_ERANK, "Gram matrix of size %d exceeds the eigensolver limit %d", K[i], kMaxRank);
-    int Kp = (Kmax + 1) & ~1;
-    c->jobs_host[i] = EigJob{K[i], A[i], W[i], V[i], work ? work + (size_t)Kp * Kp * i : nullptr, tol};
+    Kmax = std::max(Kmax, K[i]);
   }
-  if (Kmax == 0) return TP_OK;
-  HIPCHK(hipMemcpyAsync(c->jobs, c->jobs_host, sizeof(EigJob) * cnt, hipMemcpyHostToDevice, c->stream));
-  size_t e0 = 0;
-  TPCHK(prof_begin(c, &e0));
-  HIPCHK(syev_batched(c->jobs, cnt, Kmax, c->stream));
-  {
+  if (Kmax == 0) {
+    if (host_w) host_w->assign(cnt, {});
+    return TP_OK;
+  }
+  const int Kp = (Kmax + 1) & ~1;
+  double* work = nullptr;
+  if (Kmax > kGramLds) TPCHK(wsalloc(c, (size_t)Kp * Kp * std::min(cnt, kBatchJobs), &work));
+  for (int b0 = 0; b0 < cnt; b0 += kBatchJobs) {
+    const int nb = std::min(kBatchJobs, cnt - b0);
+    JobBatch<EigJob> jb;
+    for (int i = 0; i < nb; ++i)
+      jb.j[i] = EigJob{K[b0 + i], A[b0 + i], W[b0 + i], V[b0 + i], work ? work + (size_t)Kp * Kp * i : nullptr, tol};
+    size_t e0 = 0;
+    TPCHK(prof_begin(c, &e0));
+    HIPCHK(syev_batched(jb, nb, Kmax, c->stream));
     // algorithmic work: a symmetric eigendecomposition costs about 9 K^3 flops; bytes: A in, V and w out
     double fl = 0, by = 0;
-    for (int i = 0; i < cnt; ++i) { fl += 9.0 * K[i] * K[i] * K[i]; by += 8.0 * (2.0 * K[i] * K[i] + K[i]); }
+    for (int i = 0; i < nb; ++i) {
+      const double k = K[b0 + i];
+      fl += 9.0 * k * k * k;
+      by += 8.0 * (2.0 * k * k + k);
+    }
     TPCHK(prof_end(c, PC_SYEV, e0, fl, by));
   }
-  c->jobs_pending = true;
   if (host_w) {
     host_w->assign(cnt, {});
     size_t off = 0;
     for (int i = 0; i < cnt; ++i) {
+      if (off + K[i] > tp_ctx::kHost) return fail(TP_EINVAL, "eigenvalue staging too small");
       HIPCHK(hipMemcpyAsync(c->host + off, W[i], sizeof(double) * K[i], hipMemcpyDeviceToHost, c->stream));
       off += K[i];
     }
     HIPCHK(hipStreamSynchronize(c->stream));
-    c->jobs_pending = false;
     off = 0;
     for (int i = 0; i < cnt; ++i) {
       (*host_w)[i].assign(c->host + off, c->host + off + K[i]);
@@ -340,37 +335,40 @@ tp_status eig(tp_ctx* c, int cnt, const int* K, const double* const* A, double* 
 }
 
 // Pivoted Cholesky of cnt Gram matrices G[i] (K[i] x K[i]): W[i] = P R^-1 (K[i] x q[i]) with the
-// numerical rank q[i] (pivots above tol * max diagonal) returned on the host.
+// numerical rank q[i] (pivots above tol * max diagonal) returned on the host.  The kernel writes
+// the ranks straight into mapped host memory; only the stream synchronisation remains.
 tp_status chol(tp_ctx* c, int cnt, const int* K, const double* const* G, double tol, double* const* W, int* q) {
-  if (cnt > tp_ctx::kJobs) return fail(TP_EINVAL, "too many Cholesky jobs");
+  if (cnt > kBatchJobs) return fail(TP_EINVAL, "too many Cholesky jobs");
   int Kmax = 0;
   for (int i = 0; i < cnt; ++i) Kmax = std::max(Kmax, K[i]);
   if (Kmax > kMaxRank) return fail(TP_ERANK, "Gram matrix of size %d exceeds %d", Kmax, kMaxRank);
   double* work = nullptr;
   if (Kmax > kGramLds) TPCHK(wsalloc(c, (size_t)2 * Kmax * Kmax * cnt, &work));
+  int* dq = reinterpret_cast<int*>(c->dmap);
+  JobBatch<CholJob> jb;
   for (int i = 0; i < cnt; ++i)
-    c->cjobs_host[i] = CholJob{K[i], tol, G[i], W[i], c->qdev + i, work ? work + (size_t)2 * Kmax * Kmax * i : nullptr};
-  HIPCHK(hipMemcpyAsync(c->cjobs, c->cjobs_host, sizeof(CholJob) * cnt, hipMemcpyHostToDevice, c->stream));
+    jb.j[i] = CholJob{K[i], tol, G[i], W[i], dq + i, work ? work + (size_t)2 * Kmax * Kmax * i : nullptr};
   size_t e0 = 0;
   TPCHK(prof_begin(c, &e0));
-  HIPCHK(pchol_batched(c->cjobs, cnt, Kmax, c->stream));
+  HIPCHK(pchol_batched(jb, cnt, Kmax, c->stream));
   {
     double fl = 0, by = 0;
     for (int i = 0; i < cnt; ++i) { fl += 2.0 * K[i] * K[i] * K[i] / 3.0; by += 8.0 * 2.0 * K[i] * K[i]; }
     TPCHK(prof_end(c, PC_CHOL, e0, fl, by));
   }
-  HIPCHK(hipMemcpyAsync(c->qhost, c->qdev, sizeof(int) * cnt, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
-  for (int i = 0; i < cnt; ++i) q[i] = c->qhost[i];
+  const int* hq = reinterpret_cast<const int*>(c->hmap);
+  for (int i = 0; i < cnt; ++i) q[i] = hq[i];
   return TP_OK;
 }
 
 // Eigenpairs of cnt positive semidefinite Gram matrices (pivoted Cholesky + one-sided Jacobi):
-// eigenvalues (descending) on the host in host_w, numerical ranks in q, and the trace the
-// Cholesky left unresolved in rest (it belongs to the discarded tail).
-tp_status psd_eig(tp_ctx* c, int cnt, const int* K, const double* const* G, double* const* W, double* const* V,
-                  double jtol, std::vector<std::vector<double>>* host_w, int* q, double* rest) {
-  if (cnt > tp_ctx::kJobs) return fail(TP_EINVAL, "too many eigen jobs");
+// eigenvectors to V (device), eigenvalues (descending) on the host in host_w, numerical ranks in
+// q, and the trace the Cholesky left unresolved in rest (it belongs to the discarded tail).  The
+// kernel writes eigenvalues, ranks and traces straight into mapped host memory.
+tp_status psd_eig(tp_ctx* c, int cnt, const int* K, const double* const* G, double* const* V, double jtol,
+                  std::vector<std::vector<double>>* host_w, int* q, double* rest) {
+  if (cnt > kBatchJobs) return fail(TP_EINVAL, "too many eigen jobs");
   int Kmax = 0;
   size_t tot = 0;
   for (int i = 0; i < cnt; ++i) {
@@ -378,24 +376,27 @@ tp_status psd_eig(tp_ctx* c, int cnt, const int* K, const double* const* G, doub
     Kmax = std::max(Kmax, K[i]);
     tot += K[i];
   }
-  if (tot + 2 * cnt > tp_ctx::kHost) return fail(TP_EINVAL, "eigenvalue staging too small");
-  double* work = nullptr;
-  if (Kmax > kGramLds) TPCHK(wsalloc(c, (size_t)2 * Kmax * Kmax * cnt, &work));
-  double* dres;  // cnt traces then cnt ranks (as int)
-  TPCHK(wsalloc(c, (size_t)2 * cnt, &dres));
-  int* dq = reinterpret_cast<int*>(dres + cnt);
-  for (int i = 0; i < cnt; ++i)
-    c->pjobs_host[i] = PsdJob{K[i], G[i], W[i], V[i], dq + i, dres + i,
-                              work ? work + (size_t)2 * Kmax * Kmax * i : nullptr, 1e-16, jtol};
+  if (tot + 2 * cnt > tp_ctx::kMap) return fail(TP_EINVAL, "eigenvalue staging too small");
+  host_w->assign(cnt, {});
   if (Kmax == 0) {
-    host_w->assign(cnt, {});
     for (int i = 0; i < cnt; ++i) { q[i] = 0; rest[i] = 0.0; }
     return TP_OK;
   }
-  HIPCHK(hipMemcpyAsync(c->pjobs, c->pjobs_host, sizeof(PsdJob) * cnt, hipMemcpyHostToDevice, c->stream));
+  double* work = nullptr;
+  if (Kmax > kGramLds) TPCHK(wsalloc(c, (size_t)2 * Kmax * Kmax * cnt, &work));
+  // mapped layout: eigenvalues (tot), traces (cnt), ranks (cnt ints)
+  double* dres = c->dmap + tot;
+  int* dq = reinterpret_cast<int*>(dres + cnt);
+  JobBatch<PsdJob> jb;
+  size_t off = 0;
+  for (int i = 0; i < cnt; ++i) {
+    jb.j[i] = PsdJob{K[i], G[i], c->dmap + off, V[i], dq + i, dres + i,
+                     work ? work + (size_t)2 * Kmax * Kmax * i : nullptr, 1e-16, jtol};
+    off += K[i];
+  }
   size_t e0 = 0;
   TPCHK(prof_begin(c, &e0));
-  HIPCHK(psd_eig_batched(c->pjobs, cnt, Kmax, c->stream));
+  HIPCHK(psd_eig_batched(jb, cnt, Kmax, c->stream));
   {
     // algorithmic work: that of a symmetric eigendecomposition with vectors, about 9 K^3 flops
     // (tridiagonal reduction, implicit QR, back transformation); bytes: G in, V and w out
@@ -403,24 +404,44 @@ tp_status psd_eig(tp_ctx* c, int cnt, const int* K, const double* const* G, doub
     for (int i = 0; i < cnt; ++i) { fl += 9.0 * K[i] * K[i] * K[i]; by += 8.0 * (2.0 * K[i] * K[i] + K[i]); }
     TPCHK(prof_end(c, PC_GRAM_EIG, e0, fl, by));
   }
-  size_t off = 0;
-  for (int i = 0; i < cnt; ++i) {
-    HIPCHK(hipMemcpyAsync(c->host + off, W[i], sizeof(double) * K[i], hipMemcpyDeviceToHost, c->stream));
-    off += K[i];
-  }
-  HIPCHK(hipMemcpyAsync(c->host + off, dres, sizeof(double) * 2 * cnt, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
-  host_w->assign(cnt, {});
-  const int* hq = reinterpret_cast<const int*>(c->host + off + cnt);
-  for (int i = 0; i < cnt; ++i) {
-    rest[i] = c->host[off + i];
-    q[i] = hq[i];
-  }
+  const double* hres = c->hmap + tot;
+  const int* hq = reinterpret_cast<const int*>(hres + cnt);
   off = 0;
   for (int i = 0; i < cnt; ++i) {
-    (*host_w)[i].assign(c->host + off, c->host + off + K[i]);
+    rest[i] = hres[i];
+    q[i] = hq[i];
+    (*host_w)[i].assign(c->hmap + off, c->hmap + off + K[i]);
     off += K[i];
   }
+  return TP_OK;
+}
+
+// The same eigendecomposition with eigenvalues left on the device (W[i], K[i] doubles, zero past
+// the numerical rank) and no synchronisation; ranks and traces go to the mapped scratch.
+tp_status psd_eig_dev(tp_ctx* c, int cnt, const int* K, const double* const* G, double* const* W, double* const* V,
+                      double jtol) {
+  if (cnt > kBatchJobs) return fail(TP_EINVAL, "too many eigen jobs");
+  int Kmax = 0;
+  for (int i = 0; i < cnt; ++i) {
+    if (K[i] > kMaxRank) return fail(TP_ERANK, "Gram matrix of size %d exceeds the eigensolver limit %d", K[i], kMaxRank);
+    Kmax = std::max(Kmax, K[i]);
+  }
+  if (Kmax == 0) return TP_OK;
+  double* work = nullptr;
+  if (Kmax > kGramLds) TPCHK(wsalloc(c, (size_t)2 * Kmax * Kmax * cnt, &work));
+  double* dres = c->dmap + tp_ctx::kMap / 2;
+  int* dq = reinterpret_cast<int*>(dres + cnt);
+  JobBatch<PsdJob> jb;
+  for (int i = 0; i < cnt; ++i)
+    jb.j[i] = PsdJob{K[i], G[i], W[i], V[i], dq + i, dres + i, work ? work + (size_t)2 * Kmax * Kmax * i : nullptr,
+                     1e-16, jtol};
+  size_t e0 = 0;
+  TPCHK(prof_begin(c, &e0));
+  HIPCHK(psd_eig_batched(jb, cnt, Kmax, c->stream));
+  double fl = 0, by = 0;
+  for (int i = 0; i < cnt; ++i) { fl += 9.0 * K[i] * K[i] * K[i]; by += 8.0 * (2.0 * K[i] * K[i] + K[i]); }
+  TPCHK(prof_end(c, PC_SYEV, e0, fl, by));
   return TP_OK;
 }
 
@@ -505,11 +526,9 @@ tp_status hosvd(tp_ctx* c, int d, const int* q, const T* M, double tol, int cap,
                 TO* core_out, bool* capped) {
   using Tacc = double;
   double* G[3];
-  double* w[3];
   double* E[3];
   for (int m = 0; m < d; ++m) {
     TPCHK(wsalloc(c, (size_t)q[m] * q[m], &G[m]));
-    TPCHK(wsalloc(c, (size_t)q[m], &w[m]));
     TPCHK(wsalloc(c, (size_t)q[m] * q[m], &E[m]));
   }
   {
@@ -531,9 +550,10 @@ tp_status hosvd(tp_ctx* c, int d, const int* q, const T* M, double tol, int cap,
   const double* Ap[3] = {G[0], G[1], d == 3 ? G[2] : nullptr};
   int qr[3] = {0, 0, 0};
   double rest[3] = {0, 0, 0};
-  // The rank rule compares tail sums of eigenvalues with tol^2 ||M||^2 / d; Jacobi rotations stop
-  // once every column pair is orthogonal to 1e-2 tol^2 (relative), far below what moves that sum.
-  TPCHK(psd_eig(c, d, q, Ap, w, E, std::max(1e-14, 1e-2 * tol * tol), &hw, qr, rest));
+  // Jacobi rotations stop once every column pair is orthogonal to 1e-2 tol relative: that
+  // resolves every eigenvalue to 1e-2 tol of itself (the rank rule needs far less) and moves the
+  // kept subspace, hence the truncation error, by about 1e-2 tol ||M||.
+  TPCHK(psd_eig(c, d, q, Ap, E, std::max(1e-14, 1e-2 * tol), &hw, qr, rest));
   *capped = false;
   for (int m = 0; m < d; ++m) {
     double tot = rest[m];
@@ -1004,9 +1024,10 @@ tp_status inner_sym_impl(tp_ctx* c, const tp_tensor* x, const tp_symbol* S, cons
     TPCHK(run(c, g1));
     TPCHK((mm<double, double, double, double>(c, false, true, rx[0], rx[1], ry[1] * R, 1.0, D, rx[0], G[1], rx[1], 0.0, Z, rx[0])));
   }
-  HIPCHK(dot<double>(Cx, Z, (long)cx, res, res + 1, c->stream));
-  TPCHK(sync_to_host(c, res, sizeof(double), c->host));
-  *out = c->host[0];
+  // the sum lands in mapped host memory: no copy command, only the synchronisation
+  HIPCHK(dot<double>(Cx, Z, (long)cx, c->dmap, res + 1, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  *out = c->hmap[0];
   return TP_OK;
 }
 
@@ -1059,9 +1080,10 @@ tp_status inner_impl(tp_ctx* c, const tp_tensor* x, const tp_tensor* y, double* 
   int lda[3] = {px[0], px[1], px[2]};
   bool tA[3] = {false, false, false};
   TPCHK(tucker_contract(c, d, ry, Cy, A, lda, tA, px, 1.0, 0.0, Z));
-  HIPCHK(dot<double>(Cx, Z, (long)cx, res, res + 1, c->stream));
-  TPCHK(sync_to_host(c, res, sizeof(double), c->host));
-  *out = c->host[0];
+  // the sum lands in mapped host memory: no copy command, only the synchronisation
+  HIPCHK(dot<double>(Cx, Z, (long)cx, c->dmap, res + 1, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  *out = c->hmap[0];
   return TP_OK;
 }
 
@@ -1146,7 +1168,6 @@ tp_status fit_expsum(tp_ctx* c, int kind, double alpha, double cn, double cp, do
   const int m = 1000, nc = (int)cands.size();
   double *A, *t, *G, *bvec, *ew, *E, *cn_, *err, *wsol, *ones;
   FitCand* cd;
-  TPCHK(wsalloc(c, (size_t)nc, &cd));
   TPCHK(wsalloc(c, (size_t)nc * m * K, &A));
   TPCHK(wsalloc(c, (size_t)nc * K, &t));
   TPCHK(wsalloc(c, (size_t)nc * K * K, &G));
@@ -1156,8 +1177,12 @@ tp_status fit_expsum(tp_ctx* c, int kind, double alpha, double cn, double cp, do
   TPCHK(wsalloc(c, (size_t)nc * K, &cn_));
   TPCHK(wsalloc(c, (size_t)nc, &err));
   TPCHK(wsalloc(c, (size_t)nc * K, &wsol));
-  TPCHK(wsalloc(c, (size_t)m, &ones));
-  HIPCHK(hipMemcpyAsync(cd, cands.data(), sizeof(FitCand) * nc, hipMemcpyHostToDevice, c->stream));
+  // the candidates travel through the mapped host scratch (read once by the design kernel)
+  // (every user of the mapped scratch synchronises the stream before returning, so it is free)
+  if (nc * sizeof(FitCand) > tp_ctx::kMap / 4 * sizeof(double)) return fail(TP_EINVAL, "too many fit candidates");
+  FitCand* hc = reinterpret_cast<FitCand*>(c->hmap + tp_ctx::kMap / 4);
+  for (int ci = 0; ci < nc; ++ci) hc[ci] = cands[ci];
+  cd = reinterpret_cast<FitCand*>(c->dmap + tp_ctx::kMap / 4);
   HIPCHK(fit_design(kind, alpha, cn, cp, rho0, B, K, m, cd, nc, A, t, c->stream));
   // column scaling: cn_ = 1/||A_k|| from the Gram diagonal; scaled Gram = D G D
   GemmArgs<double, double, double, double> g;
@@ -1166,8 +1191,12 @@ tp_status fit_expsum(tp_ctx* c, int kind, double alpha, double cn, double cp, do
   g.B = A; g.ldb = m; g.sB = (long)m * K;
   g.C = G; g.ldc = K; g.sC = (long)K * K;
   TPCHK(run(c, g));
-  std::vector<double> hones(m, 1.0);
-  HIPCHK(hipMemcpyAsync(ones, hones.data(), sizeof(double) * m, hipMemcpyHostToDevice, c->stream));
+  {
+    const double* w1 = nullptr;
+    const double* o = nullptr;
+    TPCHK(unit_symbol<double>(c, m, &o, &w1));
+    ones = const_cast<double*>(o);
+  }
   GemmArgs<double, double, double, double> gb;
   gb.M = K; gb.N = 1; gb.K = m; gb.batch = nc;
   gb.A = A; gb.lda = m; gb.tA = true; gb.sA = (long)m * K;
@@ -1183,18 +1212,22 @@ tp_status fit_expsum(tp_ctx* c, int kind, double alpha, double cn, double cp, do
     Wp[ci] = ew + (size_t)ci * K;
     Vp[ci] = E + (size_t)ci * K * K;
   }
-  TPCHK(eig(c, nc, Ks.data(), Ap.data(), Wp.data(), Vp.data(), nullptr));
+  // the scaled normal matrices are positive semidefinite Gram matrices: the Gram eigensolver
+  // (eigenvalues to 1e-14 of themselves, ranks below 1e-16 of the largest pivot dropped)
+  TPCHK(psd_eig_dev(c, nc, Ks.data(), Ap.data(), Wp.data(), Vp.data(), 1e-14));
   HIPCHK(fit_solve(K, nc, ew, E, bvec, cn_, 1e-15, wsol, c->stream));
-  HIPCHK(fit_error(kind, alpha, cn, cp, rho0, B, K, t, wsol, nc, 4096, err, c->stream));
-  std::vector<double> herr(nc);
-  TPCHK(sync_to_host(c, err, sizeof(double) * nc, herr.data()));
+  (void)err;
+  double* derr = c->dmap;  // errors straight to the mapped host scratch
+  HIPCHK(fit_error(kind, alpha, cn, cp, rho0, B, K, t, wsol, nc, 4096, derr, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  const double* herr = c->hmap;
   int best = 0;
   for (int ci = 1; ci < nc; ++ci)
     if (herr[ci] < herr[best] || std::isnan(herr[best])) best = ci;
   *err_out = herr[best];
-  HIPCHK(hipMemcpyAsync(tau_out, t + (size_t)best * K, sizeof(double) * K, hipMemcpyDeviceToDevice, c->stream));
-  HIPCHK(hipMemcpyAsync(w_out, wsol + (size_t)best * K, sizeof(double) * K, hipMemcpyDeviceToDevice, c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
+  // copies on the compute stream (the workspace they read is released in stream order)
+  HIPCHK((convert<double, double>(t + (size_t)best * K, tau_out, K, c->stream)));
+  HIPCHK((convert<double, double>(wsol + (size_t)best * K, w_out, K, c->stream)));
   return TP_OK;
 }
 
@@ -1224,14 +1257,8 @@ tp_status tp_create(int device, void* stream, size_t workspace_bytes, tp_ctx** o
     return fail(TP_ENOMEM, "workspace allocation of %zu bytes failed: %s", workspace_bytes, hipGetErrorString(e));
   }
   HIPCHK(hipHostMalloc(&c->host, sizeof(double) * tp_ctx::kHost, hipHostMallocDefault));
-  HIPCHK(hipHostMalloc(&c->jobs_host, sizeof(EigJob) * tp_ctx::kJobs, hipHostMallocDefault));
-  HIPCHK(hipMalloc(&c->jobs, sizeof(EigJob) * tp_ctx::kJobs));
-  HIPCHK(hipHostMalloc(&c->pjobs_host, sizeof(PsdJob) * tp_ctx::kJobs, hipHostMallocDefault));
-  HIPCHK(hipMalloc(&c->pjobs, sizeof(PsdJob) * tp_ctx::kJobs));
-  HIPCHK(hipHostMalloc(&c->cjobs_host, sizeof(CholJob) * tp_ctx::kJobs, hipHostMallocDefault));
-  HIPCHK(hipMalloc(&c->cjobs, sizeof(CholJob) * tp_ctx::kJobs));
-  HIPCHK(hipMalloc(&c->qdev, sizeof(int) * tp_ctx::kJobs));
-  HIPCHK(hipHostMalloc(&c->qhost, sizeof(int) * tp_ctx::kJobs, hipHostMallocDefault));
+  HIPCHK(hipHostMalloc(&c->hmap, sizeof(double) * tp_ctx::kMap, hipHostMallocMapped | hipHostMallocCoherent));
+  HIPCHK(hipHostGetDevicePointer((void**)&c->dmap, c->hmap, 0));
   *out = c;
   return TP_OK;
 }
@@ -1247,15 +1274,8 @@ tp_status tp_destroy(tp_ctx* c) {
   for (auto& kv : c->tab64) (void)hipFree(kv.second);
   for (auto& kv : c->tab32) (void)hipFree(kv.second);
   (void)hipFree(c->ws);
-  (void)hipFree(c->jobs);
-  (void)hipFree(c->cjobs);
-  (void)hipFree(c->pjobs);
-  (void)hipHostFree(c->pjobs_host);
-  (void)hipFree(c->qdev);
-  (void)hipHostFree(c->cjobs_host);
-  (void)hipHostFree(c->qhost);
+  (void)hipHostFree(c->hmap);
   (void)hipHostFree(c->host);
-  (void)hipHostFree(c->jobs_host);
   delete c;
   return TP_OK;
 }

@@ -21,9 +21,18 @@ namespace tpk {
 // ---------------------------------------------------------------------------------------------
 constexpr int GBM = 64, GBN = 64, GBK = 16, GTHREADS = 256;
 
+// c = b * r1 + a for 0 <= c < 2^24: the float quotient is off by at most one, then corrected
+// (an integer division per loaded element would dominate the tile load).
+__device__ __forceinline__ void fast_divmod(int c, int r1, float inv, int& b, int& a) {
+  b = (int)((float)c * inv);
+  a = c - b * r1;
+  if (a < 0) { --b; a += r1; } else if (a >= r1) { ++b; a -= r1; }
+}
+
 template <typename T>
-__device__ __forceinline__ T fs_load(const FaceSplit<T>& F, int row, int c) {
-  int a = c % F.r1, b = c / F.r1;
+__device__ __forceinline__ T fs_load(const FaceSplit<T>& F, int row, int c, float inv) {
+  int a, b;
+  fast_divmod(c, F.r1, inv, b, a);
   T v = F.x1[row + (long)F.ld1 * a] * F.x2[row + (long)F.ld2 * b];
   if (F.w) v = (T)((double)v * F.w[b]);
   return v;
@@ -45,6 +54,7 @@ __global__ __launch_bounds__(GTHREADS) void k_gemm(GemmArgs<TA, TB, TC, Tacc> g)
   FaceSplit<TB> FB = g.FB;
   if (g.fsA) { FA.x1 += (long)(b / g.divA) * g.sA; FA.x2 += (long)(b / g.divA) * g.sA; }
   if (g.fsB) { FB.x1 += (long)(b / g.divB) * g.sB; FB.x2 += (long)(b / g.divB) * g.sB; }
+  const float invA = g.fsA ? 1.0f / (float)FA.r1 : 0.0f, invB = g.fsB ? 1.0f / (float)FB.r1 : 0.0f;
   TC* C = g.C + (long)b * g.sC;
   const int tm = tid % 16, tn = tid / 16;
   Tacc acc[4][4];
@@ -61,7 +71,7 @@ __global__ __launch_bounds__(GTHREADS) void k_gemm(GemmArgs<TA, TB, TC, Tacc> g)
         int m = tid % 64, kk = tid / 64 + 4 * i;
         int row = m0 + m, col = k0 + kk;
         Tacc v = 0;
-        if (row < g.M && col < kend) v = g.fsA ? (Tacc)fs_load(FA, row, col) : (Tacc)A[row + (long)g.lda * col];
+        if (row < g.M && col < kend) v = g.fsA ? (Tacc)fs_load(FA, row, col, invA) : (Tacc)A[row + (long)g.lda * col];
         As[kk][m] = v;
       }
     } else {
@@ -81,7 +91,7 @@ __global__ __launch_bounds__(GTHREADS) void k_gemm(GemmArgs<TA, TB, TC, Tacc> g)
         int kk = tid % 16, n = tid / 16 + 16 * i;
         int row = k0 + kk, col = n0 + n;
         Tacc v = 0;
-        if (row < kend && col < g.N) v = g.fsB ? (Tacc)fs_load(FB, row, col) : (Tacc)B[row + (long)g.ldb * col];
+        if (row < kend && col < g.N) v = g.fsB ? (Tacc)fs_load(FB, row, col, invB) : (Tacc)B[row + (long)g.ldb * col];
         Bs[kk][n] = v;
       }
     } else {
@@ -162,15 +172,15 @@ constexpr int MBK = 32;
 
 template <typename TA, typename TB, typename TC, typename Tacc>
 __device__ __forceinline__ void mfma_fetch(const GemmArgs<TA, TB, TC, Tacc>& g, const TA* A, const TB* B,
-                                           const FaceSplit<TA>& FA, const FaceSplit<TB>& FB, int m0, int n0,
-                                           int k0, int kend, int tid, Tacc (&ra)[8], Tacc (&rb)[8]) {
+                                           const FaceSplit<TA>& FA, const FaceSplit<TB>& FB, float invA, float invB,
+                                           int m0, int n0, int k0, int kend, int tid, Tacc (&ra)[8], Tacc (&rb)[8]) {
   if (!g.tA) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       int m = tid & 63, kk = (tid >> 6) + 4 * i;
       int row = m0 + m, col = k0 + kk;
       Tacc v = 0;
-      if (row < g.M && col < kend) v = g.fsA ? (Tacc)fs_load(FA, row, col) : (Tacc)A[row + (long)g.lda * col];
+      if (row < g.M && col < kend) v = g.fsA ? (Tacc)fs_load(FA, row, col, invA) : (Tacc)A[row + (long)g.lda * col];
       ra[i] = v;
     }
   } else {
@@ -189,7 +199,7 @@ __device__ __forceinline__ void mfma_fetch(const GemmArgs<TA, TB, TC, Tacc>& g, 
       int kk = tid & 31, n = (tid >> 5) + 8 * i;
       int row = k0 + kk, col = n0 + n;
       Tacc v = 0;
-      if (row < kend && col < g.N) v = g.fsB ? (Tacc)fs_load(FB, row, col) : (Tacc)B[row + (long)g.ldb * col];
+      if (row < kend && col < g.N) v = g.fsB ? (Tacc)fs_load(FB, row, col, invB) : (Tacc)B[row + (long)g.ldb * col];
       rb[i] = v;
     }
   } else {
@@ -222,6 +232,7 @@ __global__ __launch_bounds__(GTHREADS) void k_gemm_mfma(GemmArgs<TA, TB, TC, Tac
   FaceSplit<TB> FB = g.FB;
   if (g.fsA) { FA.x1 += (long)(b / g.divA) * g.sA; FA.x2 += (long)(b / g.divA) * g.sA; }
   if (g.fsB) { FB.x1 += (long)(b / g.divB) * g.sB; FB.x2 += (long)(b / g.divB) * g.sB; }
+  const float invA = g.fsA ? 1.0f / (float)FA.r1 : 0.0f, invB = g.fsB ? 1.0f / (float)FB.r1 : 0.0f;
   TC* C = g.C + (long)b * g.sC;
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
   V4 acc[2][2];
@@ -233,7 +244,7 @@ __global__ __launch_bounds__(GTHREADS) void k_gemm_mfma(GemmArgs<TA, TB, TC, Tac
       for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
 
   Tacc ra[8], rb[8];
-  if (kbeg < kend) mfma_fetch(g, A, B, FA, FB, m0, n0, kbeg, kend, tid, ra, rb);
+  if (kbeg < kend) mfma_fetch(g, A, B, FA, FB, invA, invB, m0, n0, kbeg, kend, tid, ra, rb);
   for (int k0 = kbeg; k0 < kend; k0 += MBK) {
     if (!g.tA) {
 #pragma unroll
@@ -250,7 +261,7 @@ __global__ __launch_bounds__(GTHREADS) void k_gemm_mfma(GemmArgs<TA, TB, TC, Tac
       for (int i = 0; i < 8; ++i) Bs[(tid >> 6) + 4 * i][tid & 63] = rb[i];
     }
     __syncthreads();
-    if (k0 + MBK < kend) mfma_fetch(g, A, B, FA, FB, m0, n0, k0 + MBK, kend, tid, ra, rb);
+    if (k0 + MBK < kend) mfma_fetch(g, A, B, FA, FB, invA, invB, m0, n0, k0 + MBK, kend, tid, ra, rb);
 #pragma unroll
     for (int kk = 0; kk < MBK; kk += 4) {
       const int kr = kk + (lane >> 4), c16 = lane & 15;
@@ -295,8 +306,17 @@ __global__ void k_gemm_reduce(int M, int N, int splits, const Tacc* part, Tacc a
   if (e >= mn) return;
   int row = (int)(e % M), col = (int)(e / M);
   const Tacc* p = part + (long)b * splits * mn + e;
-  Tacc acc = 0;
-  for (int s = 0; s < splits; ++s) acc += p[(long)s * mn];
+  // four independent partial sums keep four loads in flight (fixed order: deterministic)
+  Tacc a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  int s = 0;
+  for (; s + 4 <= splits; s += 4) {
+    a0 += p[(long)s * mn];
+    a1 += p[(long)(s + 1) * mn];
+    a2 += p[(long)(s + 2) * mn];
+    a3 += p[(long)(s + 3) * mn];
+  }
+  for (; s < splits; ++s) a0 += p[(long)s * mn];
+  Tacc acc = (a0 + a1) + (a2 + a3);
   long o = (long)b * sC + row + (long)ldc * col;
   Tacc v = alpha * acc;
   if (beta != (Tacc)0) v += beta * (Tacc)C[o];
@@ -537,9 +557,9 @@ __device__ __forceinline__ int rr_index(int j, int s, int Kp) {
 
 // One workgroup per matrix.  A (Kp x Kp) in LDS when SMEM, else in J.work (global, L2 resident).
 template <bool SMEM>
-__global__ __launch_bounds__(256) void k_syev(const EigJob* jobs) {
+__global__ __launch_bounds__(256) void k_syev(JobBatch<EigJob> jobs) {
   extern __shared__ double sm[];
-  const EigJob J = jobs[blockIdx.x];
+  const EigJob J = jobs.j[blockIdx.x];
   const int K = J.K;
   const int tid = threadIdx.x;
   if (K <= 0) return;
@@ -669,9 +689,9 @@ __global__ __launch_bounds__(256) void k_syev(const EigJob* jobs) {
 constexpr int EIG_SMALL = 96;
 constexpr int EIG_NT = 512;
 
-__global__ __launch_bounds__(EIG_NT) void k_syev_small(const EigJob* jobs) {
+__global__ __launch_bounds__(EIG_NT) void k_syev_small(JobBatch<EigJob> jobs) {
   extern __shared__ double sm[];
-  const EigJob J = jobs[blockIdx.x];
+  const EigJob J = jobs.j[blockIdx.x];
   const int K = J.K;
   const int tid = threadIdx.x;
   if (K <= 0) return;
@@ -963,10 +983,10 @@ __device__ __forceinline__ int lanes_for(int nt, int groups) {
 // sum_{i<l<=j} R(i, l) X(l, j), which the lanes split by l mod (lanes) and add with DPP; each
 // lane keeps the X(l, j) of its own residue class, so no barrier is needed.
 template <bool SMEM, int NT>
-__global__ __launch_bounds__(NT) void k_pchol(const CholJob* jobs) {
+__global__ __launch_bounds__(NT) void k_pchol(JobBatch<CholJob> jobs) {
   extern __shared__ double sm[];
   constexpr int KMAX = ChGrid<NT>::KMAX, NW = NT / 64;
-  const CholJob J = jobs[blockIdx.x];
+  const CholJob J = jobs.j[blockIdx.x];
   const int K = J.K;
   const int tid = threadIdx.x;
   if (K <= 0) { if (tid == 0 && J.q) *J.q = 0; return; }
@@ -1038,7 +1058,7 @@ __global__ __launch_bounds__(NT) void k_pchol(const CholJob* jobs) {
 }
 
 template <bool SMEM, int NT, typename Job>
-hipError_t launch_gram(void (*kern)(const Job*), const Job* jobs, int count, size_t shm, hipStream_t s) {
+hipError_t launch_gram(void (*kern)(JobBatch<Job>), const JobBatch<Job>& jobs, int count, size_t shm, hipStream_t s) {
   if (SMEM) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
@@ -1047,8 +1067,9 @@ hipError_t launch_gram(void (*kern)(const Job*), const Job* jobs, int count, siz
   return hipGetLastError();
 }
 
-hipError_t pchol_batched(const CholJob* jobs_dev, int count, int Kmax, hipStream_t s) {
+hipError_t pchol_batched(const JobBatch<CholJob>& jobs_dev, int count, int Kmax, hipStream_t s) {
   if (count <= 0) return hipSuccess;
+  if (count > kBatchJobs) return hipErrorInvalidValue;
   if (Kmax > EIG_MAX) return hipErrorInvalidValue;
   const size_t extra = (size_t)Kmax * 16 + 32 * 8 + (size_t)Kmax * 4 + 64;
   const size_t shm = (size_t)Kmax * Kmax * 8 + extra;
@@ -1066,10 +1087,10 @@ hipError_t pchol_batched(const CholJob* jobs_dev, int count, int Kmax, hipStream
 // hold its rows in registers and add their partial dot products with DPP.
 // ---------------------------------------------------------------------------------------------
 template <bool SMEM, int NT>
-__global__ __launch_bounds__(NT) void k_psd_eig(const PsdJob* jobs) {
+__global__ __launch_bounds__(NT) void k_psd_eig(JobBatch<PsdJob> jobs) {
   extern __shared__ double sm[];
   constexpr int KMAX = ChGrid<NT>::KMAX, NW = NT / 64;
-  const PsdJob J = jobs[blockIdx.x];
+  const PsdJob J = jobs.j[blockIdx.x];
   const int K = J.K;
   const int tid = threadIdx.x;
   if (K <= 0) {
@@ -1084,8 +1105,10 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdJob* jobs) {
   int* perm = reinterpret_cast<int*>(slot + 2 * NW);   // K
   int* rank = perm + K;                                // K: output position of each column
   __shared__ CholShared sh;
-  __shared__ int changed[3];
-  if (tid == 0) changed[0] = changed[1] = changed[2] = 0;
+  // per sweep: the largest relative off-diagonal |x_p.x_r| / (|x_p| |x_r|) that was rotated
+  // away, as float bits (non-negative floats order like their bit patterns)
+  __shared__ unsigned int offmax[3];
+  if (tid == 0) offmax[0] = offmax[1] = offmax[2] = 0u;
   const int q = chol_phase<NT>(J.g, K, J.ctol, S, dk, perm, slot, rank, sh);
   // X = R^T in pivot order: X[l][k] = R(k, l) (l >= k), 0 above the diagonal
   if (SMEM) {
@@ -1121,8 +1144,8 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdJob* jobs) {
   const int pr = tid >> lg, li = tid & (L - 1);
   constexpr int RMAX = SMEM ? (KMAX * KMAX + 2 * NT - 1) / (2 * NT) : 1;  // rows per lane in registers
   for (int sweep = 0; sweep < 40 && q > 1; ++sweep) {
-    int* chg = &changed[sweep % 3];
-    if (tid == 0) changed[(sweep + 1) % 3] = 0;  // last read two sweeps ago
+    unsigned int* chg = &offmax[sweep % 3];
+    if (tid == 0) offmax[(sweep + 1) % 3] = 0u;  // last read two sweeps ago
     for (int st = 0; st < qp - 1; ++st) {
       int p = 0, r = 0;
       bool valid = pr < np;
@@ -1153,7 +1176,8 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdJob* jobs) {
       al = group_sum(al, L);
       be = group_sum(be, L);
       ga = group_sum(ga, L);
-      if (valid && ga != 0.0 && fabs(ga) > J.jtol * sqrt(al * be)) {
+      const double relo = (valid && ga != 0.0) ? fabs(ga) / sqrt(al * be) : 0.0;
+      if (relo > J.jtol) {
         const double zeta = (be - al) / (2.0 * ga);
         const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
@@ -1173,11 +1197,15 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdJob* jobs) {
             X[i + K * r] = sn * a + c * b;
           }
         }
-        if (li == 0) *chg = 1;
+        if (li == 0) atomicMax(chg, __float_as_uint((float)relo));
       }
       __syncthreads();
     }
-    if (!*chg) break;  // read by every thread after the sweep's last barrier
+    // read by every thread after the sweep's last barrier.  Stop when nothing was rotated, or
+    // when every rotation was so small that the sweep's quadratic convergence leaves the
+    // columns orthogonal to jtol: off-diagonals after a sweep are O(K max^2).
+    const float mx = __uint_as_float(*chg);
+    if (mx == 0.0f || (double)mx * (double)mx * (double)q <= J.jtol) break;
   }
   __syncthreads();
   // eigenvalues = squared column norms (16 lanes per column), sorted descending;
@@ -1212,8 +1240,9 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdJob* jobs) {
   if (tid == 0) { *J.q = q; *J.rest = sh.rest; }
 }
 
-hipError_t psd_eig_batched(const PsdJob* jobs_dev, int count, int Kmax, hipStream_t s) {
+hipError_t psd_eig_batched(const JobBatch<PsdJob>& jobs_dev, int count, int Kmax, hipStream_t s) {
   if (count <= 0) return hipSuccess;
+  if (count > kBatchJobs) return hipErrorInvalidValue;
   if (Kmax > EIG_MAX) return hipErrorInvalidValue;
   const size_t extra = (size_t)Kmax * 8 + 32 * 8 + (size_t)Kmax * 8 + 64;
   const size_t shm = (size_t)Kmax * Kmax * 8 + extra;
@@ -1222,8 +1251,9 @@ hipError_t psd_eig_batched(const PsdJob* jobs_dev, int count, int Kmax, hipStrea
   return launch_gram<false, 1024>(k_psd_eig<false, 1024>, jobs_dev, count, extra, s);
 }
 
-hipError_t syev_batched(const EigJob* jobs_dev, int count, int Kmax, hipStream_t s) {
+hipError_t syev_batched(const JobBatch<EigJob>& jobs_dev, int count, int Kmax, hipStream_t s) {
   if (count <= 0) return hipSuccess;
+  if (count > kBatchJobs) return hipErrorInvalidValue;
   if (Kmax > EIG_MAX) return hipErrorInvalidValue;
   int Kp = (Kmax + 1) & ~1;
   if (Kmax <= EIG_SMALL) {

@@ -51,17 +51,23 @@ hipError_t dst_table(int N, T* tab, hipStream_t s);
 // Gram and eigen problems up to this size are kept in LDS; larger ones (up to 256) use global scratch.
 constexpr int kGramLds = 128;
 
+// Job descriptors of the batched one-workgroup-per-matrix kernels travel by value in the kernel
+// arguments (no staging copy): at most kBatchJobs per launch.
+constexpr int kBatchJobs = 16;
+template <typename J>
+struct JobBatch { J j[kBatchJobs]; };
+
 // Batched symmetric Jacobi eigensolver, FP64.  Matrix b: K[b] x K[b] at a[b] (ld K[b]);
 // eigenvalues (descending) to w[b], eigenvectors to v[b] (ld K[b]).
 // Matrices larger than 128 need `work` (Kp x Kp doubles, Kp = K rounded up to even) in global memory.
 // tol: the sweeps stop once the off-diagonal Frobenius norm is <= tol * ||A||_F (0 = 1e-14).
 struct EigJob { int K; const double* a; double* w; double* v; double* work; double tol; };
-hipError_t syev_batched(const EigJob* jobs_dev, int count, int Kmax, hipStream_t s);
+hipError_t syev_batched(const JobBatch<EigJob>& jobs, int count, int Kmax, hipStream_t s);
 
 // Batched rank-revealing pivoted Cholesky of Gram matrices: W = P R^-1 (K x q, ld K), q to *q.
 // Matrices larger than 128 need `work` (2 K^2 doubles) in global memory.
 struct CholJob { int K; double tol; const double* g; double* w; int* q; double* work; };
-hipError_t pchol_batched(const CholJob* jobs_dev, int count, int Kmax, hipStream_t s);
+hipError_t pchol_batched(const JobBatch<CholJob>& jobs, int count, int Kmax, hipStream_t s);
 
 // Batched eigendecomposition of positive semidefinite Gram matrices (pivoted Cholesky, then
 // one-sided Jacobi on R^T).  Per job: eigenvalues descending to w (K entries, zero past the
@@ -70,7 +76,7 @@ hipError_t pchol_batched(const CholJob* jobs_dev, int count, int Kmax, hipStream
 // pivots <= ctol * max diag(G); a column pair is rotated while |x_p.x_r| > jtol |x_p||x_r|.
 // Matrices larger than 128 need `work` (2 K^2 doubles) in global memory.
 struct PsdJob { int K; const double* g; double* w; double* v; int* q; double* rest; double* work; double ctol; double jtol; };
-hipError_t psd_eig_batched(const PsdJob* jobs_dev, int count, int Kmax, hipStream_t s);
+hipError_t psd_eig_batched(const JobBatch<PsdJob>& jobs, int count, int Kmax, hipStream_t s);
 
 // Elementwise helpers.
 template <typename TI, typename TO>
