@@ -16,31 +16,28 @@ import scipy.fft as sfft
 from . import spectral
 
 
-def solve_full(f, alpha, c_neg, c_pos):
+def solve_full(f, alpha, c_neg, c_pos, c0=0.0, beta=None):
     """u on the full grid: forward sine transform, divide by s(rho), inverse
     (eqn:DiagFLaplace3D / eqn:DiagFLaplace2D).  The orthonormal DST-I of scipy is
-    the library step for F (it equals spectral.dst_matrix, pinned in the tests)."""
+    the library step for F (it equals spectral.dst_matrix, pinned in the tests).
+    c0 and beta give the general symbol of spectral.symbol."""
     f = np.asarray(f, dtype=np.float64)
     fh = sfft.dstn(f, type=1, norm="ortho")
-    s = spectral.symbol(spectral.rho_grid(f.shape), alpha, c_neg, c_pos)
+    s = spectral.symbol(spectral.rho_grid(f.shape), alpha, c_neg, c_pos, c0, beta)
     return sfft.idstn(fh / s, type=1, norm="ortho")
 
 
-def apply_full(x, alpha, c_neg, c_pos):
+def apply_full(x, alpha, c_neg, c_pos, c0=0.0, beta=None):
     """A_2 x on the full grid (the same diagonalisation, multiplying by s)."""
     x = np.asarray(x, dtype=np.float64)
     xh = sfft.dstn(x, type=1, norm="ortho")
-    s = spectral.symbol(spectral.rho_grid(x.shape), alpha, c_neg, c_pos)
+    s = spectral.symbol(spectral.rho_grid(x.shape), alpha, c_neg, c_pos, c0, beta)
     return sfft.idstn(xh * s, type=1, norm="ortho")
 
 
-def brute_force(f, alpha, c_neg, c_pos):
-    """Dense route that uses no sine transform: A = Kronecker sum of the 1D
-    tridiagonal matrices (eqn_low_rank_lap), eigendecomposition by numpy.linalg.eigh,
-    A_2 = c_neg A^-alpha + c_pos A^alpha from the eigenpairs, dense solve.
-    Only for n^d up to a few thousand."""
-    f = np.asarray(f, dtype=np.float64)
-    ns = f.shape
+def laplacian_full(ns):
+    """The d-dimensional matrix A as the Kronecker sum of the 1D tridiagonal matrices
+    (eqn_low_rank_lap), dense.  Only for n^d up to a few thousand."""
     N = int(np.prod(ns))
     A = np.zeros((N, N))
     for l, n in enumerate(ns):
@@ -50,8 +47,20 @@ def brute_force(f, alpha, c_neg, c_pos):
         for M in mats[1:]:
             K = np.kron(K, M)
         A += K
+    return A
+
+
+def brute_force(f, alpha, c_neg, c_pos, c0=0.0, beta=None):
+    """Dense route that uses no sine transform: A from laplacian_full, its
+    eigendecomposition by numpy.linalg.eigh, c0 I + c_neg A^-alpha + c_pos A^beta from the
+    eigenpairs, dense solve."""
+    f = np.asarray(f, dtype=np.float64)
+    ns = f.shape
+    N = int(np.prod(ns))
+    A = laplacian_full(ns)
     lam, Q = np.linalg.eigh(A)
-    A2 = (Q * (c_neg * lam ** (-alpha) + c_pos * lam**alpha)) @ Q.T
+    b = alpha if beta is None else beta
+    A2 = (Q * (c0 + c_neg * lam ** (-alpha) + c_pos * lam**b)) @ Q.T
     return np.linalg.solve(A2, f.reshape(N)).reshape(ns)
 
 
@@ -61,10 +70,10 @@ def sine_mode(n, k):
     return np.sin(k * np.pi * x)
 
 
-def single_mode_factor(ns, ks, alpha, c_neg, c_pos):
+def single_mode_factor(ns, ks, alpha, c_neg, c_pos, c0=0.0, beta=None):
     """For f = (x)_l sin(k_l pi x): u = f / s(sum_l lambda_{k_l}) exactly."""
     rho = sum(spectral.eigenvalues(n)[k - 1] for n, k in zip(ns, ks))
-    return 1.0 / float(spectral.symbol(rho, alpha, c_neg, c_pos))
+    return 1.0 / float(spectral.symbol(rho, alpha, c_neg, c_pos, c0, beta))
 
 
 def solve_cp_restricted(weights, factors, alpha, c_neg, c_pos, rows):

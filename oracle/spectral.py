@@ -59,12 +59,16 @@ def rho_grid(ns):
     return rho
 
 
-def symbol(rho, alpha, c_neg, c_pos):
-    """s(rho) = c_neg rho^-alpha + c_pos rho^alpha: the eigenvalues of
-    A_2 = c_neg A^-alpha + c_pos A^alpha (eqn:forControl with c_neg = beta,
-    c_pos = gamma/beta; spectral definition eqn:frac_Oper)."""
+def symbol(rho, alpha, c_neg, c_pos, c0=0.0, beta=None):
+    """s(rho) = c0 + c_neg rho^-alpha + c_pos rho^beta (beta = alpha unless given): the
+    eigenvalues of c0 I + c_neg A^-alpha + c_pos A^beta (spectral definition eqn:frac_Oper).
+    c0 = 0, beta = alpha is A_2 of eqn:forControl (c_neg = beta, c_pos = gamma/beta); the
+    preconditioning tests of Sec. 6 use A^alpha (eq:precond_ex1: c_neg = c0 = 0),
+    I + A^{2 alpha} (eq:precond_ex2: c0 = 1, beta = 2 alpha) and A^alpha + A^-alpha
+    (eq:precond_ex3)."""
     rho = np.asarray(rho, dtype=np.float64)
-    return c_neg * rho ** (-alpha) + c_pos * rho**alpha
+    b = alpha if beta is None else beta
+    return c0 + c_neg * rho ** (-alpha) + c_pos * rho**b
 
 
 def paper_coefficients(beta, gamma):

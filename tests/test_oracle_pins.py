@@ -269,3 +269,46 @@ def test_tucker_error_by_parseval_matches_full_grid():
     a, b = exact.tucker_error_slabs(p.weights, p.factors, p.alpha, p.c_neg, p.c_pos, core, U, range(0, 31, 2))
     c2, d2 = exact.tucker_error_slabs(p.weights, p.factors, p.alpha, p.c_neg, p.c_pos, core, U, range(1, 31, 2))
     assert a + c2 == pytest.approx(e2, rel=1e-12)
+
+
+# --- the preconditioning tests of Sec. 6: A^alpha x = b, (I + A^{2 alpha}) x = b, (A^alpha + A^-alpha) x = b
+
+PRECOND_EQS = {  # name: (c_neg, c_pos, c0, beta as a multiple of alpha)
+    "A^a": (0.0, 1.0, 0.0, 1.0),
+    "I+A^2a": (0.0, 1.0, 1.0, 2.0),
+    "A^a+A^-a": (1.0, 1.0, 0.0, 1.0),
+}
+
+
+@pytest.mark.parametrize("eq", sorted(PRECOND_EQS))
+@pytest.mark.parametrize("alpha", [0.5, 0.1])
+@pytest.mark.parametrize("shape", [(7, 9), (5, 4, 3)])
+def test_general_symbol_solve_matches_brute_force(eq, alpha, shape):
+    """The sine-transform solve with the general symbol equals the dense eigendecomposition route."""
+    cn, cp, c0, bm = PRECOND_EQS[eq]
+    f = np.random.default_rng(11).standard_normal(shape)
+    u = exact.solve_full(f, alpha, cn, cp, c0, bm * alpha)
+    v = exact.brute_force(f, alpha, cn, cp, c0, bm * alpha)
+    assert np.linalg.norm(u - v) <= 1e-11 * np.linalg.norm(v)
+
+
+@pytest.mark.parametrize("shape", [(7, 9), (5, 4, 3)])
+def test_identity_plus_laplacian_without_fractional_powers(shape):
+    """alpha = 1/2 in (I + A^{2 alpha}) x = b is (I + A) x = b: a plain sparse solve, no
+    eigendecomposition, no sine transform."""
+    f = np.random.default_rng(12).standard_normal(shape)
+    A = exact.laplacian_full(shape)
+    x = np.linalg.solve(np.eye(A.shape[0]) + A, f.ravel()).reshape(shape)
+    u = exact.solve_full(f, 0.5, 0.0, 1.0, 1.0, 1.0)
+    assert np.linalg.norm(u - x) <= 1e-12 * np.linalg.norm(x)
+
+
+@pytest.mark.parametrize("shape", [(7, 9), (5, 4, 3)])
+def test_half_power_applied_twice_is_the_laplacian(shape):
+    """Solving A^{1/2} y = b and then A^{1/2} x = y gives A x = b (dense solve of A)."""
+    f = np.random.default_rng(13).standard_normal(shape)
+    y = exact.solve_full(f, 0.5, 0.0, 1.0)
+    x = exact.solve_full(y, 0.5, 0.0, 1.0)
+    A = exact.laplacian_full(shape)
+    ref = np.linalg.solve(A, f.ravel()).reshape(shape)
+    assert np.linalg.norm(x - ref) <= 1e-11 * np.linalg.norm(ref)
