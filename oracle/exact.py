@@ -13,7 +13,7 @@ which is what every routine below evaluates, each by a different route.
 import numpy as np
 import scipy.fft as sfft
 
-from . import spectral
+from . import spectral, tensor
 
 
 def solve_full(f, alpha, c_neg, c_pos, c0=0.0, beta=None):
@@ -141,6 +141,17 @@ def tucker_error_slabs(weights, factors, alpha, c_neg, c_pos, core, tfactors, sl
         err2 += float(np.sum((xh - uh) ** 2))
         u2 += float(np.sum(uh * uh))
     return err2, u2
+
+
+def precond_rank_r(ns, r, alpha, c_neg, c_pos, c0=0.0, beta=None):
+    """The rank-r preconditioner of the Sec. 6 iteration counts on the full grid: the inverse
+    symbol 1/s(rho) (the spectral values of the operator's inverse, eqn:DiagFLaplace3D) truncated
+    by the HOSVD to mode ranks <= r.  In 2D this is the rank-r SVD of the n x n matrix
+    1/s(lambda_i + lambda_j) (the paper's 2D reduced SVD); in 3D the Tucker rank-r reading of
+    its multigrid Tucker approximation."""
+    P = 1.0 / spectral.symbol(spectral.rho_grid(ns), alpha, c_neg, c_pos, c0, beta)
+    core, U, _ = tensor.hosvd_truncate(P, 0.0, cap=r)
+    return tensor.tucker_full(core, U)
 
 
 def state_full(u, alpha, beta):

@@ -312,3 +312,44 @@ def test_half_power_applied_twice_is_the_laplacian(shape):
     A = exact.laplacian_full(shape)
     ref = np.linalg.solve(A, f.ravel()).reshape(shape)
     assert np.linalg.norm(x - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+# ---------------------------------------------------------------- rank-r preconditioner (Sec. 6)
+@pytest.mark.parametrize("eq", sorted(PRECOND_EQS))
+@pytest.mark.parametrize("r", [1, 3, 6])
+def test_rank_r_preconditioner_2d_is_the_best_rank_r_matrix(eq, r):
+    """2D: the truncated HOSVD of the symmetric matrix P = 1/s(lambda_i + lambda_j) is its best
+    rank-r approximation, so its Frobenius error is the tail of the eigenvalue magnitudes
+    (Eckart-Young), taken here from a symmetric eigensolver rather than an SVD."""
+    cn, cp, c0, bm = PRECOND_EQS[eq]
+    n, alpha = 40, 0.5
+    P = 1.0 / spectral.symbol(spectral.rho_grid((n, n)), alpha, cn, cp, c0, bm * alpha)
+    Pr = exact.precond_rank_r((n, n), r, alpha, cn, cp, c0, bm * alpha)
+    lam = np.sort(np.abs(np.linalg.eigvalsh(P)))[::-1]
+    want = np.sqrt(np.sum(lam[r:] ** 2))
+    assert abs(np.linalg.norm(P - Pr) - want) <= 1e-10 * np.linalg.norm(P) + 1e-6 * want
+    assert np.linalg.matrix_rank(Pr, tol=1e-12 * np.linalg.norm(P)) == r
+    assert np.allclose(Pr, Pr.T, atol=1e-13 * np.abs(P).max())
+
+
+@pytest.mark.parametrize("r", [2, 4])
+def test_rank_r_preconditioner_3d_within_hosvd_bounds(r):
+    """3D: the HOSVD truncation error lies between the largest and the sum of the discarded mode
+    singular-value tails (the quasi-optimality bounds of the HOSVD)."""
+    ns, alpha = (12, 10, 9), 0.1
+    P = 1.0 / spectral.symbol(spectral.rho_grid(ns), alpha, 1.0, 1.0, 0.0, alpha)
+    Pr = exact.precond_rank_r(ns, r, alpha, 1.0, 1.0, 0.0, alpha)
+    tails = []
+    for l in range(3):
+        M = np.moveaxis(P, l, 0).reshape(ns[l], -1)
+        ev = np.sort(np.linalg.eigvalsh(M @ M.T))[::-1]
+        tails.append(np.sum(np.clip(ev[r:], 0, None)))
+    e2 = np.linalg.norm(P - Pr) ** 2
+    assert max(tails) * (1 - 1e-9) <= e2 <= sum(tails) * (1 + 1e-9)
+
+
+def test_rank_r_preconditioner_full_rank_is_exact():
+    """r at least the grid size: nothing is discarded, the inverse symbol is returned."""
+    ns = (6, 5, 4)
+    P = 1.0 / spectral.symbol(spectral.rho_grid(ns), 0.5, 0.0, 1.0, 1.0, 1.0)
+    assert np.abs(exact.precond_rank_r(ns, 6, 0.5, 0.0, 1.0, 1.0, 1.0) - P).max() <= 1e-13 * P.max()
