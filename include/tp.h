@@ -108,16 +108,21 @@ typedef struct {
  * ------------------------------------------------------------------------- */
 
 /* In the sine basis A_2 is diagonal with entries s(rho), rho = sum_l lambda_{i_l},
- * s = c_neg rho^-alpha + c_pos rho^alpha.  Lemma 4.1 is applied to A_2 itself:
- * s(rho) = rho * g(rho), g = c_neg rho^-(1+alpha) + c_pos rho^-(1-alpha), and g is
- * an exponential sum sum_k w_k exp(-tau_k rho), so the operator symbol is a
- * canonical tensor of rank d*K in spectral coordinates.  The preconditioner is a
- * rank-K' exponential sum approximating 1/s (a low Kronecker rank approximation
- * of A_2^-1, Sec. 1).
+ * s = c0 + c_neg rho^-alpha + c_pos rho^beta (beta = alpha for the control equation;
+ * c0 and beta != alpha give the test operators A^alpha, I + A^(2 alpha) and
+ * A^alpha + A^-alpha of the preconditioning experiments, Sec. 6 eq:precond_ex1-3).
+ * Lemma 4.1 is applied to A_2 itself: s(rho) = c0 + rho * g(rho),
+ * g = c_neg rho^-(1+alpha) + c_pos rho^-(1-beta), and g is an exponential sum
+ * sum_k w_k exp(-tau_k rho), so the operator symbol is a canonical tensor of rank
+ * d*K (+1 for the constant c0, whose factors are all ones) in spectral coordinates.
+ * For beta = 1 the term c_pos rho is kept exact as an exponential with tau = 0
+ * (the d one-dimensional Laplacians), and only the c_neg part is fitted.  The
+ * preconditioner is a rank-K' exponential sum approximating 1/s (a low Kronecker
+ * rank approximation of A_2^-1, Sec. 1).
  *
- * method TP_SYM_SINC: g by the sinc rule u_k = k*h, k = -sinc_kl..sinc_kr,
- *   t = log(1+e^u), weights h phi'(u) [c_neg t^alpha/Gamma(1+alpha) rho0^-(1+alpha)
- *   + c_pos t^-alpha/Gamma(1-alpha) rho0^-(1-alpha)], rho0 = d*lambda_1.
+ * method TP_SYM_SINC (c0 = 0, beta = alpha only): g by the sinc rule u_k = k*h,
+ *   k = -sinc_kl..sinc_kr, t = log(1+e^u), weights h phi'(u) [c_neg t^alpha/Gamma(1+alpha)
+ *   rho0^-(1+alpha) + c_pos t^-alpha/Gamma(1-alpha) rho0^-(1-alpha)], rho0 = d*lambda_1.
  * method TP_SYM_FIT: g by relative-error least squares on op_terms geometric
  *   exponents (fewer terms for the same accuracy).
  * The preconditioner always uses the least-squares fit with pre_terms exponents. */
@@ -128,12 +133,20 @@ typedef struct {
   double c_neg;        /* >= 0 */
   double c_pos;        /* >= 0, c_neg + c_pos > 0 */
   int32_t method;      /* tp_symbol_method */
-  int32_t op_terms;    /* TP_SYM_FIT: K (0 = 32) */
-  int32_t pre_terms;   /* K' (0 = 12) */
+  int32_t op_terms;    /* TP_SYM_FIT: K (0 = 32); ignored when nothing is left to fit */
+  int32_t pre_terms;   /* K' in [1, 64] (0 = 12) */
   int32_t sinc_kl;     /* TP_SYM_SINC (0 = library default) */
   int32_t sinc_kr;
   double sinc_h;
   int32_t prec;        /* precision of the factor matrices (tp_precision) */
+  double c0;           /* >= 0: constant term of the symbol (identity part of the operator) */
+  double beta;         /* exponent of the c_pos term, in (0, 1]; 0 = alpha */
+  int32_t pre_rank;    /* 0: the preconditioner is the pre_terms-term exponential sum (rank K');
+                        * r in [1,16]: that sum recompressed by its truncated HOSVD to mode ranks
+                        * <= r (in 2D the rank-r SVD of the matrix 1/s(lambda_i + lambda_j)), the
+                        * Tucker core spread back to canonical rank r (2D) or r^2 (3D): the rank-r
+                        * preconditioner of the Sec. 6 iteration counts.  Its err is then the max of
+                        * |p s - 1| over a geometric lattice of grid points. */
 } tp_symbol_desc;
 
 /* Build the operator symbol and the preconditioner symbol on the GPU.  Both are
@@ -153,7 +166,8 @@ tp_status tp_state_symbol_build(tp_ctx* ctx, const tp_symbol_desc* desc, tp_symb
 /* rank (host): canonical rank of the symbol; err (host): its measured error. */
 tp_status tp_symbol_info(const tp_symbol* sym, int32_t* rank, double* err);
 /* Values of the symbol at `count` multi-indices idx (device, count x d int32,
- * 0-based, row i = point i) into out (device, count doubles). */
+ * 0-based, row i = point i) into out (device, count doubles).  A point outside the
+ * grid gives NaN. */
 tp_status tp_symbol_eval(tp_ctx* ctx, const tp_symbol* sym, int32_t count,
                          const int32_t* idx, double* out);
 
@@ -210,12 +224,22 @@ tp_status tp_eval_grid(tp_ctx* ctx, const tp_tensor* x, const int32_t* const* ro
 /* ---------------------------------------------------------------------------
  * PCG  (Algorithm alg:pcg)
  * ------------------------------------------------------------------------- */
+typedef enum {
+  TP_STOP_ERROR = 0,     /* ||Z|| <= tau ||X||, Z = trunc(pre(R)) the preconditioned residual */
+  TP_STOP_RESIDUAL = 1   /* ||R|| <= tau ||B||, the relative residual of the Sec. 6 iteration counts */
+} tp_stop_rule;
+
 typedef struct {
-  double tau;        /* stop when ||Z|| <= tau ||X||, Z = trunc(pre(R)) the preconditioned residual */
+  double tau;        /* stopping tolerance of stop_rule */
   int32_t kmax;      /* iteration limit (paper: 100) */
   double trunc_tol;  /* relative truncation tolerance epsilon of trunc */
   int32_t cap;       /* mode-rank cap of every iterate (<= x->cap) */
   int32_t true_residual; /* nonzero: also compute ||B - A_2 X||/||B|| */
+  int32_t stop_rule; /* tp_stop_rule */
+  int32_t recursive_residual; /* 0: R = trunc(B - fun(X)) recomputed each step (default);
+                               * 1: R = trunc(R - alpha trunc(fun(P))) as printed in Algorithm
+                               * alg:pcg (it does not see the truncation error of X, so with
+                               * TP_STOP_RESIDUAL it reaches tau below the floor set by it) */
 } tp_pcg_opts;
 
 typedef struct {
@@ -225,13 +249,15 @@ typedef struct {
   double rel_res;    /* ||R||/||B|| of the recursive residual */
   double true_rel_res;  /* only if requested, else -1 */
   double op_applies; /* number of operator/preconditioner products */
-  double err_est;    /* ||Z||/||X|| of the returned X (the stopping quantity) */
+  double err_est;    /* the stopping quantity of the returned X: ||Z||/||X|| or ||R||/||B|| */
 } tp_pcg_info;
 
 /* Solve A_2 x = b with the operator symbol `op`, the preconditioner symbol `pre`
  * and X0 = 0.  Each step: alpha = <R,Z>/<P,fun(P)> with fun(P) kept exact, X = trunc(X + alpha P),
- * R = trunc(B - fun(X)) (recomputed, one sketched sum), Z = trunc(pre(R)), stop when
- * ||Z|| <= tau ||X||, P = trunc(Z + beta P).  Iterates are Tucker tensors (the mixed Tucker-canonical route of
+ * R = trunc(B - fun(X)) (recomputed, one sketched sum; or the recursive update of
+ * opts->recursive_residual), stop when ||R|| <= tau ||B||
+ * (TP_STOP_RESIDUAL), Z = trunc(pre(R)), stop when ||Z|| <= tau ||X|| (TP_STOP_ERROR),
+ * P = trunc(Z + beta P).  Iterates are Tucker tensors (the mixed Tucker-canonical route of
  * Sec. 5); every update is truncated as in Algorithm alg:pcg.  x->prec selects
  * the arithmetic; op and pre must have been built with that precision.
  * Without convergence (kmax reached, or the estimate grown 8-fold over its minimum or not

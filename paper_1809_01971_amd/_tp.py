@@ -7,6 +7,7 @@ import numpy as np
 TP_OK, TP_EINVAL, TP_ENOMEM, TP_ENOCONV, TP_ERANK, TP_EHIP = range(6)
 TP_FP64, TP_MIXED = 0, 1
 TP_SYM_FIT, TP_SYM_SINC = 0, 1
+TP_STOP_ERROR, TP_STOP_RESIDUAL = 0, 1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
@@ -40,12 +41,14 @@ class tp_symbol_desc(C.Structure):
     _fields_ = [("d", C.c_int32), ("n", C.c_int32 * 3), ("alpha", C.c_double), ("c_neg", C.c_double),
                 ("c_pos", C.c_double), ("method", C.c_int32), ("op_terms", C.c_int32),
                 ("pre_terms", C.c_int32), ("sinc_kl", C.c_int32), ("sinc_kr", C.c_int32),
-                ("sinc_h", C.c_double), ("prec", C.c_int32)]
+                ("sinc_h", C.c_double), ("prec", C.c_int32), ("c0", C.c_double), ("beta", C.c_double),
+                ("pre_rank", C.c_int32)]
 
 
 class tp_pcg_opts(C.Structure):
     _fields_ = [("tau", C.c_double), ("kmax", C.c_int32), ("trunc_tol", C.c_double), ("cap", C.c_int32),
-                ("true_residual", C.c_int32)]
+                ("true_residual", C.c_int32), ("stop_rule", C.c_int32),
+                ("recursive_residual", C.c_int32)]
 
 
 class tp_pcg_info(C.Structure):
@@ -200,12 +203,13 @@ class Context:
 
     # ---- symbols
     def symbol_build(self, d, n, alpha, c_neg, c_pos, prec=TP_FP64, method=TP_SYM_FIT, op_terms=0,
-                     pre_terms=0, sinc_kl=0, sinc_kr=0, sinc_h=0.0):
+                     pre_terms=0, sinc_kl=0, sinc_kr=0, sinc_h=0.0, c0=0.0, beta=0.0, pre_rank=0):
         desc = tp_symbol_desc()
         desc.d = d
         for m in range(3):
             desc.n[m] = n if m < d else 0
         desc.alpha, desc.c_neg, desc.c_pos = alpha, c_neg, c_pos
+        desc.c0, desc.beta, desc.pre_rank = c0, beta, pre_rank
         desc.method, desc.op_terms, desc.pre_terms = method, op_terms, pre_terms
         desc.sinc_kl, desc.sinc_kr, desc.sinc_h = sinc_kl, sinc_kr, sinc_h
         desc.prec = prec
@@ -283,10 +287,11 @@ class Context:
             list(range(len(rows)))[::-1])
 
     def pcg_solve(self, op, pre, weights, factors, x, tau, kmax, trunc_tol, cap, sketch, true_residual=False,
-                  allow=(TP_ERANK, TP_ENOCONV)):
+                  allow=(TP_ERANK, TP_ENOCONV), stop_rule=0, recursive_residual=False):
         keep, cp = cp_struct(weights, factors)
         sk, keep2 = sketch_struct(sketch)
-        o = tp_pcg_opts(tau, kmax, trunc_tol, cap, 1 if true_residual else 0)
+        o = tp_pcg_opts(tau, kmax, trunc_tol, cap, 1 if true_residual else 0, stop_rule,
+                        1 if recursive_residual else 0)
         info = tp_pcg_info()
         st = _check(self.lib.tp_pcg_solve(self.h, op.h, pre.h, C.byref(cp), C.byref(x.s), C.byref(o),
                                           C.byref(sk), C.byref(info)), allow=allow)
@@ -327,7 +332,7 @@ def batch_solve(ctx, problems, settings, sketches, streams=8, workspace_per_stre
         X = Tensor(p.d, p.n, s["cap"], s["prec"])
         outs.append(X)
         tens[i] = X.s
-        opts[i] = tp_pcg_opts(s["tau"], 100, s["eps"], s["cap"], 0)
+        opts[i] = tp_pcg_opts(s["tau"], 100, s["eps"], s["cap"], 0, 0, 0)
         sk, k2 = sketch_struct(sketches[p.n])
         sks[i] = sk
     _check(ctx.lib.tp_pcg_solve_batched(ctx.h, cnt, descs, cps, tens, opts, sks, infos, streams,

@@ -84,8 +84,11 @@ struct tp_symbol {
   int d = 0, n[3] = {0, 0, 0}, prec = 0;
   int kind = 0;          // 0: operator rho*g, 1: preconditioner
   int K = 0;             // exponentials
-  int R = 0;             // canonical rank (d*K for the operator)
+  int R = 0;             // canonical rank (d*K for the operator, +1 with a constant term)
   double err = 0;
+  double c0 = 0;         // constant term of the operator symbol (factors all ones)
+  double wexact = 0;     // weight of the exact tau = 0 exponential (c_pos rho for beta = 1)
+  int tucker = 0;        // > 0: rank-r recompressed preconditioner (general canonical factors)
   double* weights = nullptr;   // R (device)
   void* factors[3] = {nullptr, nullptr, nullptr};  // n x R (device, T)
   double* tau = nullptr;       // K
@@ -1150,6 +1153,10 @@ tp_status build_factors(tp_ctx* c, tp_symbol* s) {
       for (int blk = 0; blk < s->d; ++blk)
         HIPCHK(expfactors<T>(s->lam[m], s->n[m], s->tau, s->K, F + (size_t)s->n[m] * s->K * blk, s->n[m],
                              blk == m ? 1 : 0, c->stream));
+      // constant term: exp(-0 * lambda) = 1 in every mode (tau holds a trailing zero)
+      if (s->R > s->d * s->K)
+        HIPCHK(expfactors<T>(s->lam[m], s->n[m], s->tau + s->K, 1, F + (size_t)s->n[m] * s->K * s->d, s->n[m], 0,
+                             c->stream));
     } else {
       HIPCHK(expfactors<T>(s->lam[m], s->n[m], s->tau, s->K, F, s->n[m], 0, c->stream));
     }
@@ -1158,11 +1165,140 @@ tp_status build_factors(tp_ctx* c, tp_symbol* s) {
   s->owned.push_back(s->weights);
   for (int blk = 0; blk < (s->kind == 0 ? s->d : 1); ++blk)
     HIPCHK(hipMemcpyAsync(s->weights + (size_t)blk * s->K, s->w, sizeof(double) * s->K, hipMemcpyDeviceToDevice, c->stream));
+  if (s->kind == 0 && s->R > s->d * s->K)
+    HIPCHK(hipMemcpyAsync(s->weights + (size_t)s->d * s->K, &s->c0, sizeof(double), hipMemcpyHostToDevice, c->stream));
   return TP_OK;
 }
 
-// Least-squares exponential sum for f (kind 0: g, 1: 1/s) over candidates; keeps the best.
-tp_status fit_expsum(tp_ctx* c, int kind, double alpha, double cn, double cp, double rho0, double B, int K,
+// Rank-r preconditioner of the Sec. 6 tests: the truncated HOSVD of the exponential sum (a
+// canonical tensor of rank K') at mode ranks <= r, which in 2D is the rank-r SVD of the matrix
+// 1/s(lambda_i + lambda_j), then the Tucker core spread back into canonical form: rank r0 in 2D
+// (factors U0 and U1 G^T), r0*r1 in 3D (column (a,b): U0[:,a], U1[:,b], sum_c G[a,b,c] U2[:,c]).
+// Factors are formed in FP64 and stored in the symbol's precision.
+template <typename T>
+tp_status recompress_pre(tp_ctx* c, tp_symbol* s, int r) {
+  WsScope scope(c);
+  const int d = s->d, K = s->K;
+  tp_cp cp{};
+  cp.d = d;
+  cp.rank = K;
+  cp.weight = s->w;
+  for (int m = 0; m < d; ++m) {
+    cp.n[m] = s->n[m];
+    double* E;
+    TPCHK(wsalloc(c, (size_t)s->n[m] * K, &E));
+    HIPCHK(expfactors<double>(s->lam[m], s->n[m], s->tau, K, E, s->n[m], 0, c->stream));
+    cp.factor[m] = E;
+  }
+  tp_tensor t{};
+  t.d = d;
+  t.cap = r;
+  t.prec = TP_FP64;
+  double* core;
+  TPCHK(wsalloc(c, (size_t)r * r * (d == 3 ? r : 1), &core));
+  t.core = core;
+  for (int m = 0; m < d; ++m) {
+    t.n[m] = s->n[m];
+    double* U;
+    TPCHK(wsalloc(c, (size_t)s->n[m] * r, &U));
+    t.factor[m] = U;
+  }
+  bool capped = false;
+  TPCHK(from_cp_impl<double>(c, &cp, &t, 1e-15, &capped));
+  const int r0 = t.rank[0], r1 = t.rank[1], r2 = d == 3 ? t.rank[2] : 1;
+  const int R = d == 2 ? r0 : r0 * r1;
+  if (R < 1) return fail(TP_EINVAL, "preconditioner recompression produced rank 0");
+  const double* U[3] = {(const double*)t.factor[0], (const double*)t.factor[1],
+                        d == 3 ? (const double*)t.factor[2] : nullptr};
+  double* last;  // FP64 factor of the last mode: U_last times the core unfolding
+  const int nl = s->n[d - 1];
+  TPCHK(wsalloc(c, (size_t)nl * R, &last));
+  // core column-major: 2D G[a + r0 b]; 3D G[(a + r0 b) + r0 r1 c], i.e. an (R x r_last) matrix
+  TPCHK((mm<double, double, double, double>(c, false, true, nl, R, d == 2 ? r1 : r2, 1.0, U[d - 1], nl, core, R, 0.0,
+                                            last, nl)));
+  for (int m = 0; m < d; ++m) {
+    T* F = nullptr;
+    HIPCHK(hipMalloc(&F, sizeof(T) * (size_t)s->n[m] * R));
+    s->owned.push_back(F);
+    s->factors[m] = F;
+    const int n = s->n[m];
+    if (m == d - 1) {
+      HIPCHK((convert<double, T>(last, F, (long)n * R, c->stream)));
+    } else if (m == 0) {
+      // U0 once (2D) or repeated for every b (3D)
+      for (int b = 0; b < (d == 3 ? r1 : 1); ++b)
+        HIPCHK((copy2d<double, T>(n, r0, U[0], n, F + (size_t)n * r0 * b, n, 1.0, c->stream)));
+    } else {
+      // 3D mode 1: column b of U1 repeated r0 times (input leading dimension 0)
+      for (int b = 0; b < r1; ++b)
+        HIPCHK((copy2d<double, T>(n, r0, U[1] + (size_t)n * b, 0, F + (size_t)n * r0 * b, n, 1.0, c->stream)));
+    }
+  }
+  HIPCHK(hipMalloc(&s->weights, sizeof(double) * R));
+  s->owned.push_back(s->weights);
+  std::vector<double> ones(R, 1.0);
+  HIPCHK(hipMemcpyAsync(s->weights, ones.data(), sizeof(double) * R, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));  // the host vector and the workspace are released here
+  s->R = R;
+  s->tucker = r;
+  return TP_OK;
+}
+
+// max |p s - 1| of a recompressed preconditioner p over a lattice of grid points whose indices
+// are geometric in every mode (64 per mode in 2D, 16 in 3D), s the exact symbol of fn.
+tp_status pre_lattice_error(tp_ctx* c, const tp_symbol* s, const SymFn& fn, double* err) {
+  WsScope scope(c);
+  const int d = s->d, L = d == 2 ? 64 : 16;
+  std::vector<int> ax[3];
+  std::vector<double> lam[3];
+  for (int m = 0; m < d; ++m) {
+    const int n = s->n[m];
+    const double h = 1.0 / (n + 1.0);
+    for (int k = 0; k < L; ++k) {
+      int i = (int)std::floor(std::pow((double)n, (double)k / (L - 1))) - 1;
+      i = std::min(std::max(i, 0), n - 1);
+      ax[m].push_back(i);
+      lam[m].push_back(4.0 / (h * h) * std::pow(std::sin(M_PI * (i + 1) * h / 2), 2));
+    }
+  }
+  const int cnt = d == 2 ? L * L : L * L * L;
+  std::vector<int> idx((size_t)cnt * d);
+  std::vector<double> sv(cnt), pv(cnt);
+  for (int p = 0; p < cnt; ++p) {
+    int q = p;
+    double rho = 0;
+    for (int m = 0; m < d; ++m) {
+      idx[(size_t)p * d + m] = ax[m][q % L];
+      rho += lam[m][q % L];
+      q /= L;
+    }
+    sv[p] = fn.c0 + (fn.cn > 0 ? fn.cn * std::pow(rho, -fn.alpha) : 0.0) + (fn.cp > 0 ? fn.cp * std::pow(rho, fn.beta) : 0.0);
+  }
+  int* di;
+  double* dout;
+  TPCHK(wsalloc(c, idx.size(), &di));
+  TPCHK(wsalloc(c, (size_t)cnt, &dout));
+  HIPCHK(hipMemcpyAsync(di, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice, c->stream));
+  if (s->prec == TP_FP64) {
+    const double* F[3] = {(const double*)s->factors[0], (const double*)s->factors[1], (const double*)s->factors[2]};
+    HIPCHK(cp_eval<double>(d, di, cnt, s->n, F, s->R, s->weights, dout, c->stream));
+  } else {
+    const float* F[3] = {(const float*)s->factors[0], (const float*)s->factors[1], (const float*)s->factors[2]};
+    HIPCHK(cp_eval<float>(d, di, cnt, s->n, F, s->R, s->weights, dout, c->stream));
+  }
+  TPCHK(sync_to_host(c, dout, sizeof(double) * cnt, pv.data()));
+  double mx = 0;
+  for (int p = 0; p < cnt; ++p) {
+    double e = std::fabs(pv[p] * sv[p] - 1.0);
+    if (!(e <= mx)) mx = e;
+  }
+  *err = mx;
+  return TP_OK;
+}
+
+// Least-squares exponential sum for f (kind 0: g, 1: 1/s, 2: the state symbol) over candidates;
+// keeps the best.
+tp_status fit_expsum(tp_ctx* c, int kind, const SymFn& f, double rho0, double B, int K,
                      const std::vector<FitCand>& cands, double* tau_out, double* w_out, double* err_out) {
   WsScope scope(c);
   const int m = 1000, nc = (int)cands.size();
@@ -1183,7 +1319,7 @@ tp_status fit_expsum(tp_ctx* c, int kind, double alpha, double cn, double cp, do
   FitCand* hc = reinterpret_cast<FitCand*>(c->hmap + tp_ctx::kMap / 4);
   for (int ci = 0; ci < nc; ++ci) hc[ci] = cands[ci];
   cd = reinterpret_cast<FitCand*>(c->dmap + tp_ctx::kMap / 4);
-  HIPCHK(fit_design(kind, alpha, cn, cp, rho0, B, K, m, cd, nc, A, t, c->stream));
+  HIPCHK(fit_design(kind, f, rho0, B, K, m, cd, nc, A, t, c->stream));
   // column scaling: cn_ = 1/||A_k|| from the Gram diagonal; scaled Gram = D G D
   GemmArgs<double, double, double, double> g;
   g.M = K; g.N = K; g.K = m; g.batch = nc;
@@ -1218,7 +1354,7 @@ tp_status fit_expsum(tp_ctx* c, int kind, double alpha, double cn, double cp, do
   HIPCHK(fit_solve(K, nc, ew, E, bvec, cn_, 1e-15, wsol, c->stream));
   (void)err;
   double* derr = c->dmap;  // errors straight to the mapped host scratch
-  HIPCHK(fit_error(kind, alpha, cn, cp, rho0, B, K, t, wsol, nc, 4096, derr, c->stream));
+  HIPCHK(fit_error(kind, f, rho0, B, K, t, wsol, nc, 4096, derr, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   const double* herr = c->hmap;
   int best = 0;
@@ -1346,13 +1482,23 @@ tp_status tp_symbol_build(tp_ctx* c, const tp_symbol_desc* desc, tp_symbol** op,
   if (!(D.alpha > 0.0 && D.alpha <= 1.0)) return fail(TP_EINVAL, "alpha=%g must be in (0,1]", D.alpha);
   if (!(D.c_neg >= 0.0) || !(D.c_pos >= 0.0) || !(D.c_neg + D.c_pos > 0.0))
     return fail(TP_EINVAL, "coefficients c_neg=%g c_pos=%g must be >= 0 and not both 0", D.c_neg, D.c_pos);
+  if (!(D.c0 >= 0.0)) return fail(TP_EINVAL, "c0=%g must be >= 0", D.c0);
+  const double beta = D.beta == 0.0 ? D.alpha : D.beta;
+  if (!(beta > 0.0 && beta <= 1.0)) return fail(TP_EINVAL, "beta=%g must be in (0,1]", D.beta);
   if (D.prec != TP_FP64 && D.prec != TP_MIXED) return fail(TP_EINVAL, "unknown precision %d", D.prec);
   for (int m = 0; m < D.d; ++m) TPCHK(check_grid(D.n[m], D.prec));
   int Kop = D.op_terms > 0 ? D.op_terms : 32;
   int Kpre = D.pre_terms > 0 ? D.pre_terms : 12;
   if (D.method == TP_SYM_FIT && (Kop < 2 || Kop > 64)) return fail(TP_EINVAL, "op_terms=%d must be in [2,64]", Kop);
-  if (Kpre < 2 || Kpre > 64) return fail(TP_EINVAL, "pre_terms=%d must be in [2,64]", Kpre);
+  if (Kpre < 1 || Kpre > 64) return fail(TP_EINVAL, "pre_terms=%d must be in [1,64]", Kpre);
+  if (D.pre_rank < 0 || D.pre_rank > 16) return fail(TP_EINVAL, "pre_rank=%d must be in [0,16]", D.pre_rank);
   if (D.method != TP_SYM_FIT && D.method != TP_SYM_SINC) return fail(TP_EINVAL, "unknown method %d", D.method);
+  if (D.method == TP_SYM_SINC && (D.c0 != 0.0 || beta != D.alpha))
+    return fail(TP_EINVAL, "the sinc rule covers c0 = 0 and beta = alpha only");
+  // beta = 1: c_pos rho is exact (a tau = 0 exponential); what is left to fit is c_neg rho^-(1+alpha)
+  const bool exact_pos = beta == 1.0 && D.c_pos > 0.0;
+  const SymFn fn{D.c0, D.c_neg, D.c_pos, D.alpha, beta, exact_pos ? 0 : 1};
+  const bool fit_op = !(exact_pos && D.c_neg == 0.0);
   int kl = D.sinc_kl > 0 ? D.sinc_kl : 60, kr = D.sinc_kr > 0 ? D.sinc_kr : 20;
   double hh = D.sinc_h > 0 ? D.sinc_h : 0.55;
   if (D.method == TP_SYM_SINC && kl + kr + 2 > 2048) return fail(TP_EINVAL, "sinc rule too long");
@@ -1389,22 +1535,35 @@ tp_status tp_symbol_build(tp_ctx* c, const tp_symbol_desc* desc, tp_symbol** op,
   // operator
   {
     tp_symbol* so = s[0];
-    int K = D.method == TP_SYM_FIT ? Kop : kl + kr + 1 + (std::fabs(1.0 - D.alpha) < 1e-15 ? 1 : 0);
+    const int Kfit = D.method == TP_SYM_FIT ? (fit_op ? Kop : 0) : kl + kr + 1 + (std::fabs(1.0 - D.alpha) < 1e-15 ? 1 : 0);
+    const int K = Kfit + (D.method == TP_SYM_FIT && exact_pos ? 1 : 0);
     so->K = K;
-    so->R = D.d * K;
-    if (hipMalloc(&so->tau, sizeof(double) * K) != hipSuccess || hipMalloc(&so->w, sizeof(double) * K) != hipSuccess)
+    so->c0 = D.c0;
+    so->R = D.d * K + (D.c0 > 0.0 ? 1 : 0);
+    // tau and w hold the K terms and a trailing zero exponent (the constant term's factors)
+    if (hipMalloc(&so->tau, sizeof(double) * (K + 1)) != hipSuccess ||
+        hipMalloc(&so->w, sizeof(double) * (K + 1)) != hipSuccess)
       return cleanup(fail(TP_ENOMEM, "hipMalloc failed"));
     so->owned.push_back(so->tau);
     so->owned.push_back(so->w);
+    if (hipMemsetAsync(so->tau, 0, sizeof(double) * (K + 1), c->stream) != hipSuccess)
+      return cleanup(fail(TP_EHIP, "memset failed"));
     if (D.method == TP_SYM_FIT) {
-      std::vector<FitCand> cands;
-      for (double a : {-1.5, -1.0, -0.5})
-        for (double b : {1.75, 2.25, 2.75}) cands.push_back({a, b});
       double e = 0;
-      tp_status st = fit_expsum(c, 0, D.alpha, D.c_neg, D.c_pos, rho0, B, K, cands, so->tau, so->w, &e);
-      if (st != TP_OK) return cleanup(st);
-      // the fit is in the scaled variable y = rho/rho0: tau = t/rho0
-      if (scale(so->tau, K, 1.0 / rho0, c->stream) != hipSuccess) return cleanup(fail(TP_EHIP, "scale failed"));
+      if (Kfit > 0) {
+        std::vector<FitCand> cands;
+        for (double a : {-1.5, -1.0, -0.5})
+          for (double b : {1.75, 2.25, 2.75}) cands.push_back({a, b});
+        tp_status st = fit_expsum(c, 0, fn, rho0, B, Kfit, cands, so->tau, so->w, &e);
+        if (st != TP_OK) return cleanup(st);
+        // the fit is in the scaled variable y = rho/rho0: tau = t/rho0
+        if (scale(so->tau, Kfit, 1.0 / rho0, c->stream) != hipSuccess) return cleanup(fail(TP_EHIP, "scale failed"));
+      }
+      if (exact_pos) {
+        so->wexact = D.c_pos;
+        if (hipMemcpyAsync(so->w + Kfit, &so->wexact, sizeof(double), hipMemcpyHostToDevice, c->stream) != hipSuccess)
+          return cleanup(fail(TP_EHIP, "copy failed"));
+      }
       so->err = e;
     } else {
       if (sinc_g_nodes(D.alpha, D.c_neg, D.c_pos, rho0, kl, kr, hh, so->tau, so->w, c->stream) != hipSuccess)
@@ -1426,14 +1585,23 @@ tp_status tp_symbol_build(tp_ctx* c, const tp_symbol_desc* desc, tp_symbol** op,
     for (double a : {-2.5, -2.0, -1.5})
       for (double b : {0.5, 1.0, 1.5, 2.0, 2.5}) cands.push_back({a, b});
     double e = 0;
-    tp_status st = fit_expsum(c, 1, D.alpha, D.c_neg, D.c_pos, rho0, B, K, cands, sp->tau, sp->w, &e);
+    tp_status st = fit_expsum(c, 1, fn, rho0, B, K, cands, sp->tau, sp->w, &e);
     if (st != TP_OK) return cleanup(st);
     if (scale(sp->tau, K, 1.0 / rho0, c->stream) != hipSuccess) return cleanup(fail(TP_EHIP, "scale failed"));
     sp->err = e;
   }
   // measured error of the operator sum (also for the sinc rule): rho*g vs s on log samples
   for (int i = 0; i < 2; ++i) {
-    tp_status st = D.prec == TP_FP64 ? build_factors<double>(c, s[i]) : build_factors<float>(c, s[i]);
+    tp_status st;
+    if (i == 1 && D.pre_rank > 0)
+      st = D.prec == TP_FP64 ? recompress_pre<double>(c, s[1], D.pre_rank) : recompress_pre<float>(c, s[1], D.pre_rank);
+    else
+      st = D.prec == TP_FP64 ? build_factors<double>(c, s[i]) : build_factors<float>(c, s[i]);
+    if (st != TP_OK) return cleanup(st);
+  }
+  if (D.pre_rank > 0) {
+    // measured error of the recompressed preconditioner: max |p s - 1| over a lattice of grid points
+    tp_status st = pre_lattice_error(c, s[1], fn, &s[1]->err);
     if (st != TP_OK) return cleanup(st);
   }
   if (s[0]->err < 0) {
@@ -1444,7 +1612,7 @@ tp_status tp_symbol_build(tp_ctx* c, const tp_symbol_desc* desc, tp_symbol** op,
     if (hipMemcpyAsync(ts, s[0]->tau, sizeof(double) * s[0]->K, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
         scale(ts, s[0]->K, rho0, c->stream) != hipSuccess)
       return cleanup(fail(TP_EHIP, "scale failed"));
-    if (fit_error(0, D.alpha, D.c_neg, D.c_pos, rho0, B, s[0]->K, ts, s[0]->w, 1, 4096, e, c->stream) != hipSuccess)
+    if (fit_error(0, fn, rho0, B, s[0]->K, ts, s[0]->w, 1, 4096, e, c->stream) != hipSuccess)
       return cleanup(fail(TP_EHIP, "error kernel failed"));
     double he = 0;
     if (sync_to_host(c, e, sizeof(double), &he) != TP_OK) return cleanup(TP_EHIP);
@@ -1501,7 +1669,8 @@ tp_status tp_state_symbol_build(tp_ctx* c, const tp_symbol_desc* desc, tp_symbol
   for (double a : {-1.5, -1.0, -0.5})
     for (double b : {1.75, 2.25, 2.75}) cands.push_back({a, b});
   double e = 0;
-  tp_status st = fit_expsum(c, 2, D.alpha, D.c_neg, 0.0, rho0, B, K, cands, s->tau, s->w, &e);
+  const SymFn fn{0.0, D.c_neg, 0.0, D.alpha, D.alpha, 0};
+  tp_status st = fit_expsum(c, 2, fn, rho0, B, K, cands, s->tau, s->w, &e);
   if (st != TP_OK) return cleanup(st);
   if (scale(s->tau, K, 1.0 / rho0, c->stream) != hipSuccess) return cleanup(fail(TP_EHIP, "scale failed"));
   s->err = e;
@@ -1534,8 +1703,18 @@ tp_status tp_symbol_info(const tp_symbol* s, int32_t* rank, double* err) {
 tp_status tp_symbol_eval(tp_ctx* c, const tp_symbol* s, int32_t count, const int32_t* idx, double* out) {
   if (!c || !s || (count > 0 && (!idx || !out))) return fail(TP_EINVAL, "NULL argument");
   if (count < 0) return fail(TP_EINVAL, "count < 0");
-  HIPCHK(symbol_eval(s->d, idx, count, s->lam[0], s->lam[1], s->d == 3 ? s->lam[2] : s->lam[1], s->kind, s->K,
-                     s->tau, s->w, out, c->stream));
+  if (s->tucker > 0) {
+    if (s->prec == TP_FP64) {
+      const double* F[3] = {(const double*)s->factors[0], (const double*)s->factors[1], (const double*)s->factors[2]};
+      HIPCHK(cp_eval<double>(s->d, idx, count, s->n, F, s->R, s->weights, out, c->stream));
+    } else {
+      const float* F[3] = {(const float*)s->factors[0], (const float*)s->factors[1], (const float*)s->factors[2]};
+      HIPCHK(cp_eval<float>(s->d, idx, count, s->n, F, s->R, s->weights, out, c->stream));
+    }
+    return TP_OK;
+  }
+  HIPCHK(symbol_eval(s->d, idx, count, s->n, s->lam[0], s->lam[1], s->d == 3 ? s->lam[2] : s->lam[1], s->kind,
+                     s->K, s->tau, s->w, s->kind == 0 ? s->c0 : 0.0, out, c->stream));
   return TP_OK;
 }
 
@@ -1740,8 +1919,9 @@ tp_status pcg_impl(tp_ctx* c, const tp_symbol* op, const tp_symbol* pre, const t
   WsScope scope(c);
   const int cap = o->cap;
   const double eps = o->trunc_tol;
-  tp_tensor B, X, R, P, Z, Xb;
+  tp_tensor B, X, R, P, Z, Xb, S;
   TPCHK(make_tensor<T>(c, x, cap, &B));
+  if (o->recursive_residual) TPCHK(make_tensor<T>(c, x, cap, &S));
   TPCHK(make_tensor<T>(c, x, cap, &X));
   TPCHK(make_tensor<T>(c, x, cap, &Xb));
   TPCHK(make_tensor<T>(c, x, cap, &R));
@@ -1778,8 +1958,9 @@ tp_status pcg_impl(tp_ctx* c, const tp_symbol* op, const tp_symbol* pre, const t
   int k = 0;
   for (; k < o->kmax; ++k) {
     // S = fun(P) stays in exact factored form (canonical symbol times P): <P,S> is computed
-    // without truncation, and the residual is recomputed from X each step, R = trunc(B - fun(X)),
-    // so residual components a truncation drops are seen again at the next step
+    // without truncation, and by default the residual is recomputed from X each step,
+    // R = trunc(B - fun(X)), so residual components a truncation drops are seen again at the
+    // next step
     double ps = 0;
     TPCHK(inner_sym_impl<T>(c, &P, op, &P, &ps));
     if (!(ps > 0)) return fail(TP_ENOCONV, "PCG breakdown: <P,S> = %g", ps);
@@ -1793,7 +1974,16 @@ tp_status pcg_impl(tp_ctx* c, const tp_symbol* op, const tp_symbol* pre, const t
       TPCHK(truncate_impl<T>(c, 2, cf, xs, &X, eps, cap, &capped));
       anycap |= capped;
     }
-    {
+    if (o->recursive_residual) {
+      // the update of Algorithm alg:pcg as printed: S = trunc(fun(P)), R = trunc(R - a S)
+      TPCHK(apply_impl<T>(c, op, &P, &S, eps, cap, sk, &capped));
+      anycap |= capped;
+      info->op_applies += 1;
+      const tp_tensor* rs[2] = {&R, &S};
+      double cf[2] = {1.0, -a};
+      TPCHK(truncate_impl<T>(c, 2, cf, rs, &R, eps, cap, &capped));
+      anycap |= capped;
+    } else {
       Term t[2] = {{nullptr, &B, 1.0}, {op, &X, -1.0}};
       TPCHK(combo_impl<T>(c, t, 2, &R, eps, cap, sk, &capped));
       anycap |= capped;
@@ -1802,17 +1992,24 @@ tp_status pcg_impl(tp_ctx* c, const tp_symbol* op, const tp_symbol* pre, const t
     double rr = 0;
     TPCHK(inner_impl<T>(c, &R, &R, &rr));
     info->rel_res = std::sqrt(std::max(rr, 0.0)) / nb;
+    if (o->stop_rule == TP_STOP_RESIDUAL) {
+      // the relative residual of the Sec. 6 iteration counts
+      info->err_est = info->rel_res;
+      if (info->err_est <= o->tau) { converged = true; ++k; break; }
+    }
     TPCHK(apply_impl<T>(c, pre, &R, &Z, eps, cap, sk, &capped));
     anycap |= capped;
     info->op_applies += 1;
-    // "R sufficiently small": the preconditioned residual Z ~ A_2^-1 R estimates the error of X,
-    // so the test ||Z|| <= tau ||X|| bounds the relative error instead of the residual (whose
-    // norm under-weights the smooth error components by s_min/s_max)
-    double zz = 0, xx = 0;
-    TPCHK(inner_impl<T>(c, &Z, &Z, &zz));
-    TPCHK(inner_impl<T>(c, &X, &X, &xx));
-    info->err_est = std::sqrt(std::max(zz, 0.0) / std::max(xx, 1e-300));
-    if (info->err_est <= o->tau) { converged = true; ++k; break; }
+    if (o->stop_rule == TP_STOP_ERROR) {
+      // "R sufficiently small": the preconditioned residual Z ~ A_2^-1 R estimates the error of X,
+      // so the test ||Z|| <= tau ||X|| bounds the relative error instead of the residual (whose
+      // norm under-weights the smooth error components by s_min/s_max)
+      double zz = 0, xx = 0;
+      TPCHK(inner_impl<T>(c, &Z, &Z, &zz));
+      TPCHK(inner_impl<T>(c, &X, &X, &xx));
+      info->err_est = std::sqrt(std::max(zz, 0.0) / std::max(xx, 1e-300));
+      if (info->err_est <= o->tau) { converged = true; ++k; break; }
+    }
     // Safeguard (not part of the method): once the truncated iteration has reached the floor
     // set by the working precision or by the rank cap, further steps only amplify rounding
     // noise or repeat the truncation error.  The iterate with the smallest estimate is kept, and
@@ -1878,6 +2075,10 @@ extern "C" tp_status tp_pcg_solve(tp_ctx* c, const tp_symbol* op, const tp_symbo
       return fail(TP_EINVAL, "grid mismatch in mode %d", m);
   if (o->cap < 1 || o->cap > x->cap) return fail(TP_EINVAL, "opts.cap=%d must be in [1, x.cap=%d]", o->cap, x->cap);
   if (!(o->tau > 0) || o->kmax < 1 || !(o->trunc_tol > 0)) return fail(TP_EINVAL, "invalid PCG options");
+  if (o->stop_rule != TP_STOP_ERROR && o->stop_rule != TP_STOP_RESIDUAL)
+    return fail(TP_EINVAL, "unknown stop rule %d", o->stop_rule);
+  if (o->recursive_residual != 0 && o->recursive_residual != 1)
+    return fail(TP_EINVAL, "recursive_residual=%d must be 0 or 1", o->recursive_residual);
   if (sk->q < 2 || sk->q > kMaxSketch) return fail(TP_EINVAL, "sketch q=%d must be in [2,%d]", sk->q, kMaxSketch);
   if (b->rank < 0 || b->rank > kMaxRank) return fail(TP_EINVAL, "b.rank=%d outside [0,%d]", b->rank, kMaxRank);
   tp_status st = x->prec == TP_FP64 ? pcg_impl<double>(c, op, pre, b, x, o, sk, info)

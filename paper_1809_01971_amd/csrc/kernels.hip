@@ -816,6 +816,7 @@ __global__ __launch_bounds__(EIG_NT) void k_syev_small(JobBatch<EigJob> jobs) {
 struct CholShared { double rest; int q; };
 
 template <int NT> struct ChGrid;
+template <> struct ChGrid<64> { static constexpr int TX = 8, NBI = 8, NBJ = 8, KMAX = 64; };
 template <> struct ChGrid<256> { static constexpr int TX = 16, NBI = 4, NBJ = 4, KMAX = 64; };
 template <> struct ChGrid<512> { static constexpr int TX = 32, NBI = 4, NBJ = 8, KMAX = 128; };
 template <> struct ChGrid<1024> { static constexpr int TX = 32, NBI = 8, NBJ = 8, KMAX = 256; };
@@ -963,16 +964,17 @@ __device__ __forceinline__ double dpp_f64(double v) {
   return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
 }
 __device__ __forceinline__ double group_sum(double v, int lanes) {
-  v += dpp_f64<0xB1>(v);
-  v += dpp_f64<0x4E>(v);
+  if (lanes >= 2) v += dpp_f64<0xB1>(v);
+  if (lanes >= 4) v += dpp_f64<0x4E>(v);
   if (lanes >= 8) v += dpp_f64<0x141>(v);
   if (lanes >= 16) v += dpp_f64<0x140>(v);
   return v;
 }
-// Largest power of two <= v, capped at 16 (lanes per group for the DPP sums; >= 4 here).
+// Lanes per group for the DPP sums: the largest power of two <= 16 with lanes * groups <= nt
+// (at least 1).
 __device__ __forceinline__ int lanes_for(int nt, int groups) {
   int l = 16;
-  while (l > 4 && l * groups > nt) l >>= 1;
+  while (l > 1 && l * groups > nt) l >>= 1;
   return l;
 }
 
@@ -1029,7 +1031,7 @@ __global__ __launch_bounds__(NT) void k_pchol(JobBatch<CholJob> jobs) {
   // X(i, j) = -(sum_{i<l<=j} R(i, l) X(l, j)) / R(i, i), bottom-up; X(l, j), l < j, at Rp[j + K l]
   {
     const int lc = lanes_for(NT, q);
-    const int lg = lc == 16 ? 4 : (lc == 8 ? 3 : 2);
+    const int lg = lc == 16 ? 4 : (lc == 8 ? 3 : (lc == 4 ? 2 : (lc == 2 ? 1 : 0)));
     for (int j0 = 0; j0 < q; j0 += NT / lc) {
       const int j = j0 + (tid >> lg), li = tid & (lc - 1);
       if (j < q) {
@@ -1140,9 +1142,12 @@ __global__ __launch_bounds__(NT) void k_psd_eig(JobBatch<PsdJob> jobs) {
   // one-sided Jacobi on the q columns of X (round-robin pairs, L lanes per pair)
   const int qp = q + (q & 1), np = qp / 2;
   const int L = lanes_for(NT, np);
-  const int lg = L == 16 ? 4 : (L == 8 ? 3 : 2);
+  const int lg = L == 16 ? 4 : (L == 8 ? 3 : (L == 4 ? 2 : (L == 2 ? 1 : 0)));
   const int pr = tid >> lg, li = tid & (L - 1);
-  constexpr int RMAX = SMEM ? (KMAX * KMAX + 2 * NT - 1) / (2 * NT) : 1;  // rows per lane in registers
+  // rows per lane held in registers: KMAX / (lanes per pair), the lanes being at least
+  // NT / (KMAX / 2) (or 1)
+  constexpr int LMIN = (2 * NT) / KMAX > 0 ? (2 * NT) / KMAX : 1;
+  constexpr int RMAX = SMEM ? (KMAX + LMIN - 1) / LMIN : 1;
   for (int sweep = 0; sweep < 40 && q > 1; ++sweep) {
     unsigned int* chg = &offmax[sweep % 3];
     if (tid == 0) offmax[(sweep + 1) % 3] = 0u;  // last read two sweeps ago
@@ -1502,42 +1507,44 @@ template hipError_t expfactors<float>(const double*, int, const double*, int, fl
 //   kind 0: g(y) = c_neg rho^-(1+alpha) + c_pos rho^-(1-alpha), rho = rho0*y
 //   kind 1: p(y) = 1/s(rho) = 1/(c_neg rho^-alpha + c_pos rho^alpha)
 //   kind 2: c_neg rho^-alpha (the state operator beta A^-alpha)
-__device__ double fit_target(int kind, double alpha, double cn, double cp, double rho0, double y) {
-  double rho = rho0 * y;
-  double ra = pow(rho, alpha);
-  if (kind == 0) return (cn / ra + cp * ra) / rho;
-  if (kind == 2) return cn / ra;
-  return 1.0 / (cn / ra + cp * ra);
+__device__ double fit_target(int kind, const SymFn& f, double rho0, double y) {
+  const double rho = rho0 * y;
+  const double neg = f.cn > 0.0 ? f.cn * pow(rho, -f.alpha) : 0.0;
+  const double pos = f.cp > 0.0 ? f.cp * pow(rho, f.beta) : 0.0;
+  if (kind == 0) return (neg + (f.fitpos ? pos : 0.0)) / rho;
+  if (kind == 2) return neg;
+  return 1.0 / (f.c0 + neg + pos);
 }
 
-__global__ void k_fit_design(int kind, double alpha, double cn, double cp, double rho0, double B, int K, int m,
-                             const FitCand* cands, double* A, double* tvec) {
+__global__ void k_fit_design(int kind, SymFn f, double rho0, double B, int K, int m, const FitCand* cands, double* A,
+                             double* tvec) {
   int c = blockIdx.y;
   FitCand fc = cands[c];
   long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  // exponents geometric on [exp(lo), exp(hi)]; a single exponent sits at the middle of the range
   double lo = log(1.0 / B) + fc.a, hi = fc.b;
+  auto pos = [K](int k) { return K > 1 ? (double)k / (double)(K - 1) : 0.5; };
   if (e < K) {
-    double t = exp(lo + (hi - lo) * (double)e / (double)(K > 1 ? K - 1 : 1));
+    double t = exp(lo + (hi - lo) * pos((int)e));
     tvec[(long)c * K + e] = t;
   }
   if (e < (long)m * K) {
     int j = (int)(e % m), k = (int)(e / m);
-    double t = exp(lo + (hi - lo) * (double)k / (double)(K > 1 ? K - 1 : 1));
+    double t = exp(lo + (hi - lo) * pos(k));
     double y = exp(log(B) * (double)j / (double)(m > 1 ? m - 1 : 1));
-    A[(long)c * m * K + e] = exp(-t * y) / fit_target(kind, alpha, cn, cp, rho0, y);
+    A[(long)c * m * K + e] = exp(-t * y) / fit_target(kind, f, rho0, y);
   }
 }
-hipError_t fit_design(int kind, double alpha, double cneg, double cpos, double rho0, double B, int K, int m,
-                      const FitCand* cands_dev, int ncand, double* A, double* tvec, hipStream_t s) {
+hipError_t fit_design(int kind, const SymFn& f, double rho0, double B, int K, int m, const FitCand* cands_dev,
+                      int ncand, double* A, double* tvec, hipStream_t s) {
   long tot = (long)m * K;
-  hipLaunchKernelGGL(k_fit_design, dim3((tot + 255) / 256, ncand), dim3(256), 0, s, kind, alpha, cneg, cpos, rho0,
-                     B, K, m, cands_dev, A, tvec);
+  hipLaunchKernelGGL(k_fit_design, dim3((tot + 255) / 256, ncand), dim3(256), 0, s, kind, f, rho0, B, K, m, cands_dev,
+                     A, tvec);
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_fit_error(int kind, double alpha, double cn, double cp, double rho0,
-                                                   double B, int K, const double* t, const double* w, int m,
-                                                   double* err) {
+__global__ __launch_bounds__(256) void k_fit_error(int kind, SymFn f, double rho0, double B, int K, const double* t,
+                                                   const double* w, int m, double* err) {
   __shared__ double red[256];
   int c = blockIdx.x;
   const double* tc = t + (long)c * K;
@@ -1547,7 +1554,7 @@ __global__ __launch_bounds__(256) void k_fit_error(int kind, double alpha, doubl
     double y = exp(log(B) * (double)j / (double)(m - 1));
     double v = 0.0;
     for (int k = 0; k < K; ++k) v += wc[k] * exp(-tc[k] * y);
-    double r = fabs(v / fit_target(kind, alpha, cn, cp, rho0, y) - 1.0);
+    double r = fabs(v / fit_target(kind, f, rho0, y) - 1.0);
     if (!(r <= mx)) mx = r;  // NaN propagates as "bad"
   }
   red[threadIdx.x] = mx;
@@ -1561,9 +1568,9 @@ __global__ __launch_bounds__(256) void k_fit_error(int kind, double alpha, doubl
   }
   if (threadIdx.x == 0) err[c] = red[0];
 }
-hipError_t fit_error(int kind, double alpha, double cneg, double cpos, double rho0, double B, int K,
-                     const double* t, const double* w, int ncand, int m, double* err, hipStream_t s) {
-  hipLaunchKernelGGL(k_fit_error, dim3(ncand), dim3(256), 0, s, kind, alpha, cneg, cpos, rho0, B, K, t, w, m, err);
+hipError_t fit_error(int kind, const SymFn& f, double rho0, double B, int K, const double* t, const double* w,
+                     int ncand, int m, double* err, hipStream_t s) {
+  hipLaunchKernelGGL(k_fit_error, dim3(ncand), dim3(256), 0, s, kind, f, rho0, B, K, t, w, m, err);
   return hipGetLastError();
 }
 
@@ -1597,23 +1604,60 @@ hipError_t sinc_g_nodes(double alpha, double cneg, double cpos, double rho0, int
 }
 
 // symbol value at index tuples: opkind 0 -> rho * sum w exp(-tau rho); 1 -> sum w exp(-tau rho)
-__global__ void k_symbol_eval(int d, const int* idx, int count, const double* l0, const double* l1, const double* l2,
-                              int opkind, int K, const double* tau, const double* w, double* out) {
+// Multi-indices outside the grid give NaN (no read outside the eigenvalue arrays).
+__device__ inline bool idx_ok(const int* ix, int d, int n0, int n1, int n2) {
+  return ix[0] >= 0 && ix[0] < n0 && ix[1] >= 0 && ix[1] < n1 && (d < 3 || (ix[2] >= 0 && ix[2] < n2));
+}
+
+__global__ void k_symbol_eval(int d, const int* idx, int count, int n0, int n1, int n2, const double* l0,
+                              const double* l1, const double* l2, int opkind, int K, const double* tau,
+                              const double* w, double c0, double* out) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= count) return;
-  double rho = l0[idx[p * d + 0]] + l1[idx[p * d + 1]];
-  if (d == 3) rho += l2[idx[p * d + 2]];
+  const int* ix = idx + (long)p * d;
+  if (!idx_ok(ix, d, n0, n1, n2)) { out[p] = __longlong_as_double(0x7ff8000000000000LL); return; }
+  double rho = l0[ix[0]] + l1[ix[1]];
+  if (d == 3) rho += l2[ix[2]];
   double v = 0.0;
   for (int k = 0; k < K; ++k) v += w[k] * exp(-tau[k] * rho);
-  out[p] = opkind == 0 ? rho * v : v;
+  out[p] = opkind == 0 ? c0 + rho * v : v;
 }
-hipError_t symbol_eval(int d, const int* idx, int count, const double* lam0, const double* lam1, const double* lam2,
-                       int opkind, int K, const double* tau, const double* w, double* out, hipStream_t s) {
+hipError_t symbol_eval(int d, const int* idx, int count, const int* n, const double* lam0, const double* lam1,
+                       const double* lam2, int opkind, int K, const double* tau, const double* w, double c0,
+                       double* out, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_symbol_eval, dim3((count + 255) / 256), dim3(256), 0, s, d, idx, count, lam0, lam1, lam2,
-                     opkind, K, tau, w, out);
+  hipLaunchKernelGGL(k_symbol_eval, dim3((count + 255) / 256), dim3(256), 0, s, d, idx, count, n[0], n[1],
+                     d == 3 ? n[2] : 1, lam0, lam1, lam2, opkind, K, tau, w, c0, out);
   return hipGetLastError();
 }
+
+template <typename T>
+__global__ void k_cp_eval(int d, const int* idx, int count, int n0, int n1, int n2, const T* F0, const T* F1,
+                          const T* F2, int R, const double* w, double* out) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= count) return;
+  const int* ix = idx + (long)p * d;
+  if (!idx_ok(ix, d, n0, n1, n2)) { out[p] = __longlong_as_double(0x7ff8000000000000LL); return; }
+  double v = 0.0;
+  for (int k = 0; k < R; ++k) {
+    double t = w[k] * (double)F0[ix[0] + (long)n0 * k] * (double)F1[ix[1] + (long)n1 * k];
+    if (d == 3) t *= (double)F2[ix[2] + (long)n2 * k];
+    v += t;
+  }
+  out[p] = v;
+}
+template <typename T>
+hipError_t cp_eval(int d, const int* idx, int count, const int* n, const T* const* F, int R, const double* w,
+                   double* out, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cp_eval<T>, dim3((count + 255) / 256), dim3(256), 0, s, d, idx, count, n[0], n[1],
+                     d == 3 ? n[2] : 1, F[0], F[1], d == 3 ? F[2] : F[1], R, w, out);
+  return hipGetLastError();
+}
+template hipError_t cp_eval<float>(int, const int*, int, const int*, const float* const*, int, const double*,
+                                   double*, hipStream_t);
+template hipError_t cp_eval<double>(int, const int*, int, const int*, const double* const*, int, const double*,
+                                    double*, hipStream_t);
 
 // Column scaling of the least-squares normal equations: D_k = 1/sqrt(G_kk), G <- D G D, b <- D b.
 __global__ void k_fit_scale(int K, double* G, double* b, double* D) {

@@ -109,19 +109,30 @@ hipError_t lambda_1d(int n, double* out, hipStream_t s);
 // E[:,k] = exp(-tau_k lam), times lam when withLam (the Lemma 4.1 factor).
 template <typename T>
 hipError_t expfactors(const double* lam, int n, const double* tau, int K, T* E, int ldE, int withLam, hipStream_t s);
+// The function a least-squares exponential sum approximates, in rho = rho0 y:
+//   kind 0 (operator, Lemma 4.1): g = (cn rho^-alpha + [fitpos] cp rho^beta) / rho, the part of
+//          s = c0 + cn rho^-alpha + cp rho^beta that is fitted (c0 and a beta = 1 term are exact);
+//   kind 1 (preconditioner): 1 / s;   kind 2 (state): cn rho^-alpha.
+struct SymFn { double c0, cn, cp, alpha, beta; int fitpos; };
 // least-squares design matrix for candidate c: rows y_j (m), columns t_k (K):
-// A[j,k] = exp(-t_k y_j) / f(y_j); f selected by kind (0: g, 1: 1/s).  Candidates stacked.
+// A[j,k] = exp(-t_k y_j) / f(y_j).  Candidates stacked.
 struct FitCand { double a, b; };
-hipError_t fit_design(int kind, double alpha, double cneg, double cpos, double rho0, double B, int K, int m,
-                      const FitCand* cands_dev, int ncand, double* A, double* tvec, hipStream_t s);
-// Column norms (for scaling) and b = A^T 1 etc. handled with gemm; max error evaluation:
-hipError_t fit_error(int kind, double alpha, double cneg, double cpos, double rho0, double B, int K,
-                     const double* t, const double* w, int ncand, int m, double* err, hipStream_t s);
+hipError_t fit_design(int kind, const SymFn& f, double rho0, double B, int K, int m, const FitCand* cands_dev,
+                      int ncand, double* A, double* tvec, hipStream_t s);
+// max relative error of the fitted sums over m log-spaced points, per candidate
+hipError_t fit_error(int kind, const SymFn& f, double rho0, double B, int K, const double* t, const double* w,
+                     int ncand, int m, double* err, hipStream_t s);
 hipError_t sinc_g_nodes(double alpha, double cneg, double cpos, double rho0, int kl, int kr, double hh,
                         double* tau, double* w, hipStream_t s);
-hipError_t symbol_eval(int d, const int* idx, int count, const double* lam0, const double* lam1,
-                       const double* lam2, int opkind, int K, const double* tau, const double* w, double* out,
-                       hipStream_t s);
+// out = c0 + rho sum_k w_k exp(-tau_k rho) (opkind 0) or sum_k w_k exp(-tau_k rho) at multi-indices
+// (count x d, 0-based; n: host, grid sizes; points outside the grid give NaN)
+hipError_t symbol_eval(int d, const int* idx, int count, const int* n, const double* lam0, const double* lam1,
+                       const double* lam2, int opkind, int K, const double* tau, const double* w, double c0,
+                       double* out, hipStream_t s);
+// out = sum_k w_k prod_m F_m[i_m, k] for a canonical symbol with factors F_m (n_m x R, ld n_m)
+template <typename T>
+hipError_t cp_eval(int d, const int* idx, int count, const int* n, const T* const* F, int R, const double* w,
+                   double* out, hipStream_t s);
 
 hipError_t fit_scale(int K, int nc, double* G, double* b, double* D, hipStream_t s);
 hipError_t fit_solve(int K, int nc, const double* ev, const double* E, const double* b, const double* D, double cut,

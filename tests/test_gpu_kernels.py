@@ -122,7 +122,8 @@ def test_symbol_matches_exact_power(ctx, d, n, alpha, cn, cp):
     assert eo < 2e-5
     assert ep < 5e-2
     assert sp.min() > 0
-    assert op.info()[0] == d * 32
+    # alpha = 1: c_pos rho is kept exact as one more (tau = 0) term
+    assert op.info()[0] == d * (32 + (alpha == 1.0))
 
 
 def test_symbol_sinc_rule_matches_power(ctx):

@@ -1,0 +1,168 @@
+"""The test operators of the preconditioning experiments (Sec. 6, eq:precond_ex1-3) on the GPU:
+A^alpha x = b, (I + A^(2 alpha)) x = b and (A^alpha + A^-alpha) x = b, each a symbol
+c0 + c_neg rho^-alpha + c_pos rho^beta, checked against the exact oracle O1 (whose general
+symbol is pinned against dense eigendecompositions on the CPU)."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import exact, spectral, tensor
+from tests.gpu_helpers import log, rel
+
+pytestmark = pytest.mark.gpu
+
+EQS = sorted(workloads.PRECOND_EQS)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1809_01971_amd as tp
+    c = tp.Context(0, workspace_bytes=4 << 30)
+    yield c
+    c.close()
+
+
+def _build(ctx, p, prec, op_terms=36, pre_terms=28, **kw):
+    return ctx.symbol_build(p.d, p.n, p.alpha, p.c_neg, p.c_pos, prec=prec, op_terms=op_terms,
+                            pre_terms=pre_terms, c0=p.c0, beta=p.beta or 0.0, **kw)
+
+
+def _exact_symbol(p, rho):
+    return spectral.symbol(rho, p.alpha, p.c_neg, p.c_pos, p.c0, p.beta)
+
+
+@pytest.mark.parametrize("alpha", [0.5, 0.1])
+@pytest.mark.parametrize("eq", EQS)
+def test_general_symbol_values(ctx, eq, alpha):
+    """Operator and preconditioner symbols at 20000 random multi-indices of a 3D n=255 grid (and
+    its corners) against c0 + c_neg rho^-alpha + c_pos rho^beta.  With beta = 1 and c_neg = 0
+    (I + A at alpha = 1/2) the operator is exact: a constant and d Laplacian columns."""
+    p = workloads.precond_problem(eq, alpha, 255, 3)
+    log("symbol %s" % p.name)
+    op, pre, (eo, ep) = _build(ctx, p, 0)
+    rng = np.random.default_rng(5)
+    idx = rng.integers(0, p.n, size=(20000, 3))
+    idx[:3] = [[0, 0, 0], [p.n - 1] * 3, [0, p.n // 2, p.n - 1]]
+    s = _exact_symbol(p, spectral.eigenvalues(p.n)[idx].sum(axis=1))
+    err_op = np.abs(op.eval(idx) / s - 1).max()
+    sp = pre.eval(idx)
+    err_pre = np.abs(sp * s - 1).max()
+    log("  op err %.2e (reported %.2e, rank %d) pre err %.2e (reported %.2e)" % (err_op, eo, op.info()[0],
+                                                                             err_pre, ep))
+    assert err_op <= 1.05 * eo + 1e-13
+    assert err_pre <= 1.05 * ep + 1e-13
+    assert eo < 1e-5 and ep < 1e-3
+    assert sp.min() > 0
+    if eq == "I+A^2a" and alpha == 0.5:
+        assert eo == 0.0 and op.info()[0] == 3 + 1      # c0 column plus one exact tau = 0 term
+        assert err_op < 1e-13
+
+
+@pytest.mark.parametrize("d,n", [(2, 255), (3, 63)])
+@pytest.mark.parametrize("alpha", [0.5, 0.1])
+@pytest.mark.parametrize("eq", EQS)
+def test_precond_equation_fp64_against_oracle(ctx, eq, alpha, d, n):
+    """FP64 tensor PCG on the whole grid against the exact solve of O1, two N(0,1) rhs terms."""
+    import paper_1809_01971_amd as tp
+    from paper_1809_01971_amd._tp import sketch_tensors
+    p = workloads.precond_problem(eq, alpha, n, d, kind="gauss")
+    log("solve %s d=%d n=%d fp64" % (p.name, d, n))
+    op, pre, errs = _build(ctx, p, 0, op_terms=40)
+    cap = 96 if d == 2 else 60
+    X = tp.Tensor(d, n, cap, 0)
+    sk = sketch_tensors(workloads.sketch_matrices(n, d, min(cap + 16, 192)))
+    st, info = ctx.pcg_solve(op, pre, p.weights, p.factors, X, tau=3e-8, kmax=100, trunc_tol=1e-9, cap=cap,
+                             sketch=sk, true_residual=True)
+    u = exact.solve_full(tensor.cp_full(p.weights, p.factors), p.alpha, p.c_neg, p.c_pos, p.c0, p.beta)
+    err = rel(ctx.eval_grid(X, [np.arange(n)] * d), u)
+    log("  err %.2e sym %s info %s" % (err, errs, info))
+    assert info["status"] in (0, 4)
+    assert err < 1e-6
+
+
+@pytest.mark.parametrize("eq", EQS)
+def test_precond_equation_mixed_against_oracle(ctx, eq):
+    """Mixed precision, 3D n=127, alpha = 1/2, constant rhs: within 1e-4 of the exact solution."""
+    import paper_1809_01971_amd as tp
+    from paper_1809_01971_amd._tp import sketch_tensors
+    p = workloads.precond_problem(eq, 0.5, 127, 3)
+    log("solve %s d=3 n=127 mixed" % p.name)
+    op, pre, errs = _build(ctx, p, 1, op_terms=32)
+    X = tp.Tensor(3, 127, 48, 1)
+    sk = sketch_tensors(workloads.sketch_matrices(127, 3, 64))
+    st, info = ctx.pcg_solve(op, pre, p.weights, p.factors, X, tau=4e-5, kmax=100, trunc_tol=1e-5, cap=48,
+                             sketch=sk)
+    u = exact.solve_full(tensor.cp_full(p.weights, p.factors), p.alpha, p.c_neg, p.c_pos, p.c0, p.beta)
+    err = rel(ctx.eval_grid(X, [np.arange(127)] * 3), u)
+    log("  err %.2e sym %s info %s" % (err, errs, info))
+    assert info["status"] in (0, 4)
+    assert err < 1e-4
+
+
+@pytest.mark.parametrize("eq", ["A^a", "A^a+A^-a"])
+def test_residual_stop_rule(ctx, eq):
+    """stop_rule = residual: the solve stops at ||R|| <= tau ||B|| (the recomputed residual is
+    reported), and the oracle's residual ||B - A X|| / ||B|| of the returned X agrees with it."""
+    import paper_1809_01971_amd as tp
+    from paper_1809_01971_amd._tp import TP_STOP_RESIDUAL, sketch_tensors
+    p = workloads.precond_problem(eq, 0.5, 511, 2)
+    log("residual stop %s n=511" % p.name)
+    op, pre, errs = _build(ctx, p, 0, op_terms=40, pre_terms=12)
+    X = tp.Tensor(2, 511, 96, 0)
+    sk = sketch_tensors(workloads.sketch_matrices(511, 2, 112))
+    st, info = ctx.pcg_solve(op, pre, p.weights, p.factors, X, tau=1e-6, kmax=100, trunc_tol=1e-12, cap=96,
+                             sketch=sk, true_residual=True, stop_rule=TP_STOP_RESIDUAL)
+    log("  info %s" % info)
+    assert info["status"] in (0, 4)
+    assert info["rel_res"] <= 1e-6 and info["err_est"] == info["rel_res"]
+    f = tensor.cp_full(p.weights, p.factors)
+    x = ctx.eval_grid(X, [np.arange(511)] * 2)
+    r = rel(exact.apply_full(x, p.alpha, p.c_neg, p.c_pos, p.c0, p.beta), f)
+    log("  oracle residual %.2e" % r)
+    assert r < 2e-6
+
+
+@pytest.mark.parametrize("eq", EQS)
+def test_recursive_residual_update(ctx, eq):
+    """recursive_residual: R = trunc(R - a trunc(fun(P))) as printed in Algorithm alg:pcg, with the
+    rank-8 preconditioner.  The recursive residual reaches 1e-6 also for I + A, whose recomputed
+    residual stops near 1e-4: the Gram-based truncation keeps X to about 1e-8 and the operator
+    amplifies that by lambda_max / lambda_min.  The solution itself is within 1e-6 of O1."""
+    import paper_1809_01971_amd as tp
+    from paper_1809_01971_amd._tp import TP_STOP_RESIDUAL, sketch_tensors
+    n = 511
+    p = workloads.precond_problem(eq, 0.5, n, 2)
+    log("recursive residual %s n=%d" % (p.name, n))
+    op, pre, errs = _build(ctx, p, 0, op_terms=40, pre_terms=36, pre_rank=8)
+    X = tp.Tensor(2, n, 96, 0)
+    sk = sketch_tensors(workloads.sketch_matrices(n, 2, 112))
+    st, info = ctx.pcg_solve(op, pre, p.weights, p.factors, X, tau=1e-6, kmax=100, trunc_tol=1e-12, cap=96,
+                             sketch=sk, true_residual=True, stop_rule=TP_STOP_RESIDUAL, recursive_residual=True)
+    u = exact.solve_full(tensor.cp_full(p.weights, p.factors), p.alpha, p.c_neg, p.c_pos, p.c0, p.beta)
+    err = rel(ctx.eval_grid(X, [np.arange(n)] * 2), u)
+    log("  err %.2e info %s" % (err, info))
+    assert info["status"] in (0, 4) and info["rel_res"] <= 1e-6
+    assert info["iters"] <= 12
+    assert err < 1e-6
+
+
+@pytest.mark.parametrize("d,n,r,prec", [(2, 255, 1, 0), (2, 255, 4, 0), (2, 255, 8, 0), (3, 31, 2, 0),
+                                        (3, 31, 5, 0), (2, 255, 6, 1)])
+@pytest.mark.parametrize("eq", EQS)
+def test_rank_r_preconditioner_against_oracle(ctx, eq, d, n, r, prec):
+    """pre_rank = r: the recompressed preconditioner on every grid point equals the oracle's
+    truncated HOSVD of the exact inverse symbol (in 2D its rank-r SVD), alpha = 1/2."""
+    p = workloads.precond_problem(eq, 0.5, n, d)
+    log("rank-%d preconditioner %s d=%d n=%d prec=%d" % (r, p.name, d, n, prec))
+    op, pre, (eo, ep) = _build(ctx, p, prec, pre_terms=36, pre_rank=r)
+    idx = np.indices((n,) * d).reshape(d, -1).T.copy()
+    got = pre.eval(idx).reshape((n,) * d)
+    want = exact.precond_rank_r((n,) * d, r, p.alpha, p.c_neg, p.c_pos, p.c0, p.beta)
+    e = rel(got, want)
+    R = pre.info()[0]
+    P = 1.0 / _exact_symbol(p, spectral.rho_grid((n,) * d))
+    lat = np.abs(got * (1.0 / P) - 1).max()
+    log("  rank %d: vs oracle %.2e; max|p s - 1| %.2e (reported lattice %.2e)" % (R, e, lat, ep))
+    assert R == (r if d == 2 else r * r)
+    assert e < (1e-6 if prec == 0 else 1e-5)
+    assert ep <= lat * (1 + 1e-6) + 1e-12

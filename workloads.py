@@ -26,6 +26,8 @@ class Problem:
     weights: np.ndarray                      # (R,)
     factors: list = field(default_factory=list)   # d arrays (n, R), column k = term k
     name: str = ""
+    c0: float = 0.0         # constant term of the symbol (preconditioning tests)
+    beta: float = None      # exponent of the c_pos term; None = alpha
 
 
 def grid(n):
@@ -109,6 +111,28 @@ def cfg5(seed=4, n=32767):
             c = rng.uniform(0.2, 0.8)
             F[l][:, k] = np.exp(-(x - c) ** 2 / 0.01)
     return Problem(3, n, 0.3, 1.0, 1e-3, np.ones(10), F, "cfg5")
+
+
+# The test operators of the preconditioning experiments (Sec. 6, eq:precond_ex1-3) as
+# (c_neg, c_pos, c0, beta / alpha) of the symbol c0 + c_neg rho^-alpha + c_pos rho^beta.
+PRECOND_EQS = {
+    "A^a": (0.0, 1.0, 0.0, 1.0),
+    "I+A^2a": (0.0, 1.0, 1.0, 2.0),
+    "A^a+A^-a": (1.0, 1.0, 0.0, 1.0),
+}
+
+
+def precond_problem(eq, alpha, n, d, kind="ones", seed=7):
+    """Right-hand side b of the preconditioning experiments.  The paper does not state it;
+    kind "ones" is the constant grid function (rank 1), kind "gauss" two N(0,1) terms."""
+    cn, cp, c0, bm = PRECOND_EQS[eq]
+    if kind == "ones":
+        F = [np.ones((n, 1)) for _ in range(d)]
+        w = np.ones(1)
+    else:
+        F = gaussian_factors(np.random.default_rng(seed), n, d, 2)
+        w = np.ones(2)
+    return Problem(d, n, alpha, cn, cp, w, F, "%s alpha=%g" % (eq, alpha), c0=c0, beta=bm * alpha)
 
 
 def sketch_matrices(n, d, q, seed=1000):
