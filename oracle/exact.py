@@ -143,6 +143,38 @@ def tucker_error_slabs(weights, factors, alpha, c_neg, c_pos, core, tfactors, sl
     return err2, u2
 
 
+def solve_directional(f, alpha, c_neg, c_pos, c0=0.0):
+    """u on the full grid for the directionally fractional operator A_(alpha) = sum_l
+    (-Delta_l)^alpha (Remark rem:direct_fract_Lap, eq:Laplace_1Dfract) in the control equation's
+    place of A^alpha: (c0 I + c_neg A_(alpha)^-1 + c_pos A_(alpha)) u = f.  Its spectral values are
+    c0 + c_neg / rho' + c_pos rho', rho' = sum_l lambda_{i_l}^alpha (the reciprocal of the core
+    eq:3c1d for c0 = 0, c_neg = c_pos = 1)."""
+    f = np.asarray(f, dtype=np.float64)
+    fh = sfft.dstn(f, type=1, norm="ortho")
+    rp = spectral.rho_directional(f.shape, alpha)
+    return sfft.idstn(fh / (c0 + c_neg / rp + c_pos * rp), type=1, norm="ortho")
+
+
+def brute_force_directional(f, alpha, c_neg, c_pos, c0=0.0):
+    """Dense route without the sine transform: (A_l)^alpha from numpy.linalg.eigh of each 1D
+    tridiagonal matrix, A_(alpha) as their Kronecker sum, then c0 I + c_neg A_(alpha)^-1 +
+    c_pos A_(alpha) formed with a dense inverse and solved."""
+    f = np.asarray(f, dtype=np.float64)
+    ns = f.shape
+    N = int(np.prod(ns))
+    Ad = np.zeros((N, N))
+    for l, n in enumerate(ns):
+        lam, Q = np.linalg.eigh(spectral.laplacian_1d(n))
+        mats = [np.eye(m) for m in ns]
+        mats[l] = (Q * lam**alpha) @ Q.T
+        K = mats[0]
+        for M in mats[1:]:
+            K = np.kron(K, M)
+        Ad += K
+    A2 = c0 * np.eye(N) + c_neg * np.linalg.inv(Ad) + c_pos * Ad
+    return np.linalg.solve(A2, f.reshape(N)).reshape(ns)
+
+
 def precond_rank_r(ns, r, alpha, c_neg, c_pos, c0=0.0, beta=None):
     """The rank-r preconditioner of the Sec. 6 iteration counts on the full grid: the inverse
     symbol 1/s(rho) (the spectral values of the operator's inverse, eqn:DiagFLaplace3D) truncated

@@ -59,6 +59,20 @@ def rho_grid(ns):
     return rho
 
 
+def rho_directional(ns, alpha):
+    """rho'(i_1..i_d) = sum_l lambda_{i_l}^alpha: the eigenvalues of the directionally fractional
+    operator sum_l (-Delta_l)^alpha (Sec. 4.1, Remark rem:direct_fract_Lap, eq:Laplace_1Dfract),
+    whose cores eq:3a1d-eq:3c1d are functions of this sum."""
+    lams = [eigenvalues(n) ** alpha for n in ns]
+    d = len(ns)
+    rho = np.zeros(tuple(ns))
+    for l, lam in enumerate(lams):
+        shape = [1] * d
+        shape[l] = ns[l]
+        rho = rho + lam.reshape(shape)
+    return rho
+
+
 def symbol(rho, alpha, c_neg, c_pos, c0=0.0, beta=None):
     """s(rho) = c0 + c_neg rho^-alpha + c_pos rho^beta (beta = alpha unless given): the
     eigenvalues of c0 I + c_neg A^-alpha + c_pos A^beta (spectral definition eqn:frac_Oper).

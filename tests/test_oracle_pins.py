@@ -353,3 +353,35 @@ def test_rank_r_preconditioner_full_rank_is_exact():
     ns = (6, 5, 4)
     P = 1.0 / spectral.symbol(spectral.rho_grid(ns), 0.5, 0.0, 1.0, 1.0, 1.0)
     assert np.abs(exact.precond_rank_r(ns, 6, 0.5, 0.0, 1.0, 1.0, 1.0) - P).max() <= 1e-13 * P.max()
+
+
+# ------------------------------------------------- directionally fractional Laplacian (Sec. 4.1)
+@pytest.mark.parametrize("alpha", [0.3, 0.5, 0.9])
+@pytest.mark.parametrize("shape", [(7, 9), (5, 4, 3)])
+def test_directional_solve_matches_dense_powers(alpha, shape):
+    """The sine-transform solve with rho' = sum_l lambda^alpha equals the dense route that takes
+    fractional powers of each 1D matrix by its own eigendecomposition."""
+    f = np.random.default_rng(13).standard_normal(shape)
+    u = exact.solve_directional(f, alpha, 1.0, 0.3)
+    v = exact.brute_force_directional(f, alpha, 1.0, 0.3)
+    assert np.linalg.norm(u - v) <= 1e-11 * np.linalg.norm(v)
+
+
+@pytest.mark.parametrize("shape", [(7, 9), (5, 4, 3)])
+def test_directional_at_alpha_one_is_the_laplacian(shape):
+    """alpha = 1: sum_l (-Delta_l) is the Laplacian, and the directional control equation is the
+    ordinary one with alpha = 1 (checked through the dense Laplacian, no fractional power)."""
+    f = np.random.default_rng(14).standard_normal(shape)
+    u = exact.solve_directional(f, 1.0, 1.0, 0.3, c0=0.5)
+    A = exact.laplacian_full(shape)
+    N = A.shape[0]
+    v = np.linalg.solve(0.5 * np.eye(N) + np.linalg.inv(A) + 0.3 * A, f.reshape(N)).reshape(shape)
+    assert np.linalg.norm(u - v) <= 1e-11 * np.linalg.norm(v)
+
+
+def test_directional_differs_from_the_fractional_laplacian():
+    """For alpha < 1 the two operators differ (sum of powers is not the power of the sum):
+    (lambda_1 + lambda_2)^alpha < lambda_1^alpha + lambda_2^alpha."""
+    rp = spectral.rho_directional((5, 6), 0.5)
+    r = spectral.rho_grid((5, 6)) ** 0.5
+    assert np.all(r < rp)
