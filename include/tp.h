@@ -147,6 +147,11 @@ typedef struct {
                         * Tucker core spread back to canonical rank r (2D) or r^2 (3D): the rank-r
                         * preconditioner of the Sec. 6 iteration counts.  Its err is then the max of
                         * |p s - 1| over a geometric lattice of grid points. */
+  int32_t directional; /* 1: the directionally fractional operator A_(alpha) = sum_l (-Delta_l)^alpha
+                        * (Sec. 4.1 Remark rem:direct_fract_Lap, eq:Laplace_1Dfract) takes the
+                        * place of A^alpha: the 1D spectra are lambda^alpha, rho' = sum_l
+                        * lambda_{i_l}^alpha, and s = c0 + c_neg / rho' + c_pos rho' (beta must be
+                        * 0 or 1); the cores eq:3a1d-3c1d are 1/rho', 1/rho' + rho' and its inverse */
 } tp_symbol_desc;
 
 /* Build the operator symbol and the preconditioner symbol on the GPU.  Both are
@@ -159,8 +164,9 @@ tp_status tp_symbol_free(tp_symbol* sym);
 
 /* State operator of eqn:State / eqn:L_alp_state, y = beta A^-alpha u: the exponential sum
  * beta rho^-alpha ~ sum_k w_k exp(-tau_k rho) (canonical rank op_terms, least-squares fit; beta is
- * desc->c_neg, desc->c_pos is ignored), for use with tp_apply.  err (host, may be NULL) receives
- * its measured max relative error. */
+ * desc->c_neg, desc->c_pos is ignored), for use with tp_apply (with desc->directional:
+ * beta / rho', the state of the directionally fractional operator).  err (host, may be NULL)
+ * receives its measured max relative error. */
 tp_status tp_state_symbol_build(tp_ctx* ctx, const tp_symbol_desc* desc, tp_symbol** state,
                                 double* err);
 /* rank (host): canonical rank of the symbol; err (host): its measured error. */

@@ -42,7 +42,7 @@ class tp_symbol_desc(C.Structure):
                 ("c_pos", C.c_double), ("method", C.c_int32), ("op_terms", C.c_int32),
                 ("pre_terms", C.c_int32), ("sinc_kl", C.c_int32), ("sinc_kr", C.c_int32),
                 ("sinc_h", C.c_double), ("prec", C.c_int32), ("c0", C.c_double), ("beta", C.c_double),
-                ("pre_rank", C.c_int32)]
+                ("pre_rank", C.c_int32), ("directional", C.c_int32)]
 
 
 class tp_pcg_opts(C.Structure):
@@ -203,13 +203,15 @@ class Context:
 
     # ---- symbols
     def symbol_build(self, d, n, alpha, c_neg, c_pos, prec=TP_FP64, method=TP_SYM_FIT, op_terms=0,
-                     pre_terms=0, sinc_kl=0, sinc_kr=0, sinc_h=0.0, c0=0.0, beta=0.0, pre_rank=0):
+                     pre_terms=0, sinc_kl=0, sinc_kr=0, sinc_h=0.0, c0=0.0, beta=0.0, pre_rank=0,
+                     directional=False):
         desc = tp_symbol_desc()
         desc.d = d
         for m in range(3):
             desc.n[m] = n if m < d else 0
         desc.alpha, desc.c_neg, desc.c_pos = alpha, c_neg, c_pos
         desc.c0, desc.beta, desc.pre_rank = c0, beta, pre_rank
+        desc.directional = 1 if directional else 0
         desc.method, desc.op_terms, desc.pre_terms = method, op_terms, pre_terms
         desc.sinc_kl, desc.sinc_kr, desc.sinc_h = sinc_kl, sinc_kr, sinc_h
         desc.prec = prec
@@ -218,13 +220,14 @@ class Context:
         _check(self.lib.tp_symbol_build(self.h, C.byref(desc), C.byref(op), C.byref(pre), err))
         return Symbol(self, op, d, prec), Symbol(self, pre, d, prec), (err[0], err[1])
 
-    def state_symbol_build(self, d, n, alpha, beta, prec=TP_FP64, terms=0):
+    def state_symbol_build(self, d, n, alpha, beta, prec=TP_FP64, terms=0, directional=False):
         desc = tp_symbol_desc()
         desc.d = d
         for m in range(3):
             desc.n[m] = n if m < d else 0
         desc.alpha, desc.c_neg, desc.c_pos = alpha, beta, 0.0
         desc.op_terms, desc.prec = terms, prec
+        desc.directional = 1 if directional else 0
         h = P()
         err = C.c_double()
         _check(self.lib.tp_state_symbol_build(self.h, C.byref(desc), C.byref(h), C.byref(err)))

@@ -1245,8 +1245,9 @@ tp_status recompress_pre(tp_ctx* c, tp_symbol* s, int r) {
 }
 
 // max |p s - 1| of a recompressed preconditioner p over a lattice of grid points whose indices
-// are geometric in every mode (64 per mode in 2D, 16 in 3D), s the exact symbol of fn.
-tp_status pre_lattice_error(tp_ctx* c, const tp_symbol* s, const SymFn& fn, double* err) {
+// are geometric in every mode (64 per mode in 2D, 16 in 3D), s the exact symbol of fn in
+// rho = sum_l lambda_{i_l}^power.
+tp_status pre_lattice_error(tp_ctx* c, const tp_symbol* s, const SymFn& fn, double power, double* err) {
   WsScope scope(c);
   const int d = s->d, L = d == 2 ? 64 : 16;
   std::vector<int> ax[3];
@@ -1258,7 +1259,7 @@ tp_status pre_lattice_error(tp_ctx* c, const tp_symbol* s, const SymFn& fn, doub
       int i = (int)std::floor(std::pow((double)n, (double)k / (L - 1))) - 1;
       i = std::min(std::max(i, 0), n - 1);
       ax[m].push_back(i);
-      lam[m].push_back(4.0 / (h * h) * std::pow(std::sin(M_PI * (i + 1) * h / 2), 2));
+      lam[m].push_back(std::pow(4.0 / (h * h) * std::pow(std::sin(M_PI * (i + 1) * h / 2), 2), power));
     }
   }
   const int cnt = d == 2 ? L * L : L * L * L;
@@ -1483,7 +1484,14 @@ tp_status tp_symbol_build(tp_ctx* c, const tp_symbol_desc* desc, tp_symbol** op,
   if (!(D.c_neg >= 0.0) || !(D.c_pos >= 0.0) || !(D.c_neg + D.c_pos > 0.0))
     return fail(TP_EINVAL, "coefficients c_neg=%g c_pos=%g must be >= 0 and not both 0", D.c_neg, D.c_pos);
   if (!(D.c0 >= 0.0)) return fail(TP_EINVAL, "c0=%g must be >= 0", D.c0);
-  const double beta = D.beta == 0.0 ? D.alpha : D.beta;
+  if (D.directional != 0 && D.directional != 1) return fail(TP_EINVAL, "directional=%d must be 0 or 1", D.directional);
+  // directional: the 1D spectra are lambda^alpha and the symbol is a function of rho' = sum lambda^alpha
+  // with unit exponents, c0 + c_neg / rho' + c_pos rho'
+  const double power = D.directional ? D.alpha : 1.0;
+  const double alpha = D.directional ? 1.0 : D.alpha;
+  if (D.directional && D.beta != 0.0 && D.beta != 1.0)
+    return fail(TP_EINVAL, "directional symbols take beta = 0 or 1 (got %g)", D.beta);
+  const double beta = D.directional ? 1.0 : (D.beta == 0.0 ? D.alpha : D.beta);
   if (!(beta > 0.0 && beta <= 1.0)) return fail(TP_EINVAL, "beta=%g must be in (0,1]", D.beta);
   if (D.prec != TP_FP64 && D.prec != TP_MIXED) return fail(TP_EINVAL, "unknown precision %d", D.prec);
   for (int m = 0; m < D.d; ++m) TPCHK(check_grid(D.n[m], D.prec));
@@ -1493,11 +1501,11 @@ tp_status tp_symbol_build(tp_ctx* c, const tp_symbol_desc* desc, tp_symbol** op,
   if (Kpre < 1 || Kpre > 64) return fail(TP_EINVAL, "pre_terms=%d must be in [1,64]", Kpre);
   if (D.pre_rank < 0 || D.pre_rank > 16) return fail(TP_EINVAL, "pre_rank=%d must be in [0,16]", D.pre_rank);
   if (D.method != TP_SYM_FIT && D.method != TP_SYM_SINC) return fail(TP_EINVAL, "unknown method %d", D.method);
-  if (D.method == TP_SYM_SINC && (D.c0 != 0.0 || beta != D.alpha))
+  if (D.method == TP_SYM_SINC && (D.c0 != 0.0 || beta != alpha))
     return fail(TP_EINVAL, "the sinc rule covers c0 = 0 and beta = alpha only");
   // beta = 1: c_pos rho is exact (a tau = 0 exponential); what is left to fit is c_neg rho^-(1+alpha)
   const bool exact_pos = beta == 1.0 && D.c_pos > 0.0;
-  const SymFn fn{D.c0, D.c_neg, D.c_pos, D.alpha, beta, exact_pos ? 0 : 1};
+  const SymFn fn{D.c0, D.c_neg, D.c_pos, alpha, beta, exact_pos ? 0 : 1};
   const bool fit_op = !(exact_pos && D.c_neg == 0.0);
   int kl = D.sinc_kl > 0 ? D.sinc_kl : 60, kr = D.sinc_kr > 0 ? D.sinc_kr : 20;
   double hh = D.sinc_h > 0 ? D.sinc_h : 0.55;
@@ -1521,13 +1529,13 @@ tp_status tp_symbol_build(tp_ctx* c, const tp_symbol_desc* desc, tp_symbol** op,
       if (hipMalloc(&l, sizeof(double) * D.n[m]) != hipSuccess) return cleanup(fail(TP_ENOMEM, "hipMalloc failed"));
       s[i]->owned.push_back(l);
       s[i]->lam[m] = l;
-      if (lambda_1d(D.n[m], l, c->stream) != hipSuccess) return cleanup(fail(TP_EHIP, "lambda kernel failed"));
+      if (lambda_1d(D.n[m], l, c->stream, power) != hipSuccess) return cleanup(fail(TP_EHIP, "lambda kernel failed"));
     }
   }
   for (int m = 0; m < D.d; ++m) {
     double h = 1.0 / (D.n[m] + 1.0);
-    lam1[m] = 4.0 / (h * h) * std::pow(std::sin(M_PI * h / 2), 2);
-    lamn[m] = 4.0 / (h * h) * std::pow(std::sin(M_PI * D.n[m] * h / 2), 2);
+    lam1[m] = std::pow(4.0 / (h * h) * std::pow(std::sin(M_PI * h / 2), 2), power);
+    lamn[m] = std::pow(4.0 / (h * h) * std::pow(std::sin(M_PI * D.n[m] * h / 2), 2), power);
   }
   double rmin = 0, rmax = 0;
   for (int m = 0; m < D.d; ++m) { rmin += lam1[m]; rmax += lamn[m]; }
@@ -1535,7 +1543,7 @@ tp_status tp_symbol_build(tp_ctx* c, const tp_symbol_desc* desc, tp_symbol** op,
   // operator
   {
     tp_symbol* so = s[0];
-    const int Kfit = D.method == TP_SYM_FIT ? (fit_op ? Kop : 0) : kl + kr + 1 + (std::fabs(1.0 - D.alpha) < 1e-15 ? 1 : 0);
+    const int Kfit = D.method == TP_SYM_FIT ? (fit_op ? Kop : 0) : kl + kr + 1 + (std::fabs(1.0 - alpha) < 1e-15 ? 1 : 0);
     const int K = Kfit + (D.method == TP_SYM_FIT && exact_pos ? 1 : 0);
     so->K = K;
     so->c0 = D.c0;
@@ -1566,7 +1574,7 @@ tp_status tp_symbol_build(tp_ctx* c, const tp_symbol_desc* desc, tp_symbol** op,
       }
       so->err = e;
     } else {
-      if (sinc_g_nodes(D.alpha, D.c_neg, D.c_pos, rho0, kl, kr, hh, so->tau, so->w, c->stream) != hipSuccess)
+      if (sinc_g_nodes(alpha, D.c_neg, D.c_pos, rho0, kl, kr, hh, so->tau, so->w, c->stream) != hipSuccess)
         return cleanup(fail(TP_EHIP, "sinc kernel failed"));
       so->err = -1;
     }
@@ -1601,7 +1609,7 @@ tp_status tp_symbol_build(tp_ctx* c, const tp_symbol_desc* desc, tp_symbol** op,
   }
   if (D.pre_rank > 0) {
     // measured error of the recompressed preconditioner: max |p s - 1| over a lattice of grid points
-    tp_status st = pre_lattice_error(c, s[1], fn, &s[1]->err);
+    tp_status st = pre_lattice_error(c, s[1], fn, power, &s[1]->err);
     if (st != TP_OK) return cleanup(st);
   }
   if (s[0]->err < 0) {
@@ -1634,6 +1642,8 @@ tp_status tp_state_symbol_build(tp_ctx* c, const tp_symbol_desc* desc, tp_symbol
   if (!(D.alpha > 0.0 && D.alpha <= 1.0)) return fail(TP_EINVAL, "alpha=%g must be in (0,1]", D.alpha);
   if (!(D.c_neg > 0.0)) return fail(TP_EINVAL, "c_neg (beta) must be > 0");
   if (D.prec != TP_FP64 && D.prec != TP_MIXED) return fail(TP_EINVAL, "unknown precision %d", D.prec);
+  if (D.directional != 0 && D.directional != 1) return fail(TP_EINVAL, "directional=%d must be 0 or 1", D.directional);
+  const double power = D.directional ? D.alpha : 1.0, alpha = D.directional ? 1.0 : D.alpha;
   for (int m = 0; m < D.d; ++m) TPCHK(check_grid(D.n[m], D.prec));
   int K = D.op_terms > 0 ? D.op_terms : 28;
   if (K < 2 || K > 64) return fail(TP_EINVAL, "op_terms=%d must be in [2,64]", K);
@@ -1655,10 +1665,10 @@ tp_status tp_state_symbol_build(tp_ctx* c, const tp_symbol_desc* desc, tp_symbol
     if (hipMalloc(&l, sizeof(double) * D.n[m]) != hipSuccess) return cleanup(fail(TP_ENOMEM, "hipMalloc failed"));
     s->owned.push_back(l);
     s->lam[m] = l;
-    if (lambda_1d(D.n[m], l, c->stream) != hipSuccess) return cleanup(fail(TP_EHIP, "lambda kernel failed"));
+    if (lambda_1d(D.n[m], l, c->stream, power) != hipSuccess) return cleanup(fail(TP_EHIP, "lambda kernel failed"));
     double h = 1.0 / (D.n[m] + 1.0);
-    rmin += 4.0 / (h * h) * std::pow(std::sin(M_PI * h / 2), 2);
-    rmax += 4.0 / (h * h) * std::pow(std::sin(M_PI * D.n[m] * h / 2), 2);
+    rmin += std::pow(4.0 / (h * h) * std::pow(std::sin(M_PI * h / 2), 2), power);
+    rmax += std::pow(4.0 / (h * h) * std::pow(std::sin(M_PI * D.n[m] * h / 2), 2), power);
   }
   const double rho0 = rmin, B = rmax / rmin * 1.0000001;
   if (hipMalloc(&s->tau, sizeof(double) * K) != hipSuccess || hipMalloc(&s->w, sizeof(double) * K) != hipSuccess)
@@ -1669,7 +1679,7 @@ tp_status tp_state_symbol_build(tp_ctx* c, const tp_symbol_desc* desc, tp_symbol
   for (double a : {-1.5, -1.0, -0.5})
     for (double b : {1.75, 2.25, 2.75}) cands.push_back({a, b});
   double e = 0;
-  const SymFn fn{0.0, D.c_neg, 0.0, D.alpha, D.alpha, 0};
+  const SymFn fn{0.0, D.c_neg, 0.0, alpha, alpha, 0};
   tp_status st = fit_expsum(c, 2, fn, rho0, B, K, cands, s->tau, s->w, &e);
   if (st != TP_OK) return cleanup(st);
   if (scale(s->tau, K, 1.0 / rho0, c->stream) != hipSuccess) return cleanup(fail(TP_EHIP, "scale failed"));

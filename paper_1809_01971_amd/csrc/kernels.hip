@@ -1471,16 +1471,17 @@ template hipError_t gather_rows<float>(const float*, int, const int*, int, int, 
 // ---------------------------------------------------------------------------------------------
 // Symbol construction
 // ---------------------------------------------------------------------------------------------
-__global__ void k_lambda(int n, double* out) {
+__global__ void k_lambda(int n, double power, double* out) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) {
     double h = 1.0 / (double)(n + 1);
     double s = sinpi(0.5 * (double)(k + 1) * h);
-    out[k] = 4.0 / (h * h) * s * s;
+    double lam = 4.0 / (h * h) * s * s;
+    out[k] = power == 1.0 ? lam : pow(lam, power);
   }
 }
-hipError_t lambda_1d(int n, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_lambda, dim3((n + 255) / 256), dim3(256), 0, s, n, out);
+hipError_t lambda_1d(int n, double* out, hipStream_t s, double power) {
+  hipLaunchKernelGGL(k_lambda, dim3((n + 255) / 256), dim3(256), 0, s, n, power, out);
   return hipGetLastError();
 }
 

@@ -104,7 +104,9 @@ template <typename T>
 hipError_t gather_rows(const T* in, int ld, const int* rows, int m, int cols, double* out, hipStream_t s);
 
 // Symbol construction.
-hipError_t lambda_1d(int n, double* out, hipStream_t s);
+// lambda_k^power, lambda_k = (4/h^2) sin^2(pi k h/2), k = 1..n (power != 1: the spectra of the
+// directionally fractional operator)
+hipError_t lambda_1d(int n, double* out, hipStream_t s, double power = 1.0);
 // exponential-sum factor columns for a mode with eigenvalues lam (n) and exponents tau (K):
 // E[:,k] = exp(-tau_k lam), times lam when withLam (the Lemma 4.1 factor).
 template <typename T>

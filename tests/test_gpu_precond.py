@@ -231,3 +231,71 @@ def test_iteration_counts_2d_alpha_half(ctx):
     for n in (255, 511):
         sk = sketch_tensors(workloads.sketch_matrices(n, 2, 144))
         assert _iterations(ctx, "A^a", 0.5, n, 2, 2, sk, 128) is None
+
+
+# ------------------------------------------- directionally fractional Laplacian (Sec. 4.1 remark)
+@pytest.mark.parametrize("alpha", [0.5, 0.1])
+def test_directional_symbol_values(ctx, alpha):
+    """directional: the operator symbol c_neg / rho' + c_pos rho' and the preconditioner 1/s at
+    20000 random points of a 3D n = 255 grid, rho' = sum_l lambda^alpha."""
+    n = 255
+    log("directional symbol alpha=%g" % alpha)
+    op, pre, (eo, ep) = ctx.symbol_build(3, n, alpha, 1.0, 1e-2, prec=0, op_terms=36, pre_terms=28,
+                                         directional=True)
+    idx = np.random.default_rng(9).integers(0, n, size=(20000, 3))
+    idx[:2] = [[0, 0, 0], [n - 1] * 3]
+    rp = (spectral.eigenvalues(n) ** alpha)[idx].sum(axis=1)
+    s = 1.0 / rp + 1e-2 * rp
+    err_op = np.abs(op.eval(idx) / s - 1).max()
+    err_pre = np.abs(pre.eval(idx) * s - 1).max()
+    log("  op err %.2e (reported %.2e, rank %d) pre err %.2e (reported %.2e)" % (err_op, eo, op.info()[0],
+                                                                             err_pre, ep))
+    assert err_op <= 1.05 * eo + 1e-13 and eo < 1e-6
+    assert err_pre <= 1.05 * ep + 1e-13 and ep < 1e-3
+    assert op.info()[0] == 3 * (36 + 1)     # c_pos rho' exact: one tau = 0 term
+
+
+@pytest.mark.parametrize("d,n,prec", [(2, 255, 0), (3, 63, 0), (3, 255, 0), (3, 127, 1)])
+@pytest.mark.parametrize("alpha", [0.5, 0.1])
+def test_directional_control_solve_against_oracle(ctx, d, n, prec, alpha):
+    """The control equation with A_(alpha) = sum_l (-Delta_l)^alpha in place of A^alpha, beta = 1,
+    gamma = 1e-2 (c_neg = 1, c_pos = 1e-2), two N(0,1) rhs terms: the whole grid against the
+    oracle's directional solve, 1e-6 in FP64 and 1e-4 mixed."""
+    import paper_1809_01971_amd as tp
+    from paper_1809_01971_amd._tp import sketch_tensors
+    F = workloads.gaussian_factors(np.random.default_rng(21), n, d, 2)
+    w = np.ones(2)
+    log("directional solve d=%d n=%d alpha=%g prec=%d" % (d, n, alpha, prec))
+    op, pre, errs = ctx.symbol_build(d, n, alpha, 1.0, 1e-2, prec=prec, op_terms=40 if prec == 0 else 32,
+                                     pre_terms=28, directional=True)
+    cap = (96 if d == 2 else 64) if prec == 0 else 48
+    X = tp.Tensor(d, n, cap, prec)
+    sk = sketch_tensors(workloads.sketch_matrices(n, d, cap + 16))
+    eps, tau = (1e-9, 3e-8) if prec == 0 else (1e-5, 4e-5)
+    st, info = ctx.pcg_solve(op, pre, w, F, X, tau=tau, kmax=100, trunc_tol=eps, cap=cap, sketch=sk)
+    u = exact.solve_directional(tensor.cp_full(w, F), alpha, 1.0, 1e-2)
+    err = rel(ctx.eval_grid(X, [np.arange(n)] * d), u)
+    log("  err %.2e sym %s info %s" % (err, errs, info))
+    assert info["status"] in (0, 4)
+    assert err < (1e-6 if prec == 0 else 1e-4)
+
+
+def test_directional_state(ctx):
+    """State of the directional control problem, y = beta A_(alpha)^-1 u, from the state symbol."""
+    import paper_1809_01971_amd as tp
+    n, d, alpha, beta = 63, 3, 0.3, 2.0
+    st_sym, serr = ctx.state_symbol_build(d, n, alpha, beta, prec=0, terms=36, directional=True)
+    F = workloads.gaussian_factors(np.random.default_rng(22), n, d, 1)
+    U = tp.Tensor(d, n, 8, 0)
+    ctx.from_cp(np.ones(1), F, U)
+    Y = tp.Tensor(d, n, 48, 0)
+    from paper_1809_01971_amd._tp import sketch_tensors
+    ctx.apply(st_sym, U, Y, 1e-10, 48, sketch_tensors(workloads.sketch_matrices(n, d, 64)))
+    u = tensor.cp_full(np.ones(1), F)
+    import scipy.fft as sfft
+    uh = sfft.dstn(u, type=1, norm="ortho")
+    y = sfft.idstn(beta * uh / spectral.rho_directional((n,) * d, alpha), type=1, norm="ortho")
+    err = rel(ctx.eval_grid(Y, [np.arange(n)] * d), y)
+    log("directional state: err %.2e (symbol %.2e)" % (err, serr))
+    # the symbol's error is measured on 4096 log-spaced points of [rho'_min, rho'_max]
+    assert serr < 1e-7 and err < 4 * serr
