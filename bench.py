@@ -40,7 +40,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_solver(ctx, p, sk_by_q, s, steps, warmup, profile):
+def run_solver(ctx, p, sk_by_q, s, steps, warmup, profile, spectral=False):
     import torch
     import paper_1809_01971_amd as tp
     X = tp.Tensor(3, p.n, s["cap"], s["prec"])
@@ -50,7 +50,7 @@ def run_solver(ctx, p, sk_by_q, s, steps, warmup, profile):
         op, pre, errs = ctx.symbol_build(3, p.n, p.alpha, p.c_neg, p.c_pos, prec=s["prec"],
                                          op_terms=s["op_terms"], pre_terms=s["pre_terms"])
         st, info = ctx.pcg_solve(op, pre, p.weights, p.factors, X, tau=s["tau"], kmax=100,
-                                 trunc_tol=s["eps"], cap=s["cap"], sketch=sk)
+                                 trunc_tol=s["eps"], cap=s["cap"], sketch=sk, spectral_domain=spectral)
         op.free()
         pre.free()
         info["sym_err"] = errs
@@ -101,6 +101,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fp64-steps", type=int, default=None)
+    ap.add_argument("--spectral-steps", type=int, default=None,
+                    help="timed steps of the spectral-domain variant (default: --steps; 0 skips it)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first copy 256 MiB on the device (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -134,6 +136,19 @@ def main():
     else:
         dtd, infd, parts_d = None, [{"iters": None, "rank": None}], None
     parts_m = Xm.numpy_parts()
+    ssteps = args.spectral_steps if args.spectral_steps is not None else args.steps
+    spectral = None
+    if ssteps > 0:
+        # the same mixed solve with the iteration kept in sine coordinates (transforms only on B in
+        # and X out); compared with the stated path's result on a stride-16 sub-grid
+        log("bench: mixed spectral-domain steps=%d" % ssteps)
+        Xs, dts, infs, _ = run_solver(ctx, p, sk_by_q, SETTINGS["mixed"], ssteps, 1, False, spectral=True)
+        rows = [np.arange(0, p.n, 16)] * 3
+        a, b = ctx.eval_grid(Xs, rows), ctx.eval_grid(Xm, rows)
+        spectral = {"solves_per_s": ssteps / dts, "ms_per_step": 1000.0 * dts / ssteps,
+                    "iters": infs[-1]["iters"], "ranks": infs[-1]["rank"],
+                    "rel_diff_vs_stated_path": float(np.linalg.norm(a - b) / np.linalg.norm(b)),
+                    "note": "outside the paper: PCG in DST coordinates, same settings"}
 
     value = args.steps / dtm
     ms = 1000.0 * dtm / args.steps
@@ -211,6 +226,7 @@ def main():
         "iters_mixed": infm[-1]["iters"], "ranks_mixed": infm[-1]["rank"],
         "iters_fp64": infd[-1]["iters"], "ranks_fp64": infd[-1]["rank"],
         "symbol_err_mixed": infm[-1]["sym_err"][0], "precond_err": infm[-1]["sym_err"][1],
+        "spectral_domain_mixed": spectral,
         "roofline": roofline, "kernel_breakdown": breakdown, "work": work, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

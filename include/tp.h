@@ -246,6 +246,11 @@ typedef struct {
                                * 1: R = trunc(R - alpha trunc(fun(P))) as printed in Algorithm
                                * alg:pcg (it does not see the truncation error of X, so with
                                * TP_STOP_RESIDUAL it reaches tau below the floor set by it) */
+  int32_t spectral_domain;    /* 1: run the iteration in sine coordinates: the right-hand side's
+                               * factors are transformed once, every iterate keeps F V as its
+                               * factors (F orthogonal: inner products and truncations unchanged),
+                               * and only X is transformed back at the end; the products skip
+                               * their two transforms.  Same result up to rounding. */
 } tp_pcg_opts;
 
 typedef struct {

@@ -48,7 +48,7 @@ class tp_symbol_desc(C.Structure):
 class tp_pcg_opts(C.Structure):
     _fields_ = [("tau", C.c_double), ("kmax", C.c_int32), ("trunc_tol", C.c_double), ("cap", C.c_int32),
                 ("true_residual", C.c_int32), ("stop_rule", C.c_int32),
-                ("recursive_residual", C.c_int32)]
+                ("recursive_residual", C.c_int32), ("spectral_domain", C.c_int32)]
 
 
 class tp_pcg_info(C.Structure):
@@ -290,11 +290,11 @@ class Context:
             list(range(len(rows)))[::-1])
 
     def pcg_solve(self, op, pre, weights, factors, x, tau, kmax, trunc_tol, cap, sketch, true_residual=False,
-                  allow=(TP_ERANK, TP_ENOCONV), stop_rule=0, recursive_residual=False):
+                  allow=(TP_ERANK, TP_ENOCONV), stop_rule=0, recursive_residual=False, spectral_domain=False):
         keep, cp = cp_struct(weights, factors)
         sk, keep2 = sketch_struct(sketch)
         o = tp_pcg_opts(tau, kmax, trunc_tol, cap, 1 if true_residual else 0, stop_rule,
-                        1 if recursive_residual else 0)
+                        1 if recursive_residual else 0, 1 if spectral_domain else 0)
         info = tp_pcg_info()
         st = _check(self.lib.tp_pcg_solve(self.h, op.h, pre.h, C.byref(cp), C.byref(x.s), C.byref(o),
                                           C.byref(sk), C.byref(info)), allow=allow)
@@ -335,7 +335,7 @@ def batch_solve(ctx, problems, settings, sketches, streams=8, workspace_per_stre
         X = Tensor(p.d, p.n, s["cap"], s["prec"])
         outs.append(X)
         tens[i] = X.s
-        opts[i] = tp_pcg_opts(s["tau"], 100, s["eps"], s["cap"], 0, 0, 0)
+        opts[i] = tp_pcg_opts(s["tau"], 100, s["eps"], s["cap"], 0, 0, 0, 1 if s.get("spectral") else 0)
         sk, k2 = sketch_struct(sketches[p.n])
         sks[i] = sk
     _check(ctx.lib.tp_pcg_solve_batched(ctx.h, cnt, descs, cps, tens, opts, sks, infos, streams,

@@ -68,6 +68,9 @@ struct tp_ctx {
   std::map<int, double*> ones64;  // all-ones columns (identity symbol), per grid size
   std::map<int, float*> ones32;
   double* unit_w = nullptr;
+  // set inside a spectral-domain PCG solve: tensor factors are already in sine coordinates, so
+  // products and symbol inner products skip the forward and inverse transforms
+  bool spectral = false;
   // optional per-kernel-class timing with HIP events on the context stream
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -800,6 +803,10 @@ tp_status combo_impl(tp_ctx* c, const Term* terms, int nt, tp_tensor* y, double 
     const tp_tensor* x = tv[t].x;
     for (int m = 0; m < 3; ++m) P.r[m] = m < d ? x->rank[m] : 1;
     for (int m = 0; m < d; ++m) {
+      if (c->spectral) {
+        P.Vh[m] = (T*)x->factor[m];  // read only; a y aliasing x is written after the last read
+        continue;
+      }
       TPCHK(wsalloc(c, (size_t)x->n[m] * P.r[m], &P.Vh[m]));
       TPCHK(dst_cols<T>(c, x->n[m], P.r[m], (const T*)x->factor[m], P.Vh[m]));
     }
@@ -946,6 +953,12 @@ tp_status combo_impl(tp_ctx* c, const Term* terms, int nt, tp_tensor* y, double 
   for (int m = 0; m < d; ++m) {
     int n = y->n[m];
     WsScope s4(c);
+    if (c->spectral) {
+      TPCHK((mm<double, double, T, double>(c, false, false, n, rn[m], q[m], 1.0, Qb[m], n, U[m], q[m], 0.0,
+                                          (T*)y->factor[m], n)));
+      y->rank[m] = rn[m];
+      continue;
+    }
     T* W;
     TPCHK(wsalloc(c, (size_t)n * rn[m], &W));
     TPCHK((mm<double, double, T, double>(c, false, false, n, rn[m], q[m], 1.0, Qb[m], n, U[m], q[m], 0.0, W, n)));
@@ -976,10 +989,15 @@ tp_status inner_sym_impl(tp_ctx* c, const tp_tensor* x, const tp_symbol* S, cons
     int n = x->n[m];
     rx[m] = x->rank[m];
     ry[m] = y->rank[m];
-    TPCHK(wsalloc(c, (size_t)n * rx[m], &Vx[m]));
-    TPCHK(wsalloc(c, (size_t)n * ry[m], &Vy[m]));
-    TPCHK(dst_cols<T>(c, n, rx[m], (const T*)x->factor[m], Vx[m]));
-    TPCHK(dst_cols<T>(c, n, ry[m], (const T*)y->factor[m], Vy[m]));
+    if (c->spectral) {
+      Vx[m] = (T*)x->factor[m];
+      Vy[m] = (T*)y->factor[m];
+    } else {
+      TPCHK(wsalloc(c, (size_t)n * rx[m], &Vx[m]));
+      TPCHK(wsalloc(c, (size_t)n * ry[m], &Vy[m]));
+      TPCHK(dst_cols<T>(c, n, rx[m], (const T*)x->factor[m], Vx[m]));
+      TPCHK(dst_cols<T>(c, n, ry[m], (const T*)y->factor[m], Vy[m]));
+    }
     // G[i + rx (j + ry k)] (sigma folded into the last mode)
     TPCHK(wsalloc(c, (size_t)rx[m] * ry[m] * R, &G[m]));
     GemmArgs<T, T, double, double> g;
@@ -1944,8 +1962,25 @@ tp_status pcg_impl(tp_ctx* c, const tp_symbol* op, const tp_symbol* pre, const t
   info->err_est = -1;
   info->op_applies = 0;
   bool capped = false, anycap = false;
+  // spectral domain: the right-hand side's factors go to sine coordinates once, every iterate
+  // stays there (F is orthogonal per mode, so inner products and truncations are unchanged), and
+  // X comes back once at the end
+  struct SpectralScope {
+    tp_ctx* c;
+    ~SpectralScope() { c->spectral = false; }
+  } spec_scope{c};
+  tp_cp bs = *b;
+  if (o->spectral_domain && b->rank > 0) {
+    for (int m = 0; m < b->d; ++m) {
+      double* F;
+      TPCHK(wsalloc(c, (size_t)b->n[m] * b->rank, &F));
+      TPCHK(dst_cols<double>(c, b->n[m], b->rank, b->factor[m], F));
+      bs.factor[m] = F;
+    }
+  }
   // B: exact Tucker form of the canonical right-hand side, truncated well below eps
-  TPCHK(from_cp_impl<T>(c, b, &B, eps * 1e-2, &capped));
+  TPCHK(from_cp_impl<T>(c, &bs, &B, eps * 1e-2, &capped));
+  c->spectral = o->spectral_domain != 0;
   anycap |= capped;
   double nb2 = 0;
   TPCHK(inner_impl<T>(c, &B, &B, &nb2));
@@ -2049,7 +2084,14 @@ tp_status pcg_impl(tp_ctx* c, const tp_symbol* op, const tp_symbol* pre, const t
     TPCHK(copy_tensor<T>(c, &Xb, &X));
     info->err_est = best;
   }
-  TPCHK(copy_tensor<T>(c, &X, x));
+  if (c->spectral) {
+    c->spectral = false;
+    TPCHK(copy_tensor<T>(c, &X, x));
+    for (int m = 0; m < x->d; ++m) TPCHK(dst_cols<T>(c, x->n[m], x->rank[m], (const T*)X.factor[m], (T*)x->factor[m]));
+    c->spectral = true;
+  } else {
+    TPCHK(copy_tensor<T>(c, &X, x));
+  }
   for (int m = 0; m < 3; ++m) info->rank[m] = m < x->d ? x->rank[m] : 0;
   if (o->true_residual) {
     // ||B - A_2 X|| / ||B||: the sum is formed and truncated tightly relative to its own norm
@@ -2089,6 +2131,8 @@ extern "C" tp_status tp_pcg_solve(tp_ctx* c, const tp_symbol* op, const tp_symbo
     return fail(TP_EINVAL, "unknown stop rule %d", o->stop_rule);
   if (o->recursive_residual != 0 && o->recursive_residual != 1)
     return fail(TP_EINVAL, "recursive_residual=%d must be 0 or 1", o->recursive_residual);
+  if (o->spectral_domain != 0 && o->spectral_domain != 1)
+    return fail(TP_EINVAL, "spectral_domain=%d must be 0 or 1", o->spectral_domain);
   if (sk->q < 2 || sk->q > kMaxSketch) return fail(TP_EINVAL, "sketch q=%d must be in [2,%d]", sk->q, kMaxSketch);
   if (b->rank < 0 || b->rank > kMaxRank) return fail(TP_EINVAL, "b.rank=%d outside [0,%d]", b->rank, kMaxRank);
   tp_status st = x->prec == TP_FP64 ? pcg_impl<double>(c, op, pre, b, x, o, sk, info)

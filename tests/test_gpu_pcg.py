@@ -20,7 +20,7 @@ def ctx():
     c.close()
 
 
-def solve(ctx, p, prec, eps, tau, cap=64, q=None, op_terms=32, pre_terms=28):
+def solve(ctx, p, prec, eps, tau, cap=64, q=None, op_terms=32, pre_terms=28, spectral=False):
     """The sketch width is the cap plus an oversampling of 16 columns.  tau is compared with the
     error estimate ||Z||/||X||, whose floor is about 2-3 times the truncation tolerance eps."""
     import paper_1809_01971_amd as tp
@@ -31,7 +31,7 @@ def solve(ctx, p, prec, eps, tau, cap=64, q=None, op_terms=32, pre_terms=28):
     sk = sketch_tensors(workloads.sketch_matrices(p.n, p.d, q))
     X = tp.Tensor(p.d, p.n, cap, prec)
     st, info = ctx.pcg_solve(op, pre, p.weights, p.factors, X, tau=tau, kmax=100, trunc_tol=eps, cap=cap,
-                             sketch=sk, true_residual=True)
+                             sketch=sk, true_residual=True, spectral_domain=spectral)
     info["sym_err"] = errs
     return X, st, info
 
@@ -176,3 +176,38 @@ def test_state_recovery_and_cost(ctx, prec):
     tol = FP64_TOL if prec == 0 else MIXED_TOL
     assert err_y < tol
     assert abs(J - J_ref) <= tol * abs(J_ref)
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_cfg3_n2047_spectral_domain(ctx, prec):
+    """The benchmark workload with the iteration in sine coordinates (spectral_domain): the same
+    error bound against the oracle (Parseval over every 8th spectral slab of the 2047^3 grid), and
+    the result equal to the standard path's up to the truncation tolerance (the two differ only in
+    rounding and in where the transforms sit)."""
+    p = workloads.cfg3()
+    log("cfg3 spectral domain prec=%d" % prec)
+    kw = (dict(eps=3e-5, tau=1.2e-4, cap=48, q=64, op_terms=28, pre_terms=28) if prec == 1 else
+          dict(eps=1.5e-7, tau=6e-7, cap=96, q=112, op_terms=36, pre_terms=36))
+    Xs, st, info = solve(ctx, p, prec, spectral=True, **kw)
+    X0, st0, info0 = solve(ctx, p, prec, **kw)
+    core, fs = Xs.numpy_parts()
+    err = global_rel_error(p, core, fs, stride=8)   # every 8th spectral slab
+    rows = [np.arange(0, p.n, 64)] * 3
+    d = rel(ctx.eval_grid(Xs, rows), ctx.eval_grid(X0, rows))
+    log("  global err %.2e, vs standard path %.2e; info %s / %s" % (err, d, info, info0))
+    assert info["iters"] == info0["iters"]
+    assert err < (MIXED_TOL if prec == 1 else FP64_TOL)
+    assert d < (3 * kw["eps"])
+    assert abs(info["true_rel_res"] - info0["true_rel_res"]) <= 0.05 * info0["true_rel_res"] + 1e-12
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_spectral_domain_2d_against_oracle(ctx, prec):
+    p = workloads.cfg1()
+    log("cfg1 spectral domain prec=%d" % prec)
+    X, st, info = solve(ctx, p, prec, eps=1e-8 if prec == 0 else 1e-6, tau=4e-8 if prec == 0 else 4e-6,
+                        op_terms=40 if prec == 0 else 32, pre_terms=36, spectral=True)
+    u = exact.solve_full(tensor.cp_full(p.weights, p.factors), p.alpha, p.c_neg, p.c_pos)
+    err = rel(ctx.eval_grid(X, [np.arange(p.n)] * 2), u)
+    log("  err %.2e info %s" % (err, info))
+    assert err < (FP64_TOL if prec == 0 else MIXED_TOL)
