@@ -45,3 +45,37 @@ def test_invalid_arguments_are_rejected_without_a_gpu():
     assert len(lib.tp_last_error()) > 0
     # NULL out pointer
     assert lib.tp_create(0, None, 0, None) == _tp.TP_EINVAL
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every struct the binding mirrors has the header's field offsets and size (gcc compiles a
+    probe against include/tp.h; the binding's ctypes layout must agree field by field)."""
+    import ctypes as C
+    import shutil
+    import subprocess
+    from paper_1809_01971_amd import _tp
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    structs = [_tp.tp_tensor, _tp.tp_cp, _tp.tp_sketch, _tp.tp_symbol_desc, _tp.tp_pcg_opts, _tp.tp_pcg_info]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "tp.h"', "int main(void) {"]
+    for st in structs:
+        name = st.__name__
+        lines.append('  printf("%s sizeof %%zu\\n", sizeof(%s));' % (name, name))
+        for f in st._fields_:
+            lines.append('  printf("%s %s %%zu\\n", offsetof(%s, %s));' % (name, f[0], name, f[0]))
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            a, b, v = line.split()
+            got[(a, b)] = int(v)
+    for st in structs:
+        name = st.__name__
+        assert got[(name, "sizeof")] == C.sizeof(st), name
+        for f in st._fields_:
+            assert got[(name, f[0])] == getattr(st, f[0]).offset, (name, f[0])
