@@ -223,7 +223,8 @@ tp_status tp_truncate(tp_ctx* ctx, int32_t count, const double* coef,
 tp_status tp_inner(tp_ctx* ctx, const tp_tensor* x, const tp_tensor* y, double* out);
 
 /* Values of x on the sub-grid rows[0] x rows[1] (x rows[2]) (device int32 arrays
- * of m[l] 0-based indices) into out (device, m[0]*m[1]*m[2] doubles, column-major). */
+ * of m[l] 0-based indices) into out (device, m[0]*m[1]*m[2] doubles, column-major).
+ * An index outside [0, n[l]) gives NaN in the points it enters. */
 tp_status tp_eval_grid(tp_ctx* ctx, const tp_tensor* x, const int32_t* const* rows,
                        const int32_t* m, double* out);
 

@@ -207,8 +207,9 @@ class Context:
                      directional=False):
         desc = tp_symbol_desc()
         desc.d = d
+        ns = mode_sizes(d, n)
         for m in range(3):
-            desc.n[m] = n if m < d else 0
+            desc.n[m] = ns[m] if m < d else 0
         desc.alpha, desc.c_neg, desc.c_pos = alpha, c_neg, c_pos
         desc.c0, desc.beta, desc.pre_rank = c0, beta, pre_rank
         desc.directional = 1 if directional else 0
@@ -223,8 +224,9 @@ class Context:
     def state_symbol_build(self, d, n, alpha, beta, prec=TP_FP64, terms=0, directional=False):
         desc = tp_symbol_desc()
         desc.d = d
+        ns = mode_sizes(d, n)
         for m in range(3):
-            desc.n[m] = n if m < d else 0
+            desc.n[m] = ns[m] if m < d else 0
         desc.alpha, desc.c_neg, desc.c_pos = alpha, beta, 0.0
         desc.op_terms, desc.prec = terms, prec
         desc.directional = 1 if directional else 0
@@ -378,19 +380,29 @@ class Symbol:
             pass
 
 
+def mode_sizes(d, n):
+    """Grid sizes per mode from an int (every mode) or a sequence of d ints."""
+    ns = [int(v) for v in n] if hasattr(n, "__len__") else [int(n)] * d
+    if len(ns) != d:
+        raise ValueError("need %d mode sizes, got %s" % (d, n))
+    return ns
+
+
 class Tensor:
-    """Tucker tensor in torch-owned device memory (core cap^d, factors n x cap column-major)."""
+    """Tucker tensor in torch-owned device memory (core cap^d, factors n_l x cap column-major).
+    n: one grid size for every mode or one per mode."""
 
     def __init__(self, d, n, cap, prec=TP_FP64, device="cuda"):
         t = _torch()
+        self.ns = mode_sizes(d, n)
         self.d, self.n, self.cap, self.prec = d, n, cap, prec
         dt = _dtype(prec)
         self.core = t.zeros(cap ** d, dtype=dt, device=device)
-        self.factors = [t.zeros(cap * n, dtype=dt, device=device) for _ in range(d)]
+        self.factors = [t.zeros(cap * self.ns[m], dtype=dt, device=device) for m in range(d)]
         s = tp_tensor()
         s.d, s.cap, s.prec = d, cap, prec
         for m in range(3):
-            s.n[m] = n if m < d else 0
+            s.n[m] = self.ns[m] if m < d else 0
             s.rank[m] = 0
         s.core = self.core.data_ptr()
         for m in range(d):
@@ -406,7 +418,7 @@ class Tensor:
         r = self.rank
         core = self.core[: int(np.prod(r))].double().cpu().numpy().reshape(r[::-1]).transpose(
             list(range(self.d))[::-1])
-        fs = [self.factors[m][: self.n * r[m]].double().cpu().numpy().reshape(r[m], self.n).T
+        fs = [self.factors[m][: self.ns[m] * r[m]].double().cpu().numpy().reshape(r[m], self.ns[m]).T
               for m in range(self.d)]
         return core, fs
 

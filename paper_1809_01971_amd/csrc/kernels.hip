@@ -1455,7 +1455,8 @@ __global__ void k_gather_rows(const T* in, int ld, const int* rows, int m, int c
   long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < (long)m * cols) {
     int p = (int)(e % m), c = (int)(e / m);
-    out[e] = (double)in[rows[p] + (long)ld * c];
+    const int r = rows[p];  // the factor has ld = n rows: indices outside give NaN, no read
+    out[e] = (r >= 0 && r < ld) ? (double)in[r + (long)ld * c] : __longlong_as_double(0x7ff8000000000000LL);
   }
 }
 template <typename T>

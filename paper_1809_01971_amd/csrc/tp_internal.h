@@ -99,7 +99,7 @@ hipError_t khatri_rao_d(const double* X2, int q2, const double* X3, int q3, int 
 // t[i, col] = sum_j T1[i + rm*(j + ro*col)] * A[j + ro*col]
 template <typename T>
 hipError_t contract_mid(const T* T1, const T* A, int rm, int ro, int ncol, T* t, hipStream_t s);
-// Gather rows: out[p, c] = in[rows[p] + ld*c]
+// Gather rows: out[p, c] = in[rows[p] + ld*c] for rows[p] in [0, ld) (the factor's n rows), NaN otherwise
 template <typename T>
 hipError_t gather_rows(const T* in, int ld, const int* rows, int m, int cols, double* out, hipStream_t s);
 

@@ -1,0 +1,136 @@
+"""Edge cases of the GPU path through the C ABI: grids of different size per mode, a zero
+right-hand side, indices outside the grid, the largest rank cap and sketch width, and argument
+checks on a live context (every rejection happens on the host, before device work)."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import exact, spectral, tensor
+from tests.gpu_helpers import log, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1809_01971_amd as tp
+    c = tp.Context(0, workspace_bytes=4 << 30)
+    yield c
+    c.close()
+
+
+def _solve(ctx, ns, F, w, prec, eps, tau, cap, q, alpha=0.5, cn=1.0, cp=1e-2, op_terms=40, pre_terms=28):
+    import paper_1809_01971_amd as tp
+    from paper_1809_01971_amd._tp import sketch_tensors
+    d = len(ns)
+    op, pre, errs = ctx.symbol_build(d, ns, alpha, cn, cp, prec=prec, op_terms=op_terms, pre_terms=pre_terms)
+    X = tp.Tensor(d, ns, cap, prec)
+    sk = sketch_tensors(workloads.sketch_matrices(ns, d, q))
+    st, info = ctx.pcg_solve(op, pre, w, F, X, tau=tau, kmax=100, trunc_tol=eps, cap=cap, sketch=sk)
+    return X, info
+
+
+@pytest.mark.parametrize("ns,prec", [((31, 63, 127), 0), ((127, 255), 0), ((255, 15, 63), 1), ((1, 7, 3), 0)])
+def test_grids_of_different_size_per_mode(ctx, ns, prec):
+    """Each mode its own n (its own eigenvalues, sine transform length and factor height), the
+    smallest grids (n = 1, 3) included: the whole grid against O1."""
+    d = len(ns)
+    rng = np.random.default_rng(31)
+    F = [rng.standard_normal((n, 2)) for n in ns]
+    w = np.ones(2)
+    log("grid %s prec=%d" % (ns, prec))
+    eps, tau = (1e-9, 3e-8) if prec == 0 else (1e-5, 4e-5)
+    X, info = _solve(ctx, ns, F, w, prec, eps, tau, cap=48, q=64)
+    u = exact.solve_full(tensor.cp_full(w, F), 0.5, 1.0, 1e-2)
+    err = rel(ctx.eval_grid(X, [np.arange(n) for n in ns]), u)
+    log("  err %.2e info %s" % (err, info))
+    assert info["status"] in (0, 4)
+    assert all(r <= min(n, 48) for r, n in zip(info["rank"], ns))
+    assert err < (1e-6 if prec == 0 else 1e-4)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_zero_right_hand_side(ctx, prec):
+    """b = 0: the solve returns X = 0 (all ranks 0) without iterating, and evaluates to zeros."""
+    n, d = 63, 3
+    F = [np.zeros((n, 1)) for _ in range(d)]
+    X, info = _solve(ctx, (n,) * d, F, np.zeros(1), prec, 1e-6, 4e-6, cap=16, q=32)
+    log("zero rhs prec=%d: %s" % (prec, info))
+    assert info["status"] == 0 and info["iters"] == 0 and info["rank"] == [0, 0, 0]
+    assert np.all(ctx.eval_grid(X, [np.arange(0, n, 7)] * d) == 0.0)
+
+
+def test_indices_outside_the_grid_give_nan(ctx):
+    """tp_eval_grid and tp_symbol_eval bound every index they read with: points with an index
+    outside [0, n) are NaN, the others are unchanged."""
+    n, d = 63, 3
+    rng = np.random.default_rng(32)
+    F = [rng.standard_normal((n, 1)) for _ in range(d)]
+    X, info = _solve(ctx, (n,) * d, F, np.ones(1), 0, 1e-9, 3e-8, cap=32, q=48)
+    rows = [np.array([0, 5, n, -1]), np.array([1, 2]), np.array([3])]
+    v = ctx.eval_grid(X, rows)
+    ref = ctx.eval_grid(X, [np.array([0, 5]), np.array([1, 2]), np.array([3])])
+    assert np.all(np.isnan(v[2:])) and np.array_equal(v[:2], ref)
+    op, pre, _ = ctx.symbol_build(d, n, 0.5, 1.0, 1e-2, prec=0, op_terms=32, pre_terms=12)
+    pre_r, _ = ctx.symbol_build(d, n, 0.5, 1.0, 1e-2, prec=0, op_terms=32, pre_terms=28, pre_rank=3)[1:]
+    idx = np.array([[0, 0, 0], [n, 0, 0], [0, -1, 0], [0, 0, n + 5], [n - 1, n - 1, n - 1]])
+    for sym in (op, pre, pre_r):
+        s = sym.eval(idx)
+        assert np.all(np.isnan(s[1:4])) and np.all(np.isfinite(s[[0, 4]]))
+    lam = spectral.eigenvalues(n)
+    rho = lam[[0, n - 1]] * 3
+    so = op.eval(idx[[0, 4]])
+    assert np.abs(so / spectral.symbol(rho, 0.5, 1.0, 1e-2) - 1).max() < 1e-4
+
+
+def test_largest_cap_and_sketch(ctx):
+    """cap = 128 (the largest Tucker rank) with the widest sketch q = 192 on a 2D problem whose
+    solution needs more than 128 ranks at eps = 1e-8 (16 Gaussian terms): the ranks stop at the
+    cap, the iteration stops at the floor the cap sets (TP_ENOCONV with the best iterate), and the
+    error estimate it reports is the true error."""
+    n = 511
+    rng = np.random.default_rng(33)
+    F = [rng.standard_normal((n, 16)) for _ in range(2)]
+    w = np.ones(16)
+    X, info = _solve(ctx, (n, n), F, w, 0, 1e-8, 4e-8, cap=128, q=192)
+    u = exact.solve_full(tensor.cp_full(w, F), 0.5, 1.0, 1e-2)
+    err = rel(ctx.eval_grid(X, [np.arange(n)] * 2), u)
+    log("cap 128 / q 192: err %.2e info %s" % (err, info))
+    assert info["status"] in (0, 3, 4) and max(info["rank"]) <= 128
+    if info["status"] == 0:
+        assert err < 1e-6
+    else:
+        assert err < 1e-4 and 0.5 < err / info["err_est"] < 2.0
+
+
+def test_invalid_arguments_on_a_live_context(ctx):
+    """Each invalid request raises with a message; the context keeps working afterwards."""
+    import paper_1809_01971_amd as tp
+    from paper_1809_01971_amd._tp import sketch_tensors
+    n, d = 63, 3
+    bad_symbols = [dict(alpha=1.5), dict(alpha=0.0), dict(c_neg=-1.0), dict(c_neg=0.0, c_pos=0.0), dict(beta=1.5),
+                   dict(c0=-1.0), dict(pre_rank=17), dict(pre_terms=65), dict(op_terms=1),
+                   dict(directional=True, beta=0.5), dict(method=1, c0=1.0), dict(n=100), dict(n=0)]
+    for bad in bad_symbols:
+        kw = dict(n=n, alpha=0.5, c_neg=1.0, c_pos=1e-2)
+        kw.update(bad)
+        with pytest.raises(tp.TPError) as e:
+            ctx.symbol_build(d, kw.pop("n"), kw.pop("alpha"), kw.pop("c_neg"), kw.pop("c_pos"), prec=0, **kw)
+        assert e.value.status == tp.TP_EINVAL, bad
+    op, pre, _ = ctx.symbol_build(d, n, 0.5, 1.0, 1e-2, prec=0, op_terms=32, pre_terms=12)
+    F = [np.ones((n, 1))] * d
+    X = tp.Tensor(d, n, 16, 0)
+    sk = sketch_tensors(workloads.sketch_matrices(n, d, 32))
+    base = dict(tau=1e-6, kmax=100, trunc_tol=1e-8, cap=16, sketch=sk)
+    bad_solves = [(op, pre, X, dict(cap=17)), (op, pre, X, dict(cap=0)), (op, pre, X, dict(tau=0.0)),
+                  (op, pre, X, dict(kmax=0)), (op, pre, X, dict(stop_rule=2)), (pre, op, X, {}),
+                  (op, pre, X, dict(sketch=sketch_tensors(workloads.sketch_matrices(n, d, 1)))),
+                  (op, pre, tp.Tensor(d, n, 16, 1), {}), (op, pre, tp.Tensor(d, 127, 16, 0), {})]
+    for o, p_, x, bad in bad_solves:
+        kw = dict(base)
+        kw.update(bad)
+        with pytest.raises(tp.TPError) as e:
+            ctx.pcg_solve(o, p_, np.ones(1), F, x, allow=(), **kw)
+        assert e.value.status == tp.TP_EINVAL, bad
+    st, info = ctx.pcg_solve(op, pre, np.ones(1), F, X, **base)
+    assert info["status"] in (0, 4)

@@ -136,10 +136,12 @@ def precond_problem(eq, alpha, n, d, kind="ones", seed=7):
 
 
 def sketch_matrices(n, d, q, seed=1000):
-    """Gaussian test matrices Omega^(l) (n x q), one per mode, for the sketched
-    range finder of the truncation (drawn once, passed to the library)."""
+    """Gaussian test matrices Omega^(l) (n_l x q), one per mode, for the sketched
+    range finder of the truncation (drawn once, passed to the library).  n: one size
+    for every mode or a sequence of d sizes."""
     rng = np.random.default_rng(seed)
-    return [rng.standard_normal((n, q)) for _ in range(d)]
+    ns = list(n) if hasattr(n, "__len__") else [n] * d
+    return [rng.standard_normal((ns[l], q)) for l in range(d)]
 
 
 def restriction_rows(n, stride):
