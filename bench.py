@@ -26,14 +26,14 @@ PEAK = {"fp32_vector_tflops": 157.3, "fp64_vector_tflops": 78.6, "hbm_gbs": 8000
 
 # Solver settings per precision (documented in the design doc)
 SETTINGS = {
-    "mixed": dict(prec=1, eps=3e-5, tau=1.2e-4, cap=48, q=64, op_terms=28, pre_terms=28),
+    "mixed": dict(prec=1, eps=3e-5, tau=1.2e-4, cap=48, q=56, op_terms=28, pre_terms=28),
     "fp64": dict(prec=0, eps=1.5e-7, tau=6e-7, cap=96, q=112, op_terms=36, pre_terms=36),
 }
 ERR_SLAB_STRIDE = 4  # exact error over every 4th first-index spectral slab (unbiased sample)
 # HBM bytes per launch of the Gram eigensolver from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (each
 # scaled by the reading of a 256 MiB device copy); valid only for the kernel source they were
 # taken on, identified by the SHA-256 prefix of csrc/kernels.hip.
-TRAFFIC = {"gram_eig": {"src": "53769f09b6053277", "bytes_per_launch": 249582}}
+TRAFFIC = {"gram_eig": {"src": "dc5d3d16b78eee2b", "bytes_per_launch": 224939}}
 
 
 def log(msg):
