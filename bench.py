@@ -26,14 +26,23 @@ PEAK = {"fp32_vector_tflops": 157.3, "fp64_vector_tflops": 78.6, "hbm_gbs": 8000
 
 # Solver settings per precision (documented in the design doc)
 SETTINGS = {
-    "mixed": dict(prec=1, eps=3e-5, tau=1.2e-4, cap=48, q=56, op_terms=28, pre_terms=28),
+    "mixed": dict(prec=1, eps=3e-5, tau=1.2e-4, cap=56, q=64, op_terms=28, pre_terms=28),
     "fp64": dict(prec=0, eps=1.5e-7, tau=6e-7, cap=96, q=112, op_terms=36, pre_terms=36),
 }
 ERR_SLAB_STRIDE = 4  # exact error over every 4th first-index spectral slab (unbiased sample)
 # HBM bytes per launch of the Gram eigensolver from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (each
-# scaled by the reading of a 256 MiB device copy); valid only for the kernel source they were
-# taken on, identified by the SHA-256 prefix of csrc/kernels.hip.
-TRAFFIC = {"gram_eig": {"src": "dc5d3d16b78eee2b", "bytes_per_launch": 224939}}
+# scaled by the reading of a 256 MiB device copy); valid only for the kernel source and the mixed
+# settings they were taken with, identified by the SHA-256 prefix of csrc/kernels.hip followed by
+# the settings' JSON (traffic_key below).
+TRAFFIC = {"gram_eig": {"src": "692805d60ac25e94", "bytes_per_launch": 249562}}
+
+
+def traffic_key():
+    import hashlib
+    src = os.path.join(ROOT, "paper_1809_01971_amd", "csrc", "kernels.hip")
+    with open(src, "rb") as fh:
+        data = fh.read() + json.dumps(SETTINGS["mixed"], sort_keys=True).encode()
+    return hashlib.sha256(data).hexdigest()[:16]
 
 
 def log(msg):
@@ -101,6 +110,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fp64-steps", type=int, default=None)
+    ap.add_argument("--batch-steps", type=int, default=2,
+                    help="timed calls of the concurrent leg: 16 independent problems of the workload's "
+                         "shape on 8 streams per call (0 skips it)")
     ap.add_argument("--spectral-steps", type=int, default=None,
                     help="timed steps of the spectral-domain variant (default: --steps; 0 skips it)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -150,6 +162,34 @@ def main():
                     "rel_diff_vs_stated_path": float(np.linalg.norm(a - b) / np.linalg.norm(b)),
                     "note": "outside the paper: PCG in DST coordinates, same settings"}
 
+    batched = None
+    if args.batch_steps > 0:
+        # independent control problems of the same shape (16 right-hand sides, seeds 2 and up: the
+        # first is the workload itself) solved concurrently by tp_pcg_solve_batched on 8 streams;
+        # each call includes its host preparation and its per-stream workspace allocation
+        from paper_1809_01971_amd._tp import batch_solve
+        probs = [workloads.cfg3(seed=2 + i) for i in range(16)]
+        sks = {p.n: sk_by_q[SETTINGS["mixed"]["q"]]}
+        log("bench: batched 16 problems x %d calls" % args.batch_steps)
+
+        def one_batch():
+            return batch_solve(ctx, probs, lambda _: SETTINGS["mixed"], sks, streams=8,
+                               workspace_per_stream=4 << 30)
+        one_batch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.batch_steps):
+            outs, res = one_batch()
+        torch.cuda.synchronize()
+        dtb = time.perf_counter() - t0
+        rows = [np.arange(0, p.n, 16)] * 3
+        a, b = ctx.eval_grid(outs[0], rows), ctx.eval_grid(Xm, rows)
+        batched = {"problems": 16, "streams": 8, "solves_per_s": 16 * args.batch_steps / dtb,
+                   "ms_per_call": 1000.0 * dtb / args.batch_steps,
+                   "iters": sorted({r["iters"] for r in res}), "statuses": sorted({r["status"] for r in res}),
+                   "rel_diff_first_vs_single": float(np.linalg.norm(a - b) / np.linalg.norm(b)),
+                   "note": "16 independent n=2047 control problems (rhs seeds 2-17) per call, concurrent"}
+
     value = args.steps / dtm
     ms = 1000.0 * dtm / args.steps
 
@@ -166,7 +206,8 @@ def main():
     kernels = {"gemm_f64": "k_gemm_mfma<double, double, double, double>", "gemm_f32": "k_gemm_mfma<float, float, float, float>",
                "gemm_f32_f64": "k_gemm_mfma<float, float, double, double>",
                "gemm_f64_f32": "k_gemm_mfma<double, double, float, double>", "dst_f64": "k_dst1<double>",
-               "dst_f32": "k_dst1<float>", "syev": "k_syev_small", "chol": "k_pchol", "gram_eig": "k_psd_eig"}
+               "dst_f32": "k_dst1<float>", "syev": "k_psd_eig (symbol fits)", "chol": "k_pchol",
+               "gram_eig": "k_psd_eig"}
     dom = max(prof, key=lambda k: prof[k]["ms"])
     pd = prof[dom]
     bound, peak, unit = peaks[dom]
@@ -177,12 +218,8 @@ def main():
         achieved = pd["bytes"] / (pd["ms"] * 1e-3) / 1e9 if pd["ms"] > 0 else 0.0
         per_launch = pd["bytes"] / max(pd["launches"], 1)
     traffic = None
-    if dom in TRAFFIC:
-        import hashlib
-        src = os.path.join(ROOT, "paper_1809_01971_amd", "csrc", "kernels.hip")
-        with open(src, "rb") as fh:
-            if hashlib.sha256(fh.read()).hexdigest()[:16] == TRAFFIC[dom]["src"]:
-                traffic = TRAFFIC[dom]["bytes_per_launch"]
+    if dom in TRAFFIC and traffic_key() == TRAFFIC[dom]["src"]:
+        traffic = TRAFFIC[dom]["bytes_per_launch"]
     roofline = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
                 "traffic": traffic, "kernel": kernels[dom], "class": dom, "launches_per_step": pd["launches"] / args.steps,
                 "avg_launch_us": 1000.0 * pd["ms"] / max(pd["launches"], 1),
@@ -227,6 +264,7 @@ def main():
         "iters_fp64": infd[-1]["iters"], "ranks_fp64": infd[-1]["rank"],
         "symbol_err_mixed": infm[-1]["sym_err"][0], "precond_err": infm[-1]["sym_err"][1],
         "spectral_domain_mixed": spectral,
+        "batched_mixed": batched,
         "roofline": roofline, "kernel_breakdown": breakdown, "work": work, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -322,7 +322,7 @@ typedef enum {
   TP_PROF_GEMM_F64_F32 = 3,  /* FP64 operands rounded into FP32 results */
   TP_PROF_DST_F64 = 4,
   TP_PROF_DST_F32 = 5,
-  TP_PROF_SYEV = 6,          /* two-sided Jacobi (least-squares fits of the symbols) */
+  TP_PROF_SYEV = 6,          /* eigensolves of the symbols' least-squares fits (Gram eigensolver) and tp_syev */
   TP_PROF_CHOL = 7,          /* pivoted Cholesky of Gram matrices (orthonormal bases) */
   TP_PROF_GRAM_EIG = 8       /* Gram eigensolver of the HOSVD (Cholesky + one-sided Jacobi) */
 } tp_prof_class;
