@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <atomic>
+#include <functional>
 #include <map>
 #include <thread>
 #include <string>
@@ -764,11 +765,15 @@ tp_status unit_symbol(tp_ctx* c, int n, const T** f, const double** w);
 //  4. projected core M = sum_t coef_t sum_k sigma_k C x_1 P1_k x_2 P2_k x_3 P3_k with
 //     P_m[a,(i,k)] = sum_x Q_m(x,a) Vh_m(x,i) s_m(x,k),
 //  5. HOSVD of M (ranks by tolerance and cap), factors F(Q_m U_m).
+// stop_early (optional) is called with ||M||^2 between steps 4 and 5 (||M|| is the norm of the sum up
+// to the range finder's error); when it returns true the call ends there and y is left unchanged.
+using EarlyStop = std::function<bool(double)>;
 template <typename T>
 tp_status combo_impl(tp_ctx* c, const Term* terms, int nt, tp_tensor* y, double tol, int cap, const tp_sketch* sk,
-                     bool* capped) {
+                     bool* capped, const EarlyStop* stop_early = nullptr) {
   using Tacc = T;
   WsScope scope(c);
+  *capped = false;
   const int d = y->d;
   const int Qs = sk->q;
   std::vector<Term> tv;
@@ -946,6 +951,13 @@ tp_status combo_impl(tp_ctx* c, const Term* terms, int nt, tp_tensor* y, double 
       TPCHK((mm<T, T, T, Tacc>(c, false, true, q[0], q[1], r[1] * R, tv[t].coef, D, q[0], Pm[1], q[1], beta, M, q[0])));
     }
   }
+  if (stop_early) {
+    double* part;
+    TPCHK(wsalloc(c, 256, &part));
+    HIPCHK(dot<T>(M, M, (long)msz, c->dmap, part, c->stream));  // into mapped host memory
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if ((*stop_early)(c->hmap[0])) return TP_OK;
+  }
   // HOSVD of the projected core
   int rn[3] = {1, 1, 1};
   double* U[3];
@@ -970,9 +982,9 @@ tp_status combo_impl(tp_ctx* c, const Term* terms, int nt, tp_tensor* y, double 
 
 template <typename T>
 tp_status apply_impl(tp_ctx* c, const tp_symbol* S, const tp_tensor* x, tp_tensor* y, double tol, int cap,
-                     const tp_sketch* sk, bool* capped) {
+                     const tp_sketch* sk, bool* capped, const EarlyStop* stop_early = nullptr) {
   Term t{S, x, 1.0};
-  return combo_impl<T>(c, &t, 1, y, tol, cap, sk, capped);
+  return combo_impl<T>(c, &t, 1, y, tol, cap, sk, capped, stop_early);
 }
 
 // <x, F(s (.) F y)> exactly, from the spectral factors: sum_k sigma_k <Cx, Cy x_m G_m,k> with
@@ -2042,18 +2054,34 @@ tp_status pcg_impl(tp_ctx* c, const tp_symbol* op, const tp_symbol* pre, const t
       info->err_est = info->rel_res;
       if (info->err_est <= o->tau) { converged = true; ++k; break; }
     }
-    TPCHK(apply_impl<T>(c, pre, &R, &Z, eps, cap, sk, &capped));
-    anycap |= capped;
-    info->op_applies += 1;
     if (o->stop_rule == TP_STOP_ERROR) {
       // "R sufficiently small": the preconditioned residual Z ~ A_2^-1 R estimates the error of X,
       // so the test ||Z|| <= tau ||X|| bounds the relative error instead of the residual (whose
-      // norm under-weights the smooth error components by s_min/s_max)
-      double zz = 0, xx = 0;
-      TPCHK(inner_impl<T>(c, &Z, &Z, &zz));
+      // norm under-weights the smooth error components by s_min/s_max).  ||Z|| is taken from the
+      // projected core of the product (before its HOSVD), and the product is only completed into Z
+      // when the iteration goes on.
+      double xx = 0, zz = -1.0;
       TPCHK(inner_impl<T>(c, &X, &X, &xx));
-      info->err_est = std::sqrt(std::max(zz, 0.0) / std::max(xx, 1e-300));
-      if (info->err_est <= o->tau) { converged = true; ++k; break; }
+      bool stop_now = false;
+      const EarlyStop test = [&](double nz2) {
+        zz = nz2;
+        info->err_est = std::sqrt(std::max(nz2, 0.0) / std::max(xx, 1e-300));
+        stop_now = info->err_est <= o->tau;
+        return stop_now;
+      };
+      TPCHK(apply_impl<T>(c, pre, &R, &Z, eps, cap, sk, &capped, &test));
+      info->op_applies += 1;
+      if (stop_now) { converged = true; ++k; break; }
+      anycap |= capped;
+      if (zz < 0.0) {  // the product ended before its projection (a zero sum): Z itself
+        TPCHK(inner_impl<T>(c, &Z, &Z, &zz));
+        info->err_est = std::sqrt(std::max(zz, 0.0) / std::max(xx, 1e-300));
+        if (info->err_est <= o->tau) { converged = true; ++k; break; }
+      }
+    } else {
+      TPCHK(apply_impl<T>(c, pre, &R, &Z, eps, cap, sk, &capped));
+      anycap |= capped;
+      info->op_applies += 1;
     }
     // Safeguard (not part of the method): once the truncated iteration has reached the floor
     // set by the working precision or by the rank cap, further steps only amplify rounding
