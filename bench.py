@@ -30,18 +30,21 @@ SETTINGS = {
     "fp64": dict(prec=0, eps=1.5e-7, tau=6e-7, cap=96, q=112, op_terms=36, pre_terms=36),
 }
 ERR_SLAB_STRIDE = 4  # exact error over every 4th first-index spectral slab (unbiased sample)
-# HBM bytes per launch of the Gram eigensolver from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (each
-# scaled by the reading of a 256 MiB device copy); valid only for the kernel source and the mixed
-# settings they were taken with, identified by the SHA-256 prefix of csrc/kernels.hip followed by
-# the settings' JSON (traffic_key below).
-TRAFFIC = {"gram_eig": {"src": "692805d60ac25e94", "bytes_per_launch": 249562}}
+# HBM bytes per launch of each timing class (a split-K reduction counted with the contraction it
+# follows) from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, each scaled by the reading of a 256 MiB
+# device copy; valid only for the sources and mixed settings they were taken with, identified by
+# traffic_key() (SHA-256 prefix of csrc/kernels.hip, csrc/api.hip and the settings' JSON).
+TRAFFIC = {"src": "dd54eb1f16fb8f09", "bytes_per_launch": {"gemm_f32": 20184791, "gram_eig": 236331, "gemm_f64": 7726803,
+                                               "gemm_f32_f64": 13657744, "gemm_f64_f32": 1515659}}
 
 
 def traffic_key():
     import hashlib
-    src = os.path.join(ROOT, "paper_1809_01971_amd", "csrc", "kernels.hip")
-    with open(src, "rb") as fh:
-        data = fh.read() + json.dumps(SETTINGS["mixed"], sort_keys=True).encode()
+    data = b""
+    for f in ("kernels.hip", "api.hip"):
+        with open(os.path.join(ROOT, "paper_1809_01971_amd", "csrc", f), "rb") as fh:
+            data += fh.read()
+    data += json.dumps(SETTINGS["mixed"], sort_keys=True).encode()
     return hashlib.sha256(data).hexdigest()[:16]
 
 
@@ -194,10 +197,12 @@ def main():
     ms = 1000.0 * dtm / args.steps
 
     # roofline of the dominant kernel class in the timed region
-    peaks = {"gemm_f64": ("alu", PEAK["fp64_vector_tflops"], "TFLOP/s"),
-             "gemm_f32": ("alu", PEAK["fp32_vector_tflops"], "TFLOP/s"),
-             "gemm_f32_f64": ("alu", PEAK["fp32_vector_tflops"], "TFLOP/s"),
-             "gemm_f64_f32": ("alu", PEAK["fp64_vector_tflops"], "TFLOP/s"),
+    # the contractions run on the FP32 / FP64 matrix cores (16x16x4 MFMA; on MI355X their dense
+    # peaks equal the vector peaks)
+    peaks = {"gemm_f64": ("mfma", PEAK["fp64_vector_tflops"], "TFLOP/s"),
+             "gemm_f32": ("mfma", PEAK["fp32_vector_tflops"], "TFLOP/s"),
+             "gemm_f32_f64": ("mfma", PEAK["fp32_vector_tflops"], "TFLOP/s"),
+             "gemm_f64_f32": ("mfma", PEAK["fp64_vector_tflops"], "TFLOP/s"),
              "dst_f64": ("hbm", PEAK["hbm_gbs"], "GB/s"), "dst_f32": ("hbm", PEAK["hbm_gbs"], "GB/s"),
              "syev": ("alu", PEAK["fp64_vector_tflops"], "TFLOP/s"),
              "chol": ("alu", PEAK["fp64_vector_tflops"], "TFLOP/s"),
@@ -218,12 +223,13 @@ def main():
         achieved = pd["bytes"] / (pd["ms"] * 1e-3) / 1e9 if pd["ms"] > 0 else 0.0
         per_launch = pd["bytes"] / max(pd["launches"], 1)
     traffic = None
-    if dom in TRAFFIC and traffic_key() == TRAFFIC[dom]["src"]:
-        traffic = TRAFFIC[dom]["bytes_per_launch"]
+    if traffic_key() == TRAFFIC["src"]:
+        traffic = TRAFFIC["bytes_per_launch"].get(dom)
     roofline = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
                 "traffic": traffic, "kernel": kernels[dom], "class": dom, "launches_per_step": pd["launches"] / args.steps,
                 "avg_launch_us": 1000.0 * pd["ms"] / max(pd["launches"], 1),
-                "algorithmic_per_launch": per_launch}
+                "algorithmic_per_launch": per_launch,
+                "algorithmic_bytes_per_launch": pd["bytes"] / max(pd["launches"], 1)}
     breakdown = {k: {"ms_per_step": v["ms"] / args.steps, "launches_per_step": v["launches"] / args.steps}
                  for k, v in prof.items() if v["launches"] > 0}
     work = {"gflop_per_step": sum(v["flops"] for v in prof.values()) / args.steps / 1e9,
