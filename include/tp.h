@@ -252,6 +252,9 @@ typedef struct {
                                * factors (F orthogonal: inner products and truncations unchanged),
                                * and only X is transformed back at the end; the products skip
                                * their two transforms.  Same result up to rounding. */
+  int32_t warm_start;         /* 1: x holds the initial guess X^(0) of Algorithm alg:pcg on entry
+                               * (mode ranks <= cap; ranks 0 = zero), R^(0) = trunc(B - fun(X^(0)));
+                               * 0: X^(0) = 0 and x is output only */
 } tp_pcg_opts;
 
 typedef struct {
@@ -279,6 +282,16 @@ typedef struct {
 tp_status tp_pcg_solve(tp_ctx* ctx, const tp_symbol* op, const tp_symbol* pre,
                        const tp_cp* b, tp_tensor* x, const tp_pcg_opts* opts,
                        const tp_sketch* sketch, tp_pcg_info* info);
+
+/* Workspace.  tp_workspace_query: a conservative estimate (host out, bytes) of the workspace
+ * that tp_symbol_build(desc) followed by tp_pcg_solve with opts, a sketch of width sketch_q and a
+ * right-hand side of canonical rank rhs_rank needs (the largest transient arrays of the product,
+ * the symbol inner products and the sums, plus the iteration's tensors).  Needs no context.
+ * tp_workspace_peak: the high-water mark of ctx's workspace since tp_create or the last reset
+ * (reset != 0 restarts it from the current use). */
+tp_status tp_workspace_query(const tp_symbol_desc* desc, const tp_pcg_opts* opts, int32_t sketch_q,
+                             int32_t rhs_rank, size_t* bytes);
+tp_status tp_workspace_peak(tp_ctx* ctx, int32_t reset, size_t* peak);
 
 /* Many independent control problems (arrays of `count` entries, all host arrays of structs
  * whose tensor/sketch pointers are device memory): problem i builds its symbols from descs[i]

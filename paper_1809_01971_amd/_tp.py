@@ -48,7 +48,7 @@ class tp_symbol_desc(C.Structure):
 class tp_pcg_opts(C.Structure):
     _fields_ = [("tau", C.c_double), ("kmax", C.c_int32), ("trunc_tol", C.c_double), ("cap", C.c_int32),
                 ("true_residual", C.c_int32), ("stop_rule", C.c_int32),
-                ("recursive_residual", C.c_int32), ("spectral_domain", C.c_int32)]
+                ("recursive_residual", C.c_int32), ("spectral_domain", C.c_int32), ("warm_start", C.c_int32)]
 
 
 class tp_pcg_info(C.Structure):
@@ -78,6 +78,9 @@ _SIGS = {
     "tp_apply_sum": ([P, C.c_int32, C.POINTER(P), C.POINTER(C.POINTER(tp_tensor)), C.POINTER(C.c_double),
                       C.POINTER(tp_tensor), C.c_double, C.c_int32, C.POINTER(tp_sketch)], C.c_int),
     "tp_eval_grid": ([P, C.POINTER(tp_tensor), C.POINTER(P), C.POINTER(C.c_int32), P], C.c_int),
+    "tp_workspace_query": ([C.POINTER(tp_symbol_desc), C.POINTER(tp_pcg_opts), C.c_int32, C.c_int32,
+                            C.POINTER(C.c_size_t)], C.c_int),
+    "tp_workspace_peak": ([P, C.c_int32, C.POINTER(C.c_size_t)], C.c_int),
     "tp_pcg_solve": ([P, P, P, C.POINTER(tp_cp), C.POINTER(tp_tensor), C.POINTER(tp_pcg_opts),
                       C.POINTER(tp_sketch), C.POINTER(tp_pcg_info)], C.c_int),
     "tp_dst": ([P, C.c_int32, C.c_int32, C.c_int32, P, P], C.c_int),
@@ -201,6 +204,12 @@ class Context:
             out[name] = {"ms": v[0].value, "launches": v[1].value, "flops": v[2].value, "bytes": v[3].value}
         return out
 
+    # ---- workspace
+    def workspace_peak(self, reset=False):
+        v = C.c_size_t()
+        _check(self.lib.tp_workspace_peak(self.h, 1 if reset else 0, C.byref(v)))
+        return v.value
+
     # ---- symbols
     def symbol_build(self, d, n, alpha, c_neg, c_pos, prec=TP_FP64, method=TP_SYM_FIT, op_terms=0,
                      pre_terms=0, sinc_kl=0, sinc_kr=0, sinc_h=0.0, c0=0.0, beta=0.0, pre_rank=0,
@@ -292,11 +301,12 @@ class Context:
             list(range(len(rows)))[::-1])
 
     def pcg_solve(self, op, pre, weights, factors, x, tau, kmax, trunc_tol, cap, sketch, true_residual=False,
-                  allow=(TP_ERANK, TP_ENOCONV), stop_rule=0, recursive_residual=False, spectral_domain=False):
+                  allow=(TP_ERANK, TP_ENOCONV), stop_rule=0, recursive_residual=False, spectral_domain=False,
+                  warm_start=False):
         keep, cp = cp_struct(weights, factors)
         sk, keep2 = sketch_struct(sketch)
         o = tp_pcg_opts(tau, kmax, trunc_tol, cap, 1 if true_residual else 0, stop_rule,
-                        1 if recursive_residual else 0, 1 if spectral_domain else 0)
+                        1 if recursive_residual else 0, 1 if spectral_domain else 0, 1 if warm_start else 0)
         info = tp_pcg_info()
         st = _check(self.lib.tp_pcg_solve(self.h, op.h, pre.h, C.byref(cp), C.byref(x.s), C.byref(o),
                                           C.byref(sk), C.byref(info)), allow=allow)
@@ -309,12 +319,25 @@ class Context:
 def _desc(d, n, alpha, c_neg, c_pos, prec, op_terms, pre_terms):
     desc = tp_symbol_desc()
     desc.d = d
+    ns = mode_sizes(d, n)
     for m in range(3):
-        desc.n[m] = n if m < d else 0
+        desc.n[m] = ns[m] if m < d else 0
     desc.alpha, desc.c_neg, desc.c_pos = alpha, c_neg, c_pos
     desc.method, desc.op_terms, desc.pre_terms = TP_SYM_FIT, op_terms, pre_terms
     desc.prec = prec
     return desc
+
+
+def workspace_query(d, n, alpha, settings, rhs_rank, c_neg=1.0, c_pos=1e-2, **desc_kw):
+    """tp_workspace_query for a symbol descriptor and PCG settings (prec, eps, tau, cap, q, op_terms,
+    pre_terms): the estimated workspace bytes of one symbol build and solve."""
+    desc = _desc(d, n, alpha, c_neg, c_pos, settings["prec"], settings["op_terms"], settings["pre_terms"])
+    for k, v in desc_kw.items():
+        setattr(desc, k, v)
+    o = tp_pcg_opts(settings["tau"], 100, settings["eps"], settings["cap"], 0, 0, 0, 0, 0)
+    v = C.c_size_t()
+    _check(load_library().tp_workspace_query(C.byref(desc), C.byref(o), settings["q"], rhs_rank, C.byref(v)))
+    return v.value
 
 
 def batch_solve(ctx, problems, settings, sketches, streams=8, workspace_per_stream=0):
@@ -337,7 +360,7 @@ def batch_solve(ctx, problems, settings, sketches, streams=8, workspace_per_stre
         X = Tensor(p.d, p.n, s["cap"], s["prec"])
         outs.append(X)
         tens[i] = X.s
-        opts[i] = tp_pcg_opts(s["tau"], 100, s["eps"], s["cap"], 0, 0, 0, 1 if s.get("spectral") else 0)
+        opts[i] = tp_pcg_opts(s["tau"], 100, s["eps"], s["cap"], 0, 0, 0, 1 if s.get("spectral") else 0, 0)
         sk, k2 = sketch_struct(sketches[p.n])
         sks[i] = sk
     _check(ctx.lib.tp_pcg_solve_batched(ctx.h, cnt, descs, cps, tens, opts, sks, infos, streams,

@@ -61,6 +61,7 @@ struct tp_ctx {
   hipStream_t stream = nullptr;
   char* ws = nullptr;
   size_t ws_size = 0, ws_top = 0;
+  size_t ws_peak = 0;            // high-water mark of ws_top (tp_workspace_peak)
   double* host = nullptr;        // pinned host scratch (kHost doubles)
   double* hmap = nullptr;        // mapped, coherent pinned host memory (kMap doubles) that small
   double* dmap = nullptr;        //   kernel results (ranks, eigenvalues, inner products) go to; its device address
@@ -114,6 +115,7 @@ tp_status wsalloc(tp_ctx* c, size_t count, T** out) {
     return fail(TP_ENOMEM, "workspace exhausted: need %zu more bytes (top %zu of %zu)", bytes, c->ws_top, c->ws_size);
   *out = reinterpret_cast<T*>(c->ws + c->ws_top);
   c->ws_top += bytes;
+  if (c->ws_top > c->ws_peak) c->ws_peak = c->ws_top;
   return TP_OK;
 }
 struct WsScope {
@@ -2002,7 +2004,19 @@ tp_status pcg_impl(tp_ctx* c, const tp_symbol* op, const tp_symbol* pre, const t
     return TP_OK;
   }
   const double nb = std::sqrt(nb2);
-  TPCHK(copy_tensor<T>(c, &B, &R));  // R0 = B - fun(X0), X0 = 0 (no truncation)
+  const bool warm = o->warm_start && !is_zero(x);
+  if (warm) {
+    // X0 given: R0 = trunc(B - fun(X0)) (one sketched sum); X0 itself is taken as it is
+    TPCHK(copy_tensor<T>(c, x, &X));
+    if (c->spectral)  // the iteration runs in sine coordinates: transform X0's factors once
+      for (int m = 0; m < x->d; ++m) TPCHK(dst_cols<T>(c, x->n[m], X.rank[m], (const T*)X.factor[m], (T*)X.factor[m]));
+    Term t[2] = {{nullptr, &B, 1.0}, {op, &X, -1.0}};
+    TPCHK(combo_impl<T>(c, t, 2, &R, eps, cap, sk, &capped));
+    anycap |= capped;
+    info->op_applies += 1;
+  } else {
+    TPCHK(copy_tensor<T>(c, &B, &R));  // R0 = B - fun(X0), X0 = 0 (no truncation)
+  }
   TPCHK(apply_impl<T>(c, pre, &R, &Z, eps, cap, sk, &capped));
   anycap |= capped;
   info->op_applies += 1;
@@ -2022,7 +2036,7 @@ tp_status pcg_impl(tp_ctx* c, const tp_symbol* op, const tp_symbol* pre, const t
     TPCHK(inner_sym_impl<T>(c, &P, op, &P, &ps));
     if (!(ps > 0)) return fail(TP_ENOCONV, "PCG breakdown: <P,S> = %g", ps);
     const double a = rz / ps;
-    if (k == 0) {
+    if (k == 0 && !warm) {
       // X0 = 0: X1 = a P exactly (P is already truncated, a sum with zero adds nothing to cut)
       TPCHK(scaled_copy<T>(c, a, &P, &X));
     } else {
@@ -2161,6 +2175,12 @@ extern "C" tp_status tp_pcg_solve(tp_ctx* c, const tp_symbol* op, const tp_symbo
     return fail(TP_EINVAL, "recursive_residual=%d must be 0 or 1", o->recursive_residual);
   if (o->spectral_domain != 0 && o->spectral_domain != 1)
     return fail(TP_EINVAL, "spectral_domain=%d must be 0 or 1", o->spectral_domain);
+  if (o->warm_start != 0 && o->warm_start != 1)
+    return fail(TP_EINVAL, "warm_start=%d must be 0 or 1", o->warm_start);
+  if (o->warm_start)
+    for (int m = 0; m < x->d; ++m)
+      if (x->rank[m] < 0 || x->rank[m] > o->cap)
+        return fail(TP_EINVAL, "warm start: x.rank[%d]=%d outside [0, opts.cap=%d]", m, x->rank[m], o->cap);
   if (sk->q < 2 || sk->q > kMaxSketch) return fail(TP_EINVAL, "sketch q=%d must be in [2,%d]", sk->q, kMaxSketch);
   if (b->rank < 0 || b->rank > kMaxRank) return fail(TP_EINVAL, "b.rank=%d outside [0,%d]", b->rank, kMaxRank);
   tp_status st = x->prec == TP_FP64 ? pcg_impl<double>(c, op, pre, b, x, o, sk, info)
@@ -2170,6 +2190,60 @@ extern "C" tp_status tp_pcg_solve(tp_ctx* c, const tp_symbol* op, const tp_symbo
   if (e != hipSuccess) return fail(TP_EHIP, "stream sync: %s", hipGetErrorString(e));
   if (st == TP_OK && info->status == TP_ERANK) return fail(TP_ERANK, "rank cap reached during the solve");
   return st;
+}
+
+// ------------------------------------------------------------------------------ workspace size
+extern "C" tp_status tp_workspace_peak(tp_ctx* c, int32_t reset, size_t* peak) {
+  if (!c || !peak) return fail(TP_EINVAL, "NULL argument");
+  *peak = c->ws_peak;
+  if (reset) c->ws_peak = c->ws_top;
+  return TP_OK;
+}
+
+extern "C" tp_status tp_workspace_query(const tp_symbol_desc* D, const tp_pcg_opts* o, int32_t q, int32_t rb,
+                                        size_t* bytes) {
+  if (!D || !o || !bytes) return fail(TP_EINVAL, "NULL argument");
+  if (D->d != 2 && D->d != 3) return fail(TP_EINVAL, "d=%d must be 2 or 3", D->d);
+  if (o->cap < 1 || q < 2 || rb < 0) return fail(TP_EINVAL, "cap, sketch width or rhs rank out of range");
+  const int d = D->d;
+  double nmax = 0, nsum = 0;
+  for (int m = 0; m < d; ++m) {
+    if (D->n[m] < 1) return fail(TP_EINVAL, "n[%d]=%d", m, D->n[m]);
+    nmax = std::max(nmax, (double)D->n[m]);
+    nsum += D->n[m];
+  }
+  const double T = D->prec == TP_FP64 ? 8.0 : 4.0, cap = o->cap, Q = q, B = std::max(rb, 1);
+  const int kop = D->method == TP_SYM_SINC ? (D->sinc_kl > 0 ? D->sinc_kl : 60) + (D->sinc_kr > 0 ? D->sinc_kr : 20) + 2
+                                           : (D->op_terms > 0 ? D->op_terms : 32) + 1;
+  const int kpre = D->pre_terms > 0 ? D->pre_terms : 12;
+  const double rop = (double)d * kop + 1, rpre = D->pre_rank > 0 ? std::pow((double)D->pre_rank, d - 1) : kpre;
+  const double R = std::max(rop, rpre);
+  auto pw = [d](double v) { return d == 3 ? v * v * v : v * v; };
+  // the iteration's tensors (B, X, best X, R, P, Z, S and the caller-visible copy)
+  const double tens = 8.0 * (pw(cap) * T + nsum * cap * T);
+  // right-hand side to Tucker form: bases, projected factors, Khatri-Rao product, core, HOSVD
+  const double fromcp = 4.0 * d * nmax * B * 8 + 4.0 * d * B * B * 8 + cap * B * B * 8 + 6.0 * pw(B) * 8;
+  // one sketched product of two terms: inputs in sine coordinates, sketch contractions, sketches
+  // and their bases, projection (the two batched core contractions dominate), HOSVD of the core
+  const double term = d * nmax * cap * T + pw(cap) * T + d * cap * R * Q * T;
+  // (3D: the core contracted with two sketches, r^2 R q, and the two projection stages R q r^2 and
+  // R r q^2; 2D: one stage each, r R q and R q r)
+  const double sk2 = d == 3 ? cap * cap * R * Q * T : 0.0;
+  const double proj = d == 3 ? (R * Q * cap * cap + R * cap * Q * Q) * T : R * Q * cap * T;
+  const double combo = d * nmax * Q * T + 2.0 * term + sk2 + cap * R * Q * T + pw(cap) * T +
+                       d * nmax * Q * 8 * 4 + 4.0 * d * Q * Q * 8 + d * nmax * Q * T + pw(Q) * T +
+                       d * Q * cap * R * T + proj + 6.0 * pw(Q) * 8 + 4.0 * d * Q * Q * 8 + d * nmax * cap * T;
+  // symbol inner product (Grams per term, two batched core contractions)
+  const double isym = 2.0 * d * nmax * cap * T + d * cap * cap * R * 8 + 3.0 * pw(cap) * 8 +
+                      (d == 3 ? 2.0 : 1.0) * R * pw(cap) * 8;
+  // sum of two iterates: concatenated factors, bases, block core and its HOSVD
+  const double c2 = 2 * cap;
+  const double sum = d * nmax * c2 * 8 * 4 + 4.0 * d * c2 * c2 * 8 + 6.0 * pw(c2) * 8 + d * nmax * c2 * T;
+  // least-squares fits of the symbols (design matrices of the candidates)
+  const double fits = 15.0 * 1000 * 64 * 8 * 2 + 15.0 * 64 * 64 * 8 * 4;
+  const double total = tens + fromcp + std::max(std::max(combo, isym), std::max(sum, fits)) + (64 << 20);
+  *bytes = (size_t)(1.25 * total);
+  return TP_OK;
 }
 
 // ------------------------------------------------------------------------------ batched solves

@@ -134,3 +134,96 @@ def test_invalid_arguments_on_a_live_context(ctx):
         assert e.value.status == tp.TP_EINVAL, bad
     st, info = ctx.pcg_solve(op, pre, np.ones(1), F, X, **base)
     assert info["status"] in (0, 4)
+
+
+WS_CASES = [  # (d, n, alpha, settings, symbol extras)
+    (3, 2047, 0.5, dict(prec=1, eps=3e-5, tau=1.2e-4, cap=56, q=64, op_terms=28, pre_terms=28), {}),
+    (3, 1023, 0.5, dict(prec=0, eps=1.5e-7, tau=6e-7, cap=96, q=112, op_terms=36, pre_terms=36), {}),
+    (2, 2047, 0.5, dict(prec=0, eps=1e-9, tau=3e-8, cap=128, q=144, op_terms=40, pre_terms=36), {"pre_rank": 8}),
+    (3, 255, 0.1, dict(prec=0, eps=1e-9, tau=3e-8, cap=64, q=80, op_terms=40, pre_terms=28), {"directional": 1}),
+]
+
+
+@pytest.mark.parametrize("case", range(len(WS_CASES)))
+def test_workspace_query_covers_the_peak(ctx, case):
+    """tp_workspace_query bounds the workspace a symbol build and a solve use (measured high-water
+    mark of the context).  It is a worst case with every rank at the cap: where the ranks reach it
+    (the benchmark's right-hand side, case 0) it overshoots the peak by less than 8x."""
+    import paper_1809_01971_amd as tp
+    from paper_1809_01971_amd._tp import sketch_tensors, workspace_query
+    d, n, alpha, s, extra = WS_CASES[case]
+    if case == 0:
+        p = workloads.cfg3()
+        F, w = p.factors, p.weights
+    else:
+        rng = np.random.default_rng(40 + case)
+        F = [rng.standard_normal((n, 4)) / (1.0 + np.arange(n))[:, None] for _ in range(d)]
+        w = np.ones(4)
+    query = workspace_query(d, n, alpha, s, len(w), **extra)
+    big = tp.Context(0, workspace_bytes=max(query, 8 << 30))
+    try:
+        big.workspace_peak(reset=True)
+        kw = dict(extra)
+        if "directional" in kw:
+            kw["directional"] = True
+        op, pre, _ = big.symbol_build(d, n, alpha, 1.0, 1e-2, prec=s["prec"], op_terms=s["op_terms"],
+                                      pre_terms=s["pre_terms"], **kw)
+        X = tp.Tensor(d, n, s["cap"], s["prec"])
+        sk = sketch_tensors(workloads.sketch_matrices(n, d, s["q"]))
+        st, info = big.pcg_solve(op, pre, w, F, X, tau=s["tau"], kmax=100, trunc_tol=s["eps"], cap=s["cap"],
+                                 sketch=sk)
+        peak = big.workspace_peak()
+    finally:
+        big.close()
+    log("workspace case %d: peak %.1f MiB, query %.1f MiB (%.2fx) info %s" % (case, peak / 2**20, query / 2**20,
+                                                                          query / peak, info))
+    assert peak <= query
+    if case == 0:
+        assert max(info["rank"]) >= 0.85 * s["cap"] and query <= 8 * peak
+
+
+def test_solve_in_a_workspace_of_the_queried_size():
+    """A context whose workspace is exactly the queried size runs the benchmark's mixed solve."""
+    import paper_1809_01971_amd as tp
+    from paper_1809_01971_amd._tp import sketch_tensors, workspace_query
+    d, n, alpha, s, _ = WS_CASES[0]
+    p = workloads.cfg3()
+    q = workspace_query(d, n, alpha, s, len(p.weights))
+    c = tp.Context(0, workspace_bytes=q)
+    try:
+        op, pre, _ = c.symbol_build(d, n, alpha, p.c_neg, p.c_pos, prec=1, op_terms=28, pre_terms=28)
+        X = tp.Tensor(d, n, s["cap"], 1)
+        st, info = c.pcg_solve(op, pre, p.weights, p.factors, X, tau=s["tau"], kmax=100, trunc_tol=s["eps"],
+                               cap=s["cap"], sketch=sketch_tensors(workloads.sketch_matrices(n, d, s["q"])))
+    finally:
+        c.close()
+    log("solve in %.1f MiB: %s" % (q / 2**20, info))
+    assert info["status"] in (0, 4) and info["iters"] == 1
+
+
+@pytest.mark.parametrize("spectral", [False, True])
+def test_warm_start(ctx, spectral):
+    """X^(0) given (Algorithm alg:pcg's initial guess): from a coarse solution (eps 1e-3) the FP64
+    solve reaches O1's solution to 1e-6, and from its own result it stops after one step."""
+    import paper_1809_01971_amd as tp
+    from paper_1809_01971_amd._tp import sketch_tensors
+    p = workloads.cfg2(alpha=0.5, gamma=1e-1, n=63)
+    op, pre, _ = ctx.symbol_build(3, 63, p.alpha, p.c_neg, p.c_pos, prec=0, op_terms=40, pre_terms=36)
+    sk = sketch_tensors(workloads.sketch_matrices(63, 3, 64))
+    X = tp.Tensor(3, 63, 48, 0)
+    ctx.pcg_solve(op, pre, p.weights, p.factors, X, tau=4e-3, kmax=100, trunc_tol=1e-3, cap=48, sketch=sk,
+                  spectral_domain=spectral)
+    coarse = ctx.eval_grid(X, [np.arange(63)] * 3)
+    u = exact.solve_full(tensor.cp_full(p.weights, p.factors), p.alpha, p.c_neg, p.c_pos)
+    st, info = ctx.pcg_solve(op, pre, p.weights, p.factors, X, tau=4e-8, kmax=100, trunc_tol=1e-8, cap=48,
+                             sketch=sk, warm_start=True, spectral_domain=spectral)
+    fine = ctx.eval_grid(X, [np.arange(63)] * 3)
+    log("warm start spectral=%s: coarse err %.2e, warm err %.2e, %s" % (spectral, rel(coarse, u), rel(fine, u), info))
+    assert rel(coarse, u) > 1e-5 and rel(fine, u) < 1e-6
+    st, info2 = ctx.pcg_solve(op, pre, p.weights, p.factors, X, tau=4e-8, kmax=100, trunc_tol=1e-8, cap=48,
+                              sketch=sk, warm_start=True, spectral_domain=spectral)
+    assert info2["iters"] <= 1 and rel(ctx.eval_grid(X, [np.arange(63)] * 3), u) < 1e-6
+    X.s.rank[0] = 49  # a guess with a rank above the cap is rejected before any device work
+    with pytest.raises(tp.TPError):
+        ctx.pcg_solve(op, pre, p.weights, p.factors, X, tau=4e-8, kmax=100, trunc_tol=1e-8, cap=48, sketch=sk,
+                      warm_start=True, allow=())
