@@ -62,6 +62,12 @@ struct tp_ctx {
   char* ws = nullptr;
   size_t ws_size = 0, ws_top = 0;
   size_t ws_peak = 0;            // high-water mark of ws_top (tp_workspace_peak)
+  // batched solves: symbols of a worker live in its workspace (no allocation call, no device-wide
+  // synchronisation when they are freed); the workers are kept for later calls
+  bool sym_arena = false;
+  std::vector<tp_ctx*> workers;
+  std::vector<hipStream_t> worker_streams;
+  size_t worker_ws = 0;
   double* host = nullptr;        // pinned host scratch (kHost doubles)
   double* hmap = nullptr;        // mapped, coherent pinned host memory (kMap doubles) that small
   double* dmap = nullptr;        //   kernel results (ranks, eigenvalues, inner products) go to; its device address
@@ -94,6 +100,7 @@ struct tp_symbol {
   double c0 = 0;         // constant term of the operator symbol (factors all ones)
   double wexact = 0;     // weight of the exact tau = 0 exponential (c_pos rho for beta = 1)
   int tucker = 0;        // > 0: rank-r recompressed preconditioner (general canonical factors)
+  bool arena = false;    // memory in a batched worker's workspace (nothing to free)
   double* weights = nullptr;   // R (device)
   void* factors[3] = {nullptr, nullptr, nullptr};  // n x R (device, T)
   double* tau = nullptr;       // K
@@ -1174,12 +1181,25 @@ tp_status from_cp_impl(tp_ctx* c, const tp_cp* b, tp_tensor* out, double tol, bo
 }
 
 // ------------------------------------------------------------------------------ symbol build
+// Device memory of a symbol: its own allocation (freed by tp_symbol_free), or in a batched worker
+// a block of the worker's workspace below every scope (released after each problem).
+template <typename T>
+tp_status sym_alloc(tp_ctx* c, tp_symbol* s, size_t count, T** p) {
+  if (c->sym_arena) {
+    s->arena = true;
+    return wsalloc(c, count, p);
+  }
+  if (hipMalloc(p, sizeof(T) * std::max<size_t>(count, 1)) != hipSuccess)
+    return fail(TP_ENOMEM, "symbol allocation of %zu bytes failed", sizeof(T) * count);
+  s->owned.push_back(*p);
+  return TP_OK;
+}
+
 template <typename T>
 tp_status build_factors(tp_ctx* c, tp_symbol* s) {
   for (int m = 0; m < s->d; ++m) {
     T* F = nullptr;
-    HIPCHK(hipMalloc(&F, sizeof(T) * (size_t)s->n[m] * s->R));
-    s->owned.push_back(F);
+    TPCHK(sym_alloc(c, s, (size_t)s->n[m] * s->R, &F));
     s->factors[m] = F;
     if (s->kind == 0) {
       for (int blk = 0; blk < s->d; ++blk)
@@ -1193,8 +1213,7 @@ tp_status build_factors(tp_ctx* c, tp_symbol* s) {
       HIPCHK(expfactors<T>(s->lam[m], s->n[m], s->tau, s->K, F, s->n[m], 0, c->stream));
     }
   }
-  HIPCHK(hipMalloc(&s->weights, sizeof(double) * s->R));
-  s->owned.push_back(s->weights);
+  TPCHK(sym_alloc(c, s, (size_t)s->R, &s->weights));
   for (int blk = 0; blk < (s->kind == 0 ? s->d : 1); ++blk)
     HIPCHK(hipMemcpyAsync(s->weights + (size_t)blk * s->K, s->w, sizeof(double) * s->K, hipMemcpyDeviceToDevice, c->stream));
   if (s->kind == 0 && s->R > s->d * s->K)
@@ -1209,6 +1228,11 @@ tp_status build_factors(tp_ctx* c, tp_symbol* s) {
 // Factors are formed in FP64 and stored in the symbol's precision.
 template <typename T>
 tp_status recompress_pre(tp_ctx* c, tp_symbol* s, int r) {
+  // the symbol's factors and weights first (at most r^(d-1) columns), then the scoped temporaries
+  const int Rmax = s->d == 2 ? r : r * r;
+  T* Fout[3] = {nullptr, nullptr, nullptr};
+  for (int m = 0; m < s->d; ++m) TPCHK(sym_alloc(c, s, (size_t)s->n[m] * Rmax, &Fout[m]));
+  TPCHK(sym_alloc(c, s, (size_t)Rmax, &s->weights));
   WsScope scope(c);
   const int d = s->d, K = s->K;
   tp_cp cp{};
@@ -1249,9 +1273,7 @@ tp_status recompress_pre(tp_ctx* c, tp_symbol* s, int r) {
   TPCHK((mm<double, double, double, double>(c, false, true, nl, R, d == 2 ? r1 : r2, 1.0, U[d - 1], nl, core, R, 0.0,
                                             last, nl)));
   for (int m = 0; m < d; ++m) {
-    T* F = nullptr;
-    HIPCHK(hipMalloc(&F, sizeof(T) * (size_t)s->n[m] * R));
-    s->owned.push_back(F);
+    T* F = Fout[m];
     s->factors[m] = F;
     const int n = s->n[m];
     if (m == d - 1) {
@@ -1266,8 +1288,6 @@ tp_status recompress_pre(tp_ctx* c, tp_symbol* s, int r) {
         HIPCHK((copy2d<double, T>(n, r0, U[1] + (size_t)n * b, 0, F + (size_t)n * r0 * b, n, 1.0, c->stream)));
     }
   }
-  HIPCHK(hipMalloc(&s->weights, sizeof(double) * R));
-  s->owned.push_back(s->weights);
   std::vector<double> ones(R, 1.0);
   HIPCHK(hipMemcpyAsync(s->weights, ones.data(), sizeof(double) * R, hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));  // the host vector and the workspace are released here
@@ -1402,6 +1422,17 @@ tp_status fit_expsum(tp_ctx* c, int kind, const SymFn& f, double rho0, double B,
 
 }  // namespace
 
+// Worker contexts of batched solves kept in a context (destroyed with it or when the workspace
+// size of a call changes).
+void release_workers(tp_ctx* c) {
+  for (size_t w = 0; w < c->workers.size(); ++w) {
+    tp_destroy(c->workers[w]);
+    (void)hipStreamDestroy(c->worker_streams[w]);
+  }
+  c->workers.clear();
+  c->worker_streams.clear();
+}
+
 // ==================================================================================== C ABI
 extern "C" {
 
@@ -1434,6 +1465,7 @@ tp_status tp_create(int device, void* stream, size_t workspace_bytes, tp_ctx** o
 
 tp_status tp_destroy(tp_ctx* c) {
   if (!c) return TP_OK;
+  release_workers(c);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
   for (auto& e : c->ev_pool) (void)hipEventDestroy(e);
@@ -1558,8 +1590,7 @@ tp_status tp_symbol_build(tp_ctx* c, const tp_symbol_desc* desc, tp_symbol** op,
     for (int m = 0; m < D.d; ++m) {
       s[i]->n[m] = D.n[m];
       double* l = nullptr;
-      if (hipMalloc(&l, sizeof(double) * D.n[m]) != hipSuccess) return cleanup(fail(TP_ENOMEM, "hipMalloc failed"));
-      s[i]->owned.push_back(l);
+      if (sym_alloc(c, s[i], (size_t)D.n[m], &l) != TP_OK) return cleanup(TP_ENOMEM);
       s[i]->lam[m] = l;
       if (lambda_1d(D.n[m], l, c->stream, power) != hipSuccess) return cleanup(fail(TP_EHIP, "lambda kernel failed"));
     }
@@ -1581,11 +1612,8 @@ tp_status tp_symbol_build(tp_ctx* c, const tp_symbol_desc* desc, tp_symbol** op,
     so->c0 = D.c0;
     so->R = D.d * K + (D.c0 > 0.0 ? 1 : 0);
     // tau and w hold the K terms and a trailing zero exponent (the constant term's factors)
-    if (hipMalloc(&so->tau, sizeof(double) * (K + 1)) != hipSuccess ||
-        hipMalloc(&so->w, sizeof(double) * (K + 1)) != hipSuccess)
-      return cleanup(fail(TP_ENOMEM, "hipMalloc failed"));
-    so->owned.push_back(so->tau);
-    so->owned.push_back(so->w);
+    if (sym_alloc(c, so, (size_t)K + 1, &so->tau) != TP_OK || sym_alloc(c, so, (size_t)K + 1, &so->w) != TP_OK)
+      return cleanup(TP_ENOMEM);
     if (hipMemsetAsync(so->tau, 0, sizeof(double) * (K + 1), c->stream) != hipSuccess)
       return cleanup(fail(TP_EHIP, "memset failed"));
     if (D.method == TP_SYM_FIT) {
@@ -1617,10 +1645,8 @@ tp_status tp_symbol_build(tp_ctx* c, const tp_symbol_desc* desc, tp_symbol** op,
     int K = Kpre;
     sp->K = K;
     sp->R = K;
-    if (hipMalloc(&sp->tau, sizeof(double) * K) != hipSuccess || hipMalloc(&sp->w, sizeof(double) * K) != hipSuccess)
-      return cleanup(fail(TP_ENOMEM, "hipMalloc failed"));
-    sp->owned.push_back(sp->tau);
-    sp->owned.push_back(sp->w);
+    if (sym_alloc(c, sp, (size_t)K, &sp->tau) != TP_OK || sym_alloc(c, sp, (size_t)K, &sp->w) != TP_OK)
+      return cleanup(TP_ENOMEM);
     std::vector<FitCand> cands;
     for (double a : {-2.5, -2.0, -1.5})
       for (double b : {0.5, 1.0, 1.5, 2.0, 2.5}) cands.push_back({a, b});
@@ -1694,8 +1720,7 @@ tp_status tp_state_symbol_build(tp_ctx* c, const tp_symbol_desc* desc, tp_symbol
   for (int m = 0; m < D.d; ++m) {
     s->n[m] = D.n[m];
     double* l = nullptr;
-    if (hipMalloc(&l, sizeof(double) * D.n[m]) != hipSuccess) return cleanup(fail(TP_ENOMEM, "hipMalloc failed"));
-    s->owned.push_back(l);
+    if (sym_alloc(c, s, (size_t)D.n[m], &l) != TP_OK) return cleanup(TP_ENOMEM);
     s->lam[m] = l;
     if (lambda_1d(D.n[m], l, c->stream, power) != hipSuccess) return cleanup(fail(TP_EHIP, "lambda kernel failed"));
     double h = 1.0 / (D.n[m] + 1.0);
@@ -1703,10 +1728,8 @@ tp_status tp_state_symbol_build(tp_ctx* c, const tp_symbol_desc* desc, tp_symbol
     rmax += std::pow(4.0 / (h * h) * std::pow(std::sin(M_PI * D.n[m] * h / 2), 2), power);
   }
   const double rho0 = rmin, B = rmax / rmin * 1.0000001;
-  if (hipMalloc(&s->tau, sizeof(double) * K) != hipSuccess || hipMalloc(&s->w, sizeof(double) * K) != hipSuccess)
-    return cleanup(fail(TP_ENOMEM, "hipMalloc failed"));
-  s->owned.push_back(s->tau);
-  s->owned.push_back(s->w);
+  if (sym_alloc(c, s, (size_t)K, &s->tau) != TP_OK || sym_alloc(c, s, (size_t)K, &s->w) != TP_OK)
+    return cleanup(TP_ENOMEM);
   std::vector<FitCand> cands;
   for (double a : {-1.5, -1.0, -0.5})
     for (double b : {1.75, 2.25, 2.75}) cands.push_back({a, b});
@@ -1729,6 +1752,10 @@ tp_status tp_state_symbol_build(tp_ctx* c, const tp_symbol_desc* desc, tp_symbol
 
 tp_status tp_symbol_free(tp_symbol* s) {
   if (!s) return TP_OK;
+  if (s->arena) {  // workspace memory of a batched worker: released with the worker's workspace
+    delete s;
+    return TP_OK;
+  }
   (void)hipDeviceSynchronize();
   for (void* p : s->owned) (void)hipFree(p);
   delete s;
@@ -2259,20 +2286,28 @@ extern "C" tp_status tp_pcg_solve_batched(tp_ctx* c, int32_t count, const tp_sym
   if (count == 0) return TP_OK;
   HIPCHK(hipStreamSynchronize(c->stream));
   const int nw = std::min<int>(streams, count);
-  std::vector<tp_ctx*> ctxs(nw, nullptr);
-  std::vector<hipStream_t> strm(nw, nullptr);
-  for (int w = 0; w < nw; ++w) {
-    HIPCHK(hipStreamCreateWithFlags(&strm[w], hipStreamNonBlocking));
-    tp_status st = tp_create(c->device, strm[w], workspace_per_stream ? workspace_per_stream : (size_t(2) << 30), &ctxs[w]);
+  const size_t wsz = workspace_per_stream ? workspace_per_stream : (size_t(2) << 30);
+  // worker contexts (stream, workspace, sine tables) are kept in c for later calls with the same
+  // workspace size; more workers are added when a call asks for more streams
+  if (c->worker_ws != wsz) {
+    release_workers(c);
+    c->worker_ws = wsz;
+  }
+  while ((int)c->workers.size() < nw) {
+    hipStream_t sw = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&sw, hipStreamNonBlocking));
+    tp_ctx* cw = nullptr;
+    tp_status st = tp_create(c->device, sw, wsz, &cw);
     if (st != TP_OK) {
-      for (int v = 0; v <= w; ++v) {
-        if (ctxs[v]) tp_destroy(ctxs[v]);
-        if (strm[v]) (void)hipStreamDestroy(strm[v]);
-      }
+      (void)hipStreamDestroy(sw);
       return st;
     }
-    ctxs[w]->prof = false;
+    cw->prof = false;
+    cw->sym_arena = true;
+    c->workers.push_back(cw);
+    c->worker_streams.push_back(sw);
   }
+  const std::vector<tp_ctx*>& ctxs = c->workers;
   std::atomic<int> next(0);
   std::vector<tp_status> wst(nw, TP_OK);
   std::vector<std::string> werr(nw);
@@ -2284,11 +2319,14 @@ extern "C" tp_status tp_pcg_solve_batched(tp_ctx* c, int32_t count, const tp_sym
       if (i >= count) break;
       tp_symbol *op = nullptr, *pre = nullptr;
       double errs[2];
+      const size_t mark = cw->ws_top;  // the symbols go to the workspace below the solve's scopes
       tp_status st = tp_symbol_build(cw, &descs[i], &op, &pre, errs);
       if (st == TP_OK) st = tp_pcg_solve(cw, op, pre, &bs[i], &xs[i], &opts[i], &sks[i], &infos[i]);
       else infos[i].status = st;
       if (op) tp_symbol_free(op);
       if (pre) tp_symbol_free(pre);
+      (void)hipStreamSynchronize(cw->stream);  // the next problem reuses the symbols' workspace
+      cw->ws_top = mark;
       if (st != TP_OK && st != TP_ERANK && st != TP_ENOCONV && wst[w] == TP_OK) {
         wst[w] = st;
         werr[w] = g_err;
@@ -2300,11 +2338,8 @@ extern "C" tp_status tp_pcg_solve_batched(tp_ctx* c, int32_t count, const tp_sym
   for (auto& t : th) t.join();
   tp_status res = TP_OK;
   std::string msg;
-  for (int w = 0; w < nw; ++w) {
+  for (int w = 0; w < nw; ++w)
     if (wst[w] != TP_OK && res == TP_OK) { res = wst[w]; msg = werr[w]; }
-    tp_destroy(ctxs[w]);
-    (void)hipStreamDestroy(strm[w]);
-  }
   if (res != TP_OK) return fail(res, "batched solve: %s", msg.c_str());
   return TP_OK;
 }

@@ -102,3 +102,19 @@ def test_bumps_n16383_mixed_vs_fp64(ctx):
     assert im["status"] in (0, 4) and idd["status"] in (0, 4)
     assert d < MIXED_TOL
     assert idd["err_est"] < 4e-7
+
+
+def test_batched_calls_reuse_their_workers(ctx):
+    """Two batched calls in one context, with 2 and then 4 streams (the workers of the first call
+    are kept and two are added; each worker's symbols live in its workspace and are released after
+    every problem): every result equals the one of the first call."""
+    from paper_1809_01971_amd._tp import batch_solve, sketch_tensors
+    probs = workloads.cfg4()[:6]
+    sks = {n: sketch_tensors(workloads.sketch_matrices(n, 3, 96)) for n in sorted({p.n for p in probs})}
+    outs2, res2 = batch_solve(ctx, probs, _batch, sks, streams=2, workspace_per_stream=2 << 30)
+    outs4, res4 = batch_solve(ctx, probs, _batch, sks, streams=4, workspace_per_stream=2 << 30)
+    for p, a, b, ra, rb in zip(probs, outs2, outs4, res2, res4):
+        rows = [np.arange(0, p.n, 7)] * 3
+        d = rel(ctx.eval_grid(b, rows), ctx.eval_grid(a, rows))
+        log("  %s: %s / %s diff %.1e" % (p.name, ra, rb, d))
+        assert ra["iters"] == rb["iters"] and d < 1e-12
