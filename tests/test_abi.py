@@ -16,7 +16,9 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ["tp_symbol_build", "tp_apply", "tp_truncate", "tp_pcg_solve", "tp_inner", "tp_dst",
-                     "tp_create", "tp_destroy", "tp_eval_grid", "tp_from_cp"]:
+                     "tp_create", "tp_destroy", "tp_eval_grid", "tp_from_cp", "tp_pcg_solve_batched",
+                     "tp_state_symbol_build", "tp_inner_sym", "tp_apply_sum", "tp_symbol_eval",
+                     "tp_workspace_query", "tp_workspace_peak", "tp_profile", "tp_profile_read"]:
         assert required in names
 
 
