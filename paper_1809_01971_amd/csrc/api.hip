@@ -378,6 +378,31 @@ tp_status chol(tp_ctx* c, int cnt, const int* K, const double* const* G, double 
   return TP_OK;
 }
 
+// W[i] = G[i]^(-1/2) (K[i] x K[i]) by Newton-Schulz for Gram matrices near the identity; *all_ok
+// tells whether every one converged (otherwise the caller uses the pivoted Cholesky instead).
+tp_status ns_isqrt(tp_ctx* c, int cnt, const int* K, const double* const* G, double* const* W, bool* all_ok) {
+  if (cnt > kBatchJobs) return fail(TP_EINVAL, "too many Newton-Schulz jobs");
+  int Kmax = 0;
+  for (int i = 0; i < cnt; ++i) Kmax = std::max(Kmax, K[i]);
+  if (Kmax > kNsMax) return fail(TP_EINVAL, "Newton-Schulz limited to %d", kNsMax);
+  int* dok = reinterpret_cast<int*>(c->dmap);
+  JobBatch<NsJob> jb;
+  for (int i = 0; i < cnt; ++i) jb.j[i] = NsJob{K[i], G[i], W[i], dok + i};
+  size_t e0 = 0;
+  TPCHK(prof_begin(c, &e0));
+  HIPCHK(ns_isqrt_batched(jb, cnt, Kmax, c->stream));
+  {
+    double fl = 0, by = 0;  // about three K^3 products per step, three steps
+    for (int i = 0; i < cnt; ++i) { fl += 18.0 * K[i] * K[i] * K[i]; by += 8.0 * 2.0 * K[i] * K[i]; }
+    TPCHK(prof_end(c, PC_CHOL, e0, fl, by));
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  const int* hok = reinterpret_cast<const int*>(c->hmap);
+  *all_ok = true;
+  for (int i = 0; i < cnt; ++i) *all_ok = *all_ok && hok[i] == 1;
+  return TP_OK;
+}
+
 // Eigenpairs of cnt positive semidefinite Gram matrices (pivoted Cholesky + one-sided Jacobi):
 // eigenvectors to V (device), eigenvalues (descending) on the host in host_w, numerical ranks in
 // q, and the trace the Cholesky left unresolved in rest (it belongs to the discarded tail).  The
@@ -490,7 +515,17 @@ tp_status ortho_batch(tp_ctx* c, int cnt, const int* n, const int* K, const doub
     TPCHK(mm<double, double, double, double>(c, true, false, q1[i], q1[i], n[i], 1.0, Q1[i], n[i], Q1[i], n[i], 0.0, G[i], q1[i]));
   }
   int q2[3];
-  TPCHK(chol(c, cnt, q1c, Gc, 1e-14, W, q2));
+  // second pass: Q1^T Q1 = I + E with E of the first pass's loss of orthogonality.  Its inverse
+  // square root by Newton-Schulz (products of small matrices, no sequential pivot steps) gives an
+  // orthonormal basis of the same span; the pivoted Cholesky is the fallback when E is not small.
+  bool ns = true;
+  for (int i = 0; i < cnt; ++i) ns = ns && q1c[i] <= kNsMax;
+  if (ns) TPCHK(ns_isqrt(c, cnt, q1c, Gc, W, &ns));
+  if (ns) {
+    for (int i = 0; i < cnt; ++i) q2[i] = q1c[i];
+  } else {
+    TPCHK(chol(c, cnt, q1c, Gc, 1e-14, W, q2));
+  }
   for (int i = 0; i < cnt; ++i) {
     if (q1[i] == 0 || q2[i] == 0) continue;
     TPCHK(wsalloc(c, (size_t)n[i] * q2[i], &Qout[i]));

@@ -1081,6 +1081,132 @@ hipError_t pchol_batched(const JobBatch<CholJob>& jobs_dev, int count, int Kmax,
 }
 
 // ---------------------------------------------------------------------------------------------
+// Inverse square root of Gram matrices near the identity (the second pass of an orthonormalisation,
+// whose Gram is I + E with E of the order of the first pass's loss of orthogonality) by the coupled
+// Newton-Schulz iteration (Higham, Functions of Matrices, Sec. 6.3): Y0 = G, Z0 = I,
+// T = (3 I - Z Y) / 2, Y <- Y T, Z <- T Z, which converges quadratically to Y = G^(1/2),
+// Z = G^(-1/2) when ||I - G||_2 < 1.  One workgroup per matrix, Y, Z, T in LDS (K <= kNsMax).
+// ok = 0 (W untouched) when ||G - I||_F > 1/2 or the iteration has not converged in 10 steps.
+// ---------------------------------------------------------------------------------------------
+__device__ double block_max256(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  return fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+// out[r, c] for the (up to) 4 x 4 block of thread (ti, tj): sum_k A[r + K k] B[k + K c]
+__device__ __forceinline__ void ns_mm(const double* A, const double* B, int K, int ti, int tj, double o[4][4]) {
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) o[a][b] = 0.0;
+  for (int k = 0; k < K; ++k) {
+    double av[4], bv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int r = ti + 16 * a;
+      av[a] = r < K ? A[r + K * k] : 0.0;
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int cc = tj + 16 * b;
+      bv[b] = cc < K ? B[k + K * cc] : 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) o[a][b] = fma(av[a], bv[b], o[a][b]);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_ns_isqrt(JobBatch<NsJob> jobs) {
+  extern __shared__ double sm[];
+  __shared__ double red[4];
+  const NsJob J = jobs.j[blockIdx.x];
+  const int K = J.K, KK = K * K, tid = threadIdx.x;
+  const int ti = tid & 15, tj = tid >> 4;  // rows ti + 16 a, columns tj + 16 b
+  double* Y = sm;
+  double* Z = sm + KK;
+  double* T = sm + 2 * KK;
+  if (K <= 0) {
+    if (tid == 0) *J.ok = 1;
+    return;
+  }
+  double e2 = 0.0;
+  for (int e = tid; e < KK; e += 256) {
+    const int i = e % K, j = e / K;
+    const double g = J.g[e], d = g - (i == j ? 1.0 : 0.0);
+    Y[e] = g;
+    Z[e] = i == j ? 1.0 : 0.0;
+    e2 += d * d;
+  }
+  // ||G - I||_F^2 as a block sum (the max of non-negative per-wave sums would not do: sum them)
+  for (int o = 32; o > 0; o >>= 1) e2 += __shfl_xor(e2, o);
+  __syncthreads();
+  if ((tid & 63) == 0) red[tid >> 6] = e2;
+  __syncthreads();
+  const double fro2 = red[0] + red[1] + red[2] + red[3];
+  if (!(fro2 <= 0.25)) {  // uniform
+    if (tid == 0) *J.ok = 0;
+    return;
+  }
+  bool done = false;
+  for (int it = 0; it < 10 && !done; ++it) {
+    double o[4][4];
+    ns_mm(Z, Y, K, ti, tj, o);  // T = 1.5 I - 0.5 Z Y
+    double dev = 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int r = ti + 16 * a, cc = tj + 16 * b;
+        if (r < K && cc < K) {
+          const double t = (r == cc ? 1.5 : 0.0) - 0.5 * o[a][b];
+          T[r + K * cc] = t;
+          dev = fmax(dev, fabs(t - (r == cc ? 1.0 : 0.0)));
+        }
+      }
+    dev = block_max256(dev, red);  // includes the barrier that publishes T
+    double y[4][4], z[4][4];
+    ns_mm(Y, T, K, ti, tj, y);
+    ns_mm(T, Z, K, ti, tj, z);
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int r = ti + 16 * a, cc = tj + 16 * b;
+        if (r < K && cc < K) {
+          Y[r + K * cc] = y[a][b];
+          Z[r + K * cc] = z[a][b];
+        }
+      }
+    __syncthreads();
+    // T - I is of the order of the remaining error and the step squares it: from 1e-10 this step
+    // has brought Z to G^(-1/2) to working precision (the products' rounding, ~K eps, is larger
+    // than what a further step would remove)
+    done = dev <= 1e-10;
+  }
+  for (int e = tid; e < KK; e += 256) J.w[e] = Z[e];
+  if (tid == 0) *J.ok = done ? 1 : 0;
+}
+
+hipError_t ns_isqrt_batched(const JobBatch<NsJob>& jobs, int count, int Kmax, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (count > kBatchJobs || Kmax > kNsMax) return hipErrorInvalidValue;
+  const size_t shm = (size_t)3 * Kmax * Kmax * sizeof(double);
+  if (shm > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_ns_isqrt, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_ns_isqrt, dim3(count), dim3(256), shm, s, jobs);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
 // Eigenpairs of a positive semidefinite Gram matrix G (K x K) by the preconditioned one-sided
 // Jacobi method: pivoted Cholesky G[P,P] = R^T R, then Jacobi rotations orthogonalise the
 // columns of X = R^T (K x q).  At convergence X = V Sigma with V the eigenvectors of G[P,P]

@@ -69,6 +69,13 @@ hipError_t syev_batched(const JobBatch<EigJob>& jobs, int count, int Kmax, hipSt
 struct CholJob { int K; double tol; const double* g; double* w; int* q; double* work; };
 hipError_t pchol_batched(const JobBatch<CholJob>& jobs, int count, int Kmax, hipStream_t s);
 
+// Batched inverse square root W = G^(-1/2) (K x K, ld K) of Gram matrices near the identity by
+// the coupled Newton-Schulz iteration, K <= kNsMax; *ok = 0 (W untouched) when ||G - I||_F > 1/2
+// or it has not converged.
+constexpr int kNsMax = 64;
+struct NsJob { int K; const double* g; double* w; int* ok; };
+hipError_t ns_isqrt_batched(const JobBatch<NsJob>& jobs, int count, int Kmax, hipStream_t s);
+
 // Batched eigendecomposition of positive semidefinite Gram matrices (pivoted Cholesky, then
 // one-sided Jacobi on R^T).  Per job: eigenvalues descending to w (K entries, zero past the
 // numerical rank q), eigenvectors to v (K x K, ld K, zero columns past q), q to *q and the
