@@ -7,8 +7,8 @@ an input.  All draws use numpy's PCG64 generator; factor vectors are drawn term
 by term and, inside a term, mode by mode.
 
 The paper's own design functions exist only as figures (Sec. 6), so every
-workload here is synthetic with the sizes and parameters of the configurations
-named in DESIGN.md.
+workload here is synthetic, with the sizes and parameters of the configurations
+below.
 """
 from dataclasses import dataclass, field
 
