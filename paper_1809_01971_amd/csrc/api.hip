@@ -1384,74 +1384,120 @@ tp_status pre_lattice_error(tp_ctx* c, const tp_symbol* s, const SymFn& fn, doub
   return TP_OK;
 }
 
-// Least-squares exponential sum for f (kind 0: g, 1: 1/s, 2: the state symbol) over candidates;
-// keeps the best.
-tp_status fit_expsum(tp_ctx* c, int kind, const SymFn& f, double rho0, double B, int K,
-                     const std::vector<FitCand>& cands, double* tau_out, double* w_out, double* err_out) {
+// Least-squares exponential sums for several functions f (kind 0: g, 1: 1/s, 2: the state
+// symbol), each over its candidate exponent grids; keeps each fit's best candidate.  The design
+// matrices, scalings, solves and error evaluations run per fit; the eigensolves of all candidates
+// go to one launch of the Gram eigensolver when they fit in one batch, and one synchronisation
+// reads every fit error.
+struct FitSpec {
+  int kind;
+  SymFn f;
+  double rho0, B;
+  int K;
+  std::vector<FitCand> cands;
+  double* tau_out;
+  double* w_out;
+  double err;
+};
+
+tp_status fit_expsum_multi(tp_ctx* c, std::vector<FitSpec>& fits) {
   WsScope scope(c);
-  const int m = 1000, nc = (int)cands.size();
-  double *A, *t, *G, *bvec, *ew, *E, *cn_, *err, *wsol, *ones;
-  FitCand* cd;
-  TPCHK(wsalloc(c, (size_t)nc * m * K, &A));
-  TPCHK(wsalloc(c, (size_t)nc * K, &t));
-  TPCHK(wsalloc(c, (size_t)nc * K * K, &G));
-  TPCHK(wsalloc(c, (size_t)nc * K, &bvec));
-  TPCHK(wsalloc(c, (size_t)nc * K, &ew));
-  TPCHK(wsalloc(c, (size_t)nc * K * K, &E));
-  TPCHK(wsalloc(c, (size_t)nc * K, &cn_));
-  TPCHK(wsalloc(c, (size_t)nc, &err));
-  TPCHK(wsalloc(c, (size_t)nc * K, &wsol));
-  // the candidates travel through the mapped host scratch (read once by the design kernel)
-  // (every user of the mapped scratch synchronises the stream before returning, so it is free)
-  if (nc * sizeof(FitCand) > tp_ctx::kMap / 4 * sizeof(double)) return fail(TP_EINVAL, "too many fit candidates");
+  const int m = 1000, nf = (int)fits.size();
+  struct Buf { double *A, *t, *G, *bvec, *ew, *E, *cn, *wsol; int nc, off; };
+  std::vector<Buf> bf(nf);
+  int tot = 0;
+  for (int i = 0; i < nf; ++i) {
+    const int K = fits[i].K, nc = (int)fits[i].cands.size();
+    Buf& b = bf[i];
+    b.nc = nc;
+    b.off = tot;
+    tot += nc;
+    TPCHK(wsalloc(c, (size_t)nc * m * K, &b.A));
+    TPCHK(wsalloc(c, (size_t)nc * K, &b.t));
+    TPCHK(wsalloc(c, (size_t)nc * K * K, &b.G));
+    TPCHK(wsalloc(c, (size_t)nc * K, &b.bvec));
+    TPCHK(wsalloc(c, (size_t)nc * K, &b.ew));
+    TPCHK(wsalloc(c, (size_t)nc * K * K, &b.E));
+    TPCHK(wsalloc(c, (size_t)nc * K, &b.cn));
+    TPCHK(wsalloc(c, (size_t)nc * K, &b.wsol));
+  }
+  // the candidates travel through the mapped host scratch (read once by the design kernels;
+  // every user of the mapped scratch synchronises the stream before returning, so it is free)
+  if (tot * sizeof(FitCand) > tp_ctx::kMap / 4 * sizeof(double)) return fail(TP_EINVAL, "too many fit candidates");
   FitCand* hc = reinterpret_cast<FitCand*>(c->hmap + tp_ctx::kMap / 4);
-  for (int ci = 0; ci < nc; ++ci) hc[ci] = cands[ci];
-  cd = reinterpret_cast<FitCand*>(c->dmap + tp_ctx::kMap / 4);
-  HIPCHK(fit_design(kind, f, rho0, B, K, m, cd, nc, A, t, c->stream));
-  // column scaling: cn_ = 1/||A_k|| from the Gram diagonal; scaled Gram = D G D
-  GemmArgs<double, double, double, double> g;
-  g.M = K; g.N = K; g.K = m; g.batch = nc;
-  g.A = A; g.lda = m; g.tA = true; g.sA = (long)m * K;
-  g.B = A; g.ldb = m; g.sB = (long)m * K;
-  g.C = G; g.ldc = K; g.sC = (long)K * K;
-  TPCHK(run(c, g));
+  FitCand* dc = reinterpret_cast<FitCand*>(c->dmap + tp_ctx::kMap / 4);
+  const double* ones = nullptr;
   {
     const double* w1 = nullptr;
-    const double* o = nullptr;
-    TPCHK(unit_symbol<double>(c, m, &o, &w1));
-    ones = const_cast<double*>(o);
+    TPCHK(unit_symbol<double>(c, m, &ones, &w1));
   }
-  GemmArgs<double, double, double, double> gb;
-  gb.M = K; gb.N = 1; gb.K = m; gb.batch = nc;
-  gb.A = A; gb.lda = m; gb.tA = true; gb.sA = (long)m * K;
-  gb.B = ones; gb.ldb = m; gb.sB = 0;
-  gb.C = bvec; gb.ldc = K; gb.sC = K;
-  TPCHK(run(c, gb));
-  HIPCHK(fit_scale(K, nc, G, bvec, cn_, c->stream));
-  std::vector<int> Ks(nc, K);
-  std::vector<const double*> Ap(nc);
-  std::vector<double*> Wp(nc), Vp(nc);
-  for (int ci = 0; ci < nc; ++ci) {
-    Ap[ci] = G + (size_t)ci * K * K;
-    Wp[ci] = ew + (size_t)ci * K;
-    Vp[ci] = E + (size_t)ci * K * K;
+  std::vector<int> Ks;
+  std::vector<const double*> Ap;
+  std::vector<double*> Wp, Vp;
+  for (int i = 0; i < nf; ++i) {
+    const FitSpec& F = fits[i];
+    const Buf& b = bf[i];
+    const int K = F.K, nc = b.nc;
+    for (int ci = 0; ci < nc; ++ci) hc[b.off + ci] = F.cands[ci];
+    HIPCHK(fit_design(F.kind, F.f, F.rho0, F.B, K, m, dc + b.off, nc, b.A, b.t, c->stream));
+    // column scaling: cn = 1/||A_k|| from the Gram diagonal; scaled Gram = D G D
+    GemmArgs<double, double, double, double> g;
+    g.M = K; g.N = K; g.K = m; g.batch = nc;
+    g.A = b.A; g.lda = m; g.tA = true; g.sA = (long)m * K;
+    g.B = b.A; g.ldb = m; g.sB = (long)m * K;
+    g.C = b.G; g.ldc = K; g.sC = (long)K * K;
+    TPCHK(run(c, g));
+    GemmArgs<double, double, double, double> gb;
+    gb.M = K; gb.N = 1; gb.K = m; gb.batch = nc;
+    gb.A = b.A; gb.lda = m; gb.tA = true; gb.sA = (long)m * K;
+    gb.B = ones; gb.ldb = m; gb.sB = 0;
+    gb.C = b.bvec; gb.ldc = K; gb.sC = K;
+    TPCHK(run(c, gb));
+    HIPCHK(fit_scale(K, nc, b.G, b.bvec, b.cn, c->stream));
+    for (int ci = 0; ci < nc; ++ci) {
+      Ks.push_back(K);
+      Ap.push_back(b.G + (size_t)ci * K * K);
+      Wp.push_back(b.ew + (size_t)ci * K);
+      Vp.push_back(b.E + (size_t)ci * K * K);
+    }
   }
   // the scaled normal matrices are positive semidefinite Gram matrices: the Gram eigensolver
   // (eigenvalues to 1e-14 of themselves, ranks below 1e-16 of the largest pivot dropped)
-  TPCHK(psd_eig_dev(c, nc, Ks.data(), Ap.data(), Wp.data(), Vp.data(), 1e-14));
-  HIPCHK(fit_solve(K, nc, ew, E, bvec, cn_, 1e-15, wsol, c->stream));
-  (void)err;
-  double* derr = c->dmap;  // errors straight to the mapped host scratch
-  HIPCHK(fit_error(kind, f, rho0, B, K, t, wsol, nc, 4096, derr, c->stream));
+  if (tot <= kBatchJobs) {
+    TPCHK(psd_eig_dev(c, tot, Ks.data(), Ap.data(), Wp.data(), Vp.data(), 1e-14));
+  } else {
+    for (int i = 0; i < nf; ++i)
+      TPCHK(psd_eig_dev(c, bf[i].nc, Ks.data() + bf[i].off, Ap.data() + bf[i].off, Wp.data() + bf[i].off,
+                        Vp.data() + bf[i].off, 1e-14));
+  }
+  for (int i = 0; i < nf; ++i) {
+    const FitSpec& F = fits[i];
+    const Buf& b = bf[i];
+    HIPCHK(fit_solve(F.K, b.nc, b.ew, b.E, b.bvec, b.cn, 1e-15, b.wsol, c->stream));
+    // errors straight to the mapped host scratch
+    HIPCHK(fit_error(F.kind, F.f, F.rho0, F.B, F.K, b.t, b.wsol, b.nc, 4096, c->dmap + b.off, c->stream));
+  }
   HIPCHK(hipStreamSynchronize(c->stream));
   const double* herr = c->hmap;
-  int best = 0;
-  for (int ci = 1; ci < nc; ++ci)
-    if (herr[ci] < herr[best] || std::isnan(herr[best])) best = ci;
-  *err_out = herr[best];
-  // copies on the compute stream (the workspace they read is released in stream order)
-  HIPCHK((convert<double, double>(t + (size_t)best * K, tau_out, K, c->stream)));
-  HIPCHK((convert<double, double>(wsol + (size_t)best * K, w_out, K, c->stream)));
+  for (int i = 0; i < nf; ++i) {
+    FitSpec& F = fits[i];
+    const Buf& b = bf[i];
+    int best = 0;
+    for (int ci = 1; ci < b.nc; ++ci)
+      if (herr[b.off + ci] < herr[b.off + best] || std::isnan(herr[b.off + best])) best = ci;
+    F.err = herr[b.off + best];
+    // copies on the compute stream (the workspace they read is released in stream order)
+    HIPCHK((convert<double, double>(b.t + (size_t)best * F.K, F.tau_out, F.K, c->stream)));
+    HIPCHK((convert<double, double>(b.wsol + (size_t)best * F.K, F.w_out, F.K, c->stream)));
+  }
+  return TP_OK;
+}
+
+tp_status fit_expsum(tp_ctx* c, int kind, const SymFn& f, double rho0, double B, int K,
+                     const std::vector<FitCand>& cands, double* tau_out, double* w_out, double* err_out) {
+  std::vector<FitSpec> fits(1, FitSpec{kind, f, rho0, B, K, cands, tau_out, w_out, 0.0});
+  TPCHK(fit_expsum_multi(c, fits));
+  *err_out = fits[0].err;
   return TP_OK;
 }
 
@@ -1638,6 +1684,8 @@ tp_status tp_symbol_build(tp_ctx* c, const tp_symbol_desc* desc, tp_symbol** op,
   double rmin = 0, rmax = 0;
   for (int m = 0; m < D.d; ++m) { rmin += lam1[m]; rmax += lamn[m]; }
   const double rho0 = rmin, B = rmax / rmin * 1.0000001;
+  std::vector<FitSpec> fits;  // the operator's fit (if any) and the preconditioner's, run together below
+  int op_fit = -1;
   // operator
   {
     tp_symbol* so = s[0];
@@ -1652,22 +1700,19 @@ tp_status tp_symbol_build(tp_ctx* c, const tp_symbol_desc* desc, tp_symbol** op,
     if (hipMemsetAsync(so->tau, 0, sizeof(double) * (K + 1), c->stream) != hipSuccess)
       return cleanup(fail(TP_EHIP, "memset failed"));
     if (D.method == TP_SYM_FIT) {
-      double e = 0;
       if (Kfit > 0) {
         std::vector<FitCand> cands;
         for (double a : {-1.5, -1.0, -0.5})
           for (double b : {1.75, 2.25, 2.75}) cands.push_back({a, b});
-        tp_status st = fit_expsum(c, 0, fn, rho0, B, Kfit, cands, so->tau, so->w, &e);
-        if (st != TP_OK) return cleanup(st);
-        // the fit is in the scaled variable y = rho/rho0: tau = t/rho0
-        if (scale(so->tau, Kfit, 1.0 / rho0, c->stream) != hipSuccess) return cleanup(fail(TP_EHIP, "scale failed"));
+        fits.push_back(FitSpec{0, fn, rho0, B, Kfit, cands, so->tau, so->w, 0.0});
+        op_fit = 0;
       }
       if (exact_pos) {
         so->wexact = D.c_pos;
         if (hipMemcpyAsync(so->w + Kfit, &so->wexact, sizeof(double), hipMemcpyHostToDevice, c->stream) != hipSuccess)
           return cleanup(fail(TP_EHIP, "copy failed"));
       }
-      so->err = e;
+      so->err = 0.0;
     } else {
       if (sinc_g_nodes(alpha, D.c_neg, D.c_pos, rho0, kl, kr, hh, so->tau, so->w, c->stream) != hipSuccess)
         return cleanup(fail(TP_EHIP, "sinc kernel failed"));
@@ -1685,11 +1730,20 @@ tp_status tp_symbol_build(tp_ctx* c, const tp_symbol_desc* desc, tp_symbol** op,
     std::vector<FitCand> cands;
     for (double a : {-2.5, -2.0, -1.5})
       for (double b : {0.5, 1.0, 1.5, 2.0, 2.5}) cands.push_back({a, b});
-    double e = 0;
-    tp_status st = fit_expsum(c, 1, fn, rho0, B, K, cands, sp->tau, sp->w, &e);
+    fits.push_back(FitSpec{1, fn, rho0, B, K, cands, sp->tau, sp->w, 0.0});
+  }
+  // both least-squares fits at once (one launch of the eigensolver for all their candidates); the
+  // fits are in the scaled variable y = rho/rho0: tau = t/rho0
+  {
+    tp_status st = fit_expsum_multi(c, fits);
     if (st != TP_OK) return cleanup(st);
-    if (scale(sp->tau, K, 1.0 / rho0, c->stream) != hipSuccess) return cleanup(fail(TP_EHIP, "scale failed"));
-    sp->err = e;
+    if (op_fit >= 0) {
+      if (scale(s[0]->tau, fits[op_fit].K, 1.0 / rho0, c->stream) != hipSuccess) return cleanup(fail(TP_EHIP, "scale failed"));
+      s[0]->err = fits[op_fit].err;
+    }
+    FitSpec& fp = fits.back();
+    if (scale(s[1]->tau, fp.K, 1.0 / rho0, c->stream) != hipSuccess) return cleanup(fail(TP_EHIP, "scale failed"));
+    s[1]->err = fp.err;
   }
   // measured error of the operator sum (also for the sinc rule): rho*g vs s on log samples
   for (int i = 0; i < 2; ++i) {

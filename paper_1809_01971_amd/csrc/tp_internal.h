@@ -52,8 +52,8 @@ hipError_t dst_table(int N, T* tab, hipStream_t s);
 constexpr int kGramLds = 128;
 
 // Job descriptors of the batched one-workgroup-per-matrix kernels travel by value in the kernel
-// arguments (no staging copy): at most kBatchJobs per launch.
-constexpr int kBatchJobs = 16;
+// arguments (no staging copy): at most kBatchJobs per launch (24 descriptors of at most 72 bytes).
+constexpr int kBatchJobs = 24;
 template <typename J>
 struct JobBatch { J j[kBatchJobs]; };
 
