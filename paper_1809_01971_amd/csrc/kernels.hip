@@ -1233,8 +1233,8 @@ __global__ __launch_bounds__(NT) void k_psd_eig(JobBatch<PsdJob> jobs) {
   int* perm = reinterpret_cast<int*>(slot + 2 * NW);   // K
   int* rank = perm + K;                                // K: output position of each column
   __shared__ CholShared sh;
-  // per sweep: the largest relative off-diagonal |x_p.x_r| / (|x_p| |x_r|) that was rotated
-  // away, as float bits (non-negative floats order like their bit patterns)
+  // per sweep: the largest squared relative off-diagonal (x_p.x_r)^2 / (|x_p|^2 |x_r|^2) that
+  // was rotated away, as float bits (non-negative floats order like their bit patterns)
   __shared__ unsigned int offmax[3];
   if (tid == 0) offmax[0] = offmax[1] = offmax[2] = 0u;
   const int q = chol_phase<NT>(J.g, K, J.ctol, S, dk, perm, slot, rank, sh);
@@ -1274,6 +1274,13 @@ __global__ __launch_bounds__(NT) void k_psd_eig(JobBatch<PsdJob> jobs) {
   // NT / (KMAX / 2) (or 1)
   constexpr int LMIN = (2 * NT) / KMAX > 0 ? (2 * NT) / KMAX : 1;
   constexpr int RMAX = SMEM ? (KMAX + LMIN - 1) / LMIN : 1;
+  static_assert((RMAX & (RMAX - 1)) == 0, "row blocks per lane: a power of two");
+  // The columns lie K doubles apart, a multiple of the LDS bank period when K is a multiple of
+  // 16, so pairs that read the same rows of their columns hit the same banks.  Each pair walks
+  // its row blocks from a different start (pr mod RMAX): the pairs of a wave then touch disjoint
+  // row blocks at every load and store.  A lane still covers the rows li + L t, t < RMAX.
+  const int rot = pr & (RMAX - 1);
+  const double jtol2 = J.jtol * J.jtol;
   for (int sweep = 0; sweep < 40 && q > 1; ++sweep) {
     unsigned int* chg = &offmax[sweep % 3];
     if (tid == 0) offmax[(sweep + 1) % 3] = 0u;  // last read two sweeps ago
@@ -1291,7 +1298,7 @@ __global__ __launch_bounds__(NT) void k_psd_eig(JobBatch<PsdJob> jobs) {
       if (SMEM) {
 #pragma unroll
         for (int t = 0; t < RMAX; ++t) {
-          const int i = li + L * t;
+          const int i = li + L * ((t + rot) & (RMAX - 1));
           const bool in = valid && i < K;
           xa[t] = in ? X[i + K * p] : 0.0;
           xb[t] = in ? X[i + K * r] : 0.0;
@@ -1307,15 +1314,16 @@ __global__ __launch_bounds__(NT) void k_psd_eig(JobBatch<PsdJob> jobs) {
       al = group_sum(al, L);
       be = group_sum(be, L);
       ga = group_sum(ga, L);
-      const double relo = (valid && ga != 0.0) ? fabs(ga) / sqrt(al * be) : 0.0;
-      if (relo > J.jtol) {
+      // rotate while |ga| / sqrt(al be) > jtol, tested on the squares (no square root)
+      const double ab = al * be;
+      if (valid && ga * ga > jtol2 * ab) {
         const double zeta = (be - al) / (2.0 * ga);
         const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+        const double c = rsqrt(1.0 + t * t), sn = c * t;
         if (SMEM) {
 #pragma unroll
           for (int u = 0; u < RMAX; ++u) {
-            const int i = li + L * u;
+            const int i = li + L * ((u + rot) & (RMAX - 1));
             if (i < K) {
               X[i + K * p] = c * xa[u] - sn * xb[u];
               X[i + K * r] = sn * xa[u] + c * xb[u];
@@ -1328,15 +1336,16 @@ __global__ __launch_bounds__(NT) void k_psd_eig(JobBatch<PsdJob> jobs) {
             X[i + K * r] = sn * a + c * b;
           }
         }
-        if (li == 0) atomicMax(chg, __float_as_uint((float)relo));
+        // the squared relative off-diagonal that was rotated away
+        if (li == 0) atomicMax(chg, __float_as_uint((float)((ga * ga) / ab)));
       }
       __syncthreads();
     }
     // read by every thread after the sweep's last barrier.  Stop when nothing was rotated, or
     // when every rotation was so small that the sweep's quadratic convergence leaves the
     // columns orthogonal to jtol: off-diagonals after a sweep are O(K max^2).
-    const float mx = __uint_as_float(*chg);
-    if (mx == 0.0f || (double)mx * (double)mx * (double)q <= J.jtol) break;
+    const float mx2 = __uint_as_float(*chg);
+    if (mx2 == 0.0f || (double)mx2 * (double)q <= J.jtol) break;
   }
   __syncthreads();
   // eigenvalues = squared column norms (16 lanes per column), sorted descending;

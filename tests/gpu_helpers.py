@@ -19,9 +19,12 @@ def log(*args):
 
 
 def _err_part(args):
+    from threadpoolctl import threadpool_limits
     from oracle import exact
     (w, F, alpha, cn, cp, core, T, slabs) = args
-    return exact.tucker_error_slabs(w, F, alpha, cn, cp, core, T, slabs)
+    # one BLAS thread per worker: the pool already spreads the slabs over the cores
+    with threadpool_limits(limits=1):
+        return exact.tucker_error_slabs(w, F, alpha, cn, cp, core, T, slabs)
 
 
 def global_rel_error(p, core, tfactors, workers=None, stride=1):

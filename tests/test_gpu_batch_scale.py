@@ -43,6 +43,7 @@ def _single(ctx, p, s, sk):
     return X, info
 
 
+@pytest.mark.timeout(300)  # the exact check of twelve whole grids is CPU work
 def test_batched_sample_against_oracle(ctx):
     """The first 12 problems of the batch (n in {127, 255, 511, 1023}, alpha in [0.1, 0.9], gamma in
     [1e-4, 1e-1], rank 1-12), solved together on 4 streams with tolerance 1e-5 and a rank cap large
