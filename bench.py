@@ -37,8 +37,8 @@ ERR_SLAB_STRIDE = 4  # exact error over every 4th first-index spectral slab (unb
 # follows) from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, each scaled by the reading of a 256 MiB
 # device copy; valid only for the sources and mixed settings they were taken with, identified by
 # traffic_key() (SHA-256 prefix of csrc/kernels.hip, csrc/api.hip and the settings' JSON).
-TRAFFIC = {"src": "96f2f100db1e9250", "bytes_per_launch": {"gemm_f32": 20185306, "gram_eig": 232235, "gemm_f64": 7725218,
-                                               "gemm_f32_f64": 13669300, "gemm_f64_f32": 1507644}}
+TRAFFIC = {"src": "2fc8830fe3532c90", "bytes_per_launch": {"gemm_f32": 20182540, "gram_eig": 233131, "gemm_f64": 7727381,
+                                               "gemm_f32_f64": 13674500, "gemm_f64_f32": 1515729}}
 
 
 def traffic_key():

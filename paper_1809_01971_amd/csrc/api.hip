@@ -234,6 +234,39 @@ tp_status dst_cols(tp_ctx* c, int n, int cols, const T* in, T* out) {
   return TP_OK;
 }
 
+// Several transforms at once: jobs of one length share a launch (up to kDstJobs per launch), as
+// the modes of the tensors in a product do; mixed lengths and n + 1 > 16384 take one launch each.
+template <typename T>
+tp_status dst_cols_batch(tp_ctx* c, int cnt, const int* n, const int* cols, const T* const* in, T* const* out) {
+  bool same = cnt > 0 && n[0] + 1 <= 16384;
+  for (int i = 1; i < cnt; ++i) same = same && n[i] == n[0];
+  if (!same) {
+    for (int i = 0; i < cnt; ++i) TPCHK(dst_cols<T>(c, n[i], cols[i], in[i], out[i]));
+    return TP_OK;
+  }
+  const T* tab = nullptr;
+  TPCHK(get_table<T>(c, n[0] + 1, &tab));
+  const double* tab64 = nullptr;
+  TPCHK(get_table<double>(c, n[0] + 1, &tab64));
+  const double lg = std::log2(2.0 * (n[0] + 1));
+  for (int i0 = 0; i0 < cnt; i0 += kDstJobs) {
+    const int k = std::min(kDstJobs, cnt - i0);
+    DstJob<T> jobs[kDstJobs];
+    long tc = 0;
+    for (int i = 0; i < k; ++i) {
+      jobs[i] = DstJob<T>{in[i0 + i], out[i0 + i], cols[i0 + i], n[0], n[0], 0};
+      tc += std::max(0, cols[i0 + i]);
+    }
+    if (tc == 0) continue;
+    size_t e0 = 0;
+    TPCHK(prof_begin(c, &e0));
+    HIPCHK(dst1_batched<T>(n[0] + 1, jobs, k, tab, tab64, c->stream));
+    TPCHK(prof_end(c, std::is_same<T, double>::value ? PC_DST_F64 : PC_DST_F32, e0, 2.5 * (n[0] + 1) * lg * tc,
+                   2.0 * n[0] * tc * sizeof(T)));
+  }
+  return TP_OK;
+}
+
 tp_status sync_to_host(tp_ctx* c, const void* dev, size_t bytes, void* host) {
   if (bytes == 0) return TP_OK;
   HIPCHK(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, c->stream));
@@ -847,18 +880,30 @@ tp_status combo_impl(tp_ctx* c, const Term* terms, int nt, tp_tensor* y, double 
       Om[m] = o;
     }
   }
+  // the factors of every term in sine coordinates (one launch for all of them)
+  {
+    std::vector<int> jn, jc;
+    std::vector<const T*> ji;
+    std::vector<T*> jo;
+    for (int t = 0; t < nterm; ++t) {
+      Prep& P = pr[t];
+      const tp_tensor* x = tv[t].x;
+      for (int m = 0; m < 3; ++m) P.r[m] = m < d ? x->rank[m] : 1;
+      for (int m = 0; m < d; ++m) {
+        if (c->spectral) {
+          P.Vh[m] = (T*)x->factor[m];  // read only; a y aliasing x is written after the last read
+          continue;
+        }
+        TPCHK(wsalloc(c, (size_t)x->n[m] * P.r[m], &P.Vh[m]));
+        jn.push_back(x->n[m]); jc.push_back(P.r[m]);
+        ji.push_back((const T*)x->factor[m]); jo.push_back(P.Vh[m]);
+      }
+    }
+    TPCHK(dst_cols_batch<T>(c, (int)jn.size(), jn.data(), jc.data(), ji.data(), jo.data()));
+  }
   for (int t = 0; t < nterm; ++t) {
     Prep& P = pr[t];
     const tp_tensor* x = tv[t].x;
-    for (int m = 0; m < 3; ++m) P.r[m] = m < d ? x->rank[m] : 1;
-    for (int m = 0; m < d; ++m) {
-      if (c->spectral) {
-        P.Vh[m] = (T*)x->factor[m];  // read only; a y aliasing x is written after the last read
-        continue;
-      }
-      TPCHK(wsalloc(c, (size_t)x->n[m] * P.r[m], &P.Vh[m]));
-      TPCHK(dst_cols<T>(c, x->n[m], P.r[m], (const T*)x->factor[m], P.Vh[m]));
-    }
     size_t csz = (size_t)P.r[0] * P.r[1] * P.r[2];
     TPCHK(wsalloc(c, csz, &P.C));
     HIPCHK((convert<T, T>((const T*)x->core, P.C, (long)csz, c->stream)));
@@ -1006,21 +1051,27 @@ tp_status combo_impl(tp_ctx* c, const Term* terms, int nt, tp_tensor* y, double 
   int rn[3] = {1, 1, 1};
   double* U[3];
   TPCHK((hosvd<T, T>(c, d, q, M, tol, cap, rn, U, (T*)y->core, capped)));
+  WsScope s4(c);
+  T* W[3] = {nullptr, nullptr, nullptr};
+  int yn[3];
+  T* yf[3];
   for (int m = 0; m < d; ++m) {
     int n = y->n[m];
-    WsScope s4(c);
+    yn[m] = n;
+    yf[m] = (T*)y->factor[m];
     if (c->spectral) {
       TPCHK((mm<double, double, T, double>(c, false, false, n, rn[m], q[m], 1.0, Qb[m], n, U[m], q[m], 0.0,
                                           (T*)y->factor[m], n)));
-      y->rank[m] = rn[m];
       continue;
     }
-    T* W;
-    TPCHK(wsalloc(c, (size_t)n * rn[m], &W));
-    TPCHK((mm<double, double, T, double>(c, false, false, n, rn[m], q[m], 1.0, Qb[m], n, U[m], q[m], 0.0, W, n)));
-    TPCHK(dst_cols<T>(c, n, rn[m], W, (T*)y->factor[m]));
-    y->rank[m] = rn[m];
+    TPCHK(wsalloc(c, (size_t)n * rn[m], &W[m]));
+    TPCHK((mm<double, double, T, double>(c, false, false, n, rn[m], q[m], 1.0, Qb[m], n, U[m], q[m], 0.0, W[m], n)));
   }
+  if (!c->spectral) {
+    const T* Wc[3] = {W[0], W[1], W[2]};
+    TPCHK(dst_cols_batch<T>(c, d, yn, rn, Wc, yf));
+  }
+  for (int m = 0; m < d; ++m) y->rank[m] = rn[m];
   return TP_OK;
 }
 
@@ -1041,19 +1092,29 @@ tp_status inner_sym_impl(tp_ctx* c, const tp_tensor* x, const tp_symbol* S, cons
   int rx[3] = {1, 1, 1}, ry[3] = {1, 1, 1};
   T *Vx[3], *Vy[3];
   double* G[3];
-  for (int m = 0; m < d; ++m) {
-    int n = x->n[m];
-    rx[m] = x->rank[m];
-    ry[m] = y->rank[m];
-    if (c->spectral) {
-      Vx[m] = (T*)x->factor[m];
-      Vy[m] = (T*)y->factor[m];
-    } else {
+  {
+    int jn[6], jc[6];
+    const T* ji[6];
+    T* jo[6];
+    int nj = 0;
+    for (int m = 0; m < d; ++m) {
+      int n = x->n[m];
+      rx[m] = x->rank[m];
+      ry[m] = y->rank[m];
+      if (c->spectral) {
+        Vx[m] = (T*)x->factor[m];
+        Vy[m] = (T*)y->factor[m];
+        continue;
+      }
       TPCHK(wsalloc(c, (size_t)n * rx[m], &Vx[m]));
       TPCHK(wsalloc(c, (size_t)n * ry[m], &Vy[m]));
-      TPCHK(dst_cols<T>(c, n, rx[m], (const T*)x->factor[m], Vx[m]));
-      TPCHK(dst_cols<T>(c, n, ry[m], (const T*)y->factor[m], Vy[m]));
+      jn[nj] = n; jc[nj] = rx[m]; ji[nj] = (const T*)x->factor[m]; jo[nj++] = Vx[m];
+      jn[nj] = n; jc[nj] = ry[m]; ji[nj] = (const T*)y->factor[m]; jo[nj++] = Vy[m];
     }
+    TPCHK(dst_cols_batch<T>(c, nj, jn, jc, ji, jo));
+  }
+  for (int m = 0; m < d; ++m) {
+    int n = x->n[m];
     // G[i + rx (j + ry k)] (sigma folded into the last mode)
     TPCHK(wsalloc(c, (size_t)rx[m] * ry[m] * R, &G[m]));
     GemmArgs<T, T, double, double> g;

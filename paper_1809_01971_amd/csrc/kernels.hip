@@ -390,9 +390,13 @@ template hipError_t dst_table<float>(int, float*, hipStream_t);
 // columns where the FP64 work array fits in LDS, see dst1).
 // GLOBAL: the work array lives in `work` (one slice of cpw * N/2 complex values per workgroup,
 // L2 resident) instead of LDS; the barriers order those global accesses within the workgroup.
+// Several column blocks of one length share a launch: the workgroups of job i start at
+// blockIdx.x = blk0 (increasing with i).
+template <typename TI>
+struct DstJobs { DstJob<TI> j[kDstJobs]; int count; };
+
 template <typename TI, typename T, bool GLOBAL>
-__global__ __launch_bounds__(256) void k_dst1(int N, int logL, int cols, int cpw, const TI* in,
-                                              int ldin, TI* out, int ldout,
+__global__ __launch_bounds__(256) void k_dst1(int N, int logL, int cpw, DstJobs<TI> jobs,
                                               const T* __restrict__ tab, T scale, C2<T>* work) {
   extern __shared__ char smem_raw[];
   const int L = N >> 1;
@@ -401,7 +405,12 @@ __global__ __launch_bounds__(256) void k_dst1(int N, int logL, int cols, int cpw
   double* partial = GLOBAL ? reinterpret_cast<double*>(smem_raw)
                            : reinterpret_cast<double*>(reinterpret_cast<C2<T>*>(smem_raw) + tot);  // 256 chunk totals
   const int tid = threadIdx.x;
-  const int col0 = blockIdx.x * cpw;
+  int jb = 0;
+  while (jb + 1 < jobs.count && (int)blockIdx.x >= jobs.j[jb + 1].blk0) ++jb;
+  const int cols = jobs.j[jb].cols, ldin = jobs.j[jb].ldin, ldout = jobs.j[jb].ldout;
+  const TI* in = jobs.j[jb].in;
+  TI* out = jobs.j[jb].out;
+  const int col0 = ((int)blockIdx.x - jobs.j[jb].blk0) * cpw;
 
   auto xval = [&](int c, int j) -> T {  // x_j, 1-based, zero outside 1..N-1
     int col = col0 + c;
@@ -501,17 +510,26 @@ __global__ __launch_bounds__(256) void k_dst1(int N, int logL, int cols, int cpw
 }
 
 template <typename TI, typename T>
-hipError_t dst1_launch(int N, int cols, const TI* in, int ldin, TI* out, int ldout, const T* tab, void* work,
-                       hipStream_t s) {
+hipError_t dst1_launch(int N, const DstJob<TI>* jl, int count, const T* tab, void* work, hipStream_t s) {
   int L = N / 2;
   int logL = 0;
   while ((1 << logL) < L) ++logL;
   int cpw = L >= 256 ? 1 : 256 / L;
   T scale = (T)sqrt(2.0 / (double)N);
-  int blocks = (cols + cpw - 1) / cpw;
+  DstJobs<TI> jobs;
+  jobs.count = 0;
+  int blocks = 0;
+  for (int i = 0; i < count; ++i) {
+    if (jl[i].cols <= 0) continue;
+    DstJob<TI> j = jl[i];
+    j.blk0 = blocks;
+    blocks += (j.cols + cpw - 1) / cpw;
+    jobs.j[jobs.count++] = j;
+  }
+  if (blocks == 0) return hipSuccess;
   if (work) {
-    hipLaunchKernelGGL((k_dst1<TI, T, true>), dim3(blocks), dim3(256), 256 * sizeof(double), s, N, logL, cols, cpw,
-                       in, ldin, out, ldout, tab, scale, reinterpret_cast<C2<T>*>(work));
+    hipLaunchKernelGGL((k_dst1<TI, T, true>), dim3(blocks), dim3(256), 256 * sizeof(double), s, N, logL, cpw, jobs,
+                       tab, scale, reinterpret_cast<C2<T>*>(work));
     return hipGetLastError();
   }
   size_t shm = (size_t)cpw * L * sizeof(C2<T>) + 256 * sizeof(double);
@@ -520,8 +538,8 @@ hipError_t dst1_launch(int N, int cols, const TI* in, int ldin, TI* out, int ldo
                                        (int)shm);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_dst1<TI, T, false>), dim3(blocks), dim3(256), shm, s, N, logL, cols, cpw, in, ldin, out, ldout,
-                     tab, scale, (C2<T>*)nullptr);
+  hipLaunchKernelGGL((k_dst1<TI, T, false>), dim3(blocks), dim3(256), shm, s, N, logL, cpw, jobs, tab, scale,
+                     (C2<T>*)nullptr);
   return hipGetLastError();
 }
 
@@ -530,19 +548,37 @@ hipError_t dst1_launch(int N, int cols, const TI* in, int ldin, TI* out, int ldo
 // transform of a vector whose spectrum sits at either end (the smooth factors of the iterates)
 // loses about eps N / pi relative accuracy (measured: 5e-5 for the inverse of the first mode at
 // N = 8192, 7e-5 at N = 32768); the FP64 work array removes it.  It fits in LDS up to N = 16384;
-// at N = 32768 it lives in `work` (cols * N/2 complex doubles, global).
+// at N = 32768 it lives in `work` (cols * N/2 complex doubles, global, one job per launch).
+template <typename T>
+static hipError_t dst1_jobs(int N, const DstJob<T>* jobs, int count, const T* tab, const double* tab64, void* work,
+                            hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (count > kDstJobs) return hipErrorInvalidValue;
+  if (std::is_same<T, float>::value && tab64 && (N <= 16384 || work))
+    return dst1_launch<T, double>(N, jobs, count, tab64, N <= 16384 ? nullptr : work, s);
+  return dst1_launch<T, T>(N, jobs, count, tab, N <= 16384 ? nullptr : work, s);
+}
+
 template <typename T>
 hipError_t dst1(int N, int cols, const T* in, int ldin, T* out, int ldout, const T* tab, const double* tab64,
                 void* work, hipStream_t s) {
   if (cols <= 0) return hipSuccess;
-  if (std::is_same<T, float>::value && tab64 && (N <= 16384 || work))
-    return dst1_launch<T, double>(N, cols, in, ldin, out, ldout, tab64, N <= 16384 ? nullptr : work, s);
-  return dst1_launch<T, T>(N, cols, in, ldin, out, ldout, tab, N <= 16384 ? nullptr : work, s);
+  const DstJob<T> j{in, out, cols, ldin, ldout, 0};
+  return dst1_jobs<T>(N, &j, 1, tab, tab64, work, s);
 }
+
+template <typename T>
+hipError_t dst1_batched(int N, const DstJob<T>* jobs, int count, const T* tab, const double* tab64, hipStream_t s) {
+  if (N > 16384) return hipErrorInvalidValue;
+  return dst1_jobs<T>(N, jobs, count, tab, tab64, nullptr, s);
+}
+
 template hipError_t dst1<double>(int, int, const double*, int, double*, int, const double*, const double*, void*,
                                  hipStream_t);
 template hipError_t dst1<float>(int, int, const float*, int, float*, int, const float*, const double*, void*,
                                 hipStream_t);
+template hipError_t dst1_batched<double>(int, const DstJob<double>*, int, const double*, const double*, hipStream_t);
+template hipError_t dst1_batched<float>(int, const DstJob<float>*, int, const float*, const double*, hipStream_t);
 
 // ---------------------------------------------------------------------------------------------
 // Cyclic Jacobi eigensolver (FP64), round-robin parallel ordering, A in LDS, V in global.

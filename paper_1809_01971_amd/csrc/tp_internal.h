@@ -44,6 +44,14 @@ void gemm_set_mfma(int on);
 template <typename T>
 hipError_t dst1(int N, int cols, const T* in, int ldin, T* out, int ldout, const T* tab, const double* tab64,
                 void* work, hipStream_t s);
+// The same transform of up to kDstJobs column blocks of one length in one launch (N <= 16384):
+// block i maps cols columns of in (ld ldin) to out (ld ldout); in == out is allowed.  The jobs
+// travel in the kernel arguments; blk0 is set by the launch.
+constexpr int kDstJobs = 6;
+template <typename T>
+struct DstJob { const T* in; T* out; int cols; int ldin; int ldout; int blk0; };
+template <typename T>
+hipError_t dst1_batched(int N, const DstJob<T>* jobs, int count, const T* tab, const double* tab64, hipStream_t s);
 
 template <typename T>
 hipError_t dst_table(int N, T* tab, hipStream_t s);
