@@ -37,8 +37,8 @@ ERR_SLAB_STRIDE = 4  # exact error over every 4th first-index spectral slab (unb
 # follows) from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, each scaled by the reading of a 256 MiB
 # device copy; valid only for the sources and mixed settings they were taken with, identified by
 # traffic_key() (SHA-256 prefix of csrc/kernels.hip, csrc/api.hip and the settings' JSON).
-TRAFFIC = {"src": "2fc8830fe3532c90", "bytes_per_launch": {"gemm_f32": 20182540, "gram_eig": 233131, "gemm_f64": 7727381,
-                                               "gemm_f32_f64": 13674500, "gemm_f64_f32": 1515729}}
+TRAFFIC = {"src": "b5efe5871e6c9cfc", "bytes_per_launch": {"gemm_f32": 20177615, "gram_eig": 235818, "gemm_f64": 7718843,
+                                               "gemm_f32_f64": 13660664, "gemm_f64_f32": 1518213}}
 
 
 def traffic_key():

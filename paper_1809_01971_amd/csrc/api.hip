@@ -1536,7 +1536,9 @@ tp_status fit_expsum_multi(tp_ctx* c, std::vector<FitSpec>& fits) {
     const Buf& b = bf[i];
     HIPCHK(fit_solve(F.K, b.nc, b.ew, b.E, b.bvec, b.cn, 1e-15, b.wsol, c->stream));
     // errors straight to the mapped host scratch
-    HIPCHK(fit_error(F.kind, F.f, F.rho0, F.B, F.K, b.t, b.wsol, b.nc, 4096, c->dmap + b.off, c->stream));
+    double* part;
+    TPCHK(wsalloc(c, (size_t)16 * b.nc, &part));
+    HIPCHK(fit_error(F.kind, F.f, F.rho0, F.B, F.K, b.t, b.wsol, b.nc, 4096, c->dmap + b.off, part, c->stream));
   }
   HIPCHK(hipStreamSynchronize(c->stream));
   const double* herr = c->hmap;
@@ -1823,12 +1825,13 @@ tp_status tp_symbol_build(tp_ctx* c, const tp_symbol_desc* desc, tp_symbol** op,
   if (s[0]->err < 0) {
     // evaluate rho*g(rho)/s(rho)-1 with fit_error in the unscaled variable (rho0 = 1 scaling: y = rho/rho0)
     WsScope scope(c);
-    double *ts, *e;
-    if (wsalloc(c, (size_t)s[0]->K, &ts) != TP_OK || wsalloc(c, 1, &e) != TP_OK) return cleanup(TP_ENOMEM);
+    double *ts, *e, *part;
+    if (wsalloc(c, (size_t)s[0]->K, &ts) != TP_OK || wsalloc(c, 1, &e) != TP_OK || wsalloc(c, 16, &part) != TP_OK)
+      return cleanup(TP_ENOMEM);
     if (hipMemcpyAsync(ts, s[0]->tau, sizeof(double) * s[0]->K, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
         scale(ts, s[0]->K, rho0, c->stream) != hipSuccess)
       return cleanup(fail(TP_EHIP, "scale failed"));
-    if (fit_error(0, fn, rho0, B, s[0]->K, ts, s[0]->w, 1, 4096, e, c->stream) != hipSuccess)
+    if (fit_error(0, fn, rho0, B, s[0]->K, ts, s[0]->w, 1, 4096, e, part, c->stream) != hipSuccess)
       return cleanup(fail(TP_EHIP, "error kernel failed"));
     double he = 0;
     if (sync_to_host(c, e, sizeof(double), &he) != TP_OK) return cleanup(TP_EHIP);

@@ -1716,14 +1716,17 @@ hipError_t fit_design(int kind, const SymFn& f, double rho0, double B, int K, in
   return hipGetLastError();
 }
 
+// kFitSplit workgroups share the points of a candidate; each writes its maximum to part and a
+// second kernel takes the maximum of those per candidate.
+constexpr int kFitSplit = 16;
 __global__ __launch_bounds__(256) void k_fit_error(int kind, SymFn f, double rho0, double B, int K, const double* t,
-                                                   const double* w, int m, double* err) {
+                                                   const double* w, int m, double* part) {
   __shared__ double red[256];
-  int c = blockIdx.x;
+  const int c = blockIdx.x / kFitSplit, sub = blockIdx.x % kFitSplit;
   const double* tc = t + (long)c * K;
   const double* wc = w + (long)c * K;
   double mx = 0.0;
-  for (int j = threadIdx.x; j < m; j += 256) {
+  for (int j = sub * 256 + threadIdx.x; j < m; j += 256 * kFitSplit) {
     double y = exp(log(B) * (double)j / (double)(m - 1));
     double v = 0.0;
     for (int k = 0; k < K; ++k) v += wc[k] * exp(-tc[k] * y);
@@ -1739,11 +1742,23 @@ __global__ __launch_bounds__(256) void k_fit_error(int kind, SymFn f, double rho
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) err[c] = red[0];
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+__global__ void k_fit_error_max(int ncand, const double* part, double* err) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncand) return;
+  double mx = part[(long)c * kFitSplit];
+  for (int i = 1; i < kFitSplit; ++i) {
+    const double a = part[(long)c * kFitSplit + i];
+    mx = (mx >= a || isnan(mx)) ? mx : a;
+  }
+  err[c] = mx;
 }
 hipError_t fit_error(int kind, const SymFn& f, double rho0, double B, int K, const double* t, const double* w,
-                     int ncand, int m, double* err, hipStream_t s) {
-  hipLaunchKernelGGL(k_fit_error, dim3(ncand), dim3(256), 0, s, kind, f, rho0, B, K, t, w, m, err);
+                     int ncand, int m, double* err, double* part, hipStream_t s) {
+  if (ncand <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fit_error, dim3(ncand * kFitSplit), dim3(256), 0, s, kind, f, rho0, B, K, t, w, m, part);
+  hipLaunchKernelGGL(k_fit_error_max, dim3((ncand + 255) / 256), dim3(256), 0, s, ncand, (const double*)part, err);
   return hipGetLastError();
 }
 

@@ -136,9 +136,10 @@ struct SymFn { double c0, cn, cp, alpha, beta; int fitpos; };
 struct FitCand { double a, b; };
 hipError_t fit_design(int kind, const SymFn& f, double rho0, double B, int K, int m, const FitCand* cands_dev,
                       int ncand, double* A, double* tvec, hipStream_t s);
-// max relative error of the fitted sums over m log-spaced points, per candidate
+// max relative error of the fitted sums over m log-spaced points, per candidate; part: device
+// scratch of 16 ncand doubles (partial maxima)
 hipError_t fit_error(int kind, const SymFn& f, double rho0, double B, int K, const double* t, const double* w,
-                     int ncand, int m, double* err, hipStream_t s);
+                     int ncand, int m, double* err, double* part, hipStream_t s);
 hipError_t sinc_g_nodes(double alpha, double cneg, double cpos, double rho0, int kl, int kr, double hh,
                         double* tau, double* w, hipStream_t s);
 // out = c0 + rho sum_k w_k exp(-tau_k rho) (opkind 0) or sum_k w_k exp(-tau_k rho) at multi-indices
