@@ -21,8 +21,7 @@
  *     message (thread-local, valid until the next call on that thread).  Invalid
  *     arguments are rejected before any device work is enqueued.
  *   - The grid size n must satisfy n >= 1 and n+1 a power of two (the sine
- *     transform runs as a radix-2 FFT); n+1 <= 32768 in mixed precision and
- *     n+1 <= 16384 in FP64.
+ *     transform runs as a radix-2 FFT), n+1 <= 32768, in both precisions.
  */
 #ifndef TP_H
 #define TP_H
@@ -40,7 +39,10 @@ typedef enum {
   TP_ENOMEM = 2,    /* workspace or device allocation too small / failed */
   TP_ENOCONV = 3,   /* PCG did not reach tau; x holds its best iterate (the tables' '---') */
   TP_ERANK = 4,     /* a truncation hit the rank cap with the tolerance unmet */
-  TP_EHIP = 5       /* a HIP runtime call failed */
+  TP_EHIP = 5,      /* a HIP runtime call failed */
+  TP_EINDEF = 6     /* tp_symbol_build: the preconditioner is not positive on the points it was
+                     * checked on (PCG needs a positive definite one); both symbols are still
+                     * returned, owned by the caller, and a solve with them may break down */
 } tp_status;
 
 typedef enum { TP_FP64 = 0, TP_MIXED = 1 } tp_precision;
@@ -122,7 +124,11 @@ typedef struct {
  *
  * method TP_SYM_SINC (c0 = 0, beta = alpha only): g by the sinc rule u_k = k*h,
  *   k = -sinc_kl..sinc_kr, t = log(1+e^u), weights h phi'(u) [c_neg t^alpha/Gamma(1+alpha)
- *   rho0^-(1+alpha) + c_pos t^-alpha/Gamma(1-alpha) rho0^-(1-alpha)], rho0 = d*lambda_1.
+ *   rho0^-(1+alpha) + c_pos t^-alpha/Gamma(1-alpha) rho0^-(1-alpha)], rho0 = d*lambda_1
+ *   (Sec. 2 eqn:sinc_Laplace_tr, Sec. 4.2 with the substitution t = log(1+e^u)).  The paper's
+ *   symmetric rule with M is sinc_kl = sinc_kr = M (2M+1 nodes).  sinc_h = 0: the step is
+ *   h = c pi / sqrt(M'), M' = (sinc_kl + sinc_kr)/2, with the c of 24 geometric values in
+ *   [0.4, 4] whose rule has the smallest measured error (the paper leaves c open).
  * method TP_SYM_FIT: g by relative-error least squares on op_terms geometric
  *   exponents (fewer terms for the same accuracy).
  * The preconditioner always uses the least-squares fit with pre_terms exponents. */
@@ -135,9 +141,9 @@ typedef struct {
   int32_t method;      /* tp_symbol_method */
   int32_t op_terms;    /* TP_SYM_FIT: K (0 = 32); ignored when nothing is left to fit */
   int32_t pre_terms;   /* K' in [1, 64] (0 = 12) */
-  int32_t sinc_kl;     /* TP_SYM_SINC (0 = library default) */
-  int32_t sinc_kr;
-  double sinc_h;
+  int32_t sinc_kl;     /* TP_SYM_SINC: nodes left of u = 0 (0 = 60) */
+  int32_t sinc_kr;     /* nodes right of u = 0 (0 = 20) */
+  double sinc_h;       /* step (0 = chosen by the library, see above) */
   int32_t prec;        /* precision of the factor matrices (tp_precision) */
   double c0;           /* >= 0: constant term of the symbol (identity part of the operator) */
   double beta;         /* exponent of the c_pos term, in (0, 1]; 0 = alpha */
@@ -157,7 +163,11 @@ typedef struct {
 /* Build the operator symbol and the preconditioner symbol on the GPU.  Both are
  * owned by the library (free with tp_symbol_free).  err (host, 2 doubles, may be
  * NULL) receives the measured max relative errors of the two exponential sums
- * on 4096 log-spaced points of [rho_min, rho_max]. */
+ * on 4096 log-spaced points of [rho_min, rho_max] (for pre_rank > 0 the second is
+ * max |p s - 1| over the lattice of grid points).  Returns TP_EINDEF, with both symbols
+ * built and returned, when the preconditioner p is not positive on those points: for the
+ * fitted sum when its relative error reaches 1, for a rank-r preconditioner when
+ * min p s <= 0 on the lattice (Algorithm alg:pcg needs a positive definite preconditioner). */
 tp_status tp_symbol_build(tp_ctx* ctx, const tp_symbol_desc* desc, tp_symbol** op,
                           tp_symbol** pre, double* err);
 tp_status tp_symbol_free(tp_symbol* sym);

@@ -83,8 +83,3 @@ def symbol(rho, alpha, c_neg, c_pos, c0=0.0, beta=None):
     rho = np.asarray(rho, dtype=np.float64)
     b = alpha if beta is None else beta
     return c0 + c_neg * rho ** (-alpha) + c_pos * rho**b
-
-
-def paper_coefficients(beta, gamma):
-    """(c_neg, c_pos) of eqn:forControl: beta A^-alpha + (gamma/beta) A^alpha."""
-    return float(beta), float(gamma) / float(beta)

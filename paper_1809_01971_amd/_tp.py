@@ -4,7 +4,7 @@ import os
 
 import numpy as np
 
-TP_OK, TP_EINVAL, TP_ENOMEM, TP_ENOCONV, TP_ERANK, TP_EHIP = range(6)
+TP_OK, TP_EINVAL, TP_ENOMEM, TP_ENOCONV, TP_ERANK, TP_EHIP, TP_EINDEF = range(7)
 TP_FP64, TP_MIXED = 0, 1
 TP_SYM_FIT, TP_SYM_SINC = 0, 1
 TP_STOP_ERROR, TP_STOP_RESIDUAL = 0, 1
@@ -213,7 +213,10 @@ class Context:
     # ---- symbols
     def symbol_build(self, d, n, alpha, c_neg, c_pos, prec=TP_FP64, method=TP_SYM_FIT, op_terms=0,
                      pre_terms=0, sinc_kl=0, sinc_kr=0, sinc_h=0.0, c0=0.0, beta=0.0, pre_rank=0,
-                     directional=False):
+                     directional=False, allow_indefinite=False):
+        """Operator and preconditioner symbols and their measured errors.  A preconditioner that is
+        not positive on its checked points (TP_EINDEF) raises unless allow_indefinite; then the
+        symbols are returned and `indefinite` is set on the preconditioner."""
         desc = tp_symbol_desc()
         desc.d = d
         ns = mode_sizes(d, n)
@@ -227,7 +230,17 @@ class Context:
         desc.prec = prec
         op, pre = P(), P()
         err = (C.c_double * 2)()
-        _check(self.lib.tp_symbol_build(self.h, C.byref(desc), C.byref(op), C.byref(pre), err))
+        st = self.lib.tp_symbol_build(self.h, C.byref(desc), C.byref(op), C.byref(pre), err)
+        if st == TP_EINDEF:
+            so, sp = Symbol(self, op, d, prec), Symbol(self, pre, d, prec)
+            sp.indefinite = True
+            if allow_indefinite:
+                return so, sp, (err[0], err[1])
+            msg = self.lib.tp_last_error().decode(errors="replace")
+            so.free()
+            sp.free()
+            raise TPError(st, msg)
+        _check(st)
         return Symbol(self, op, d, prec), Symbol(self, pre, d, prec), (err[0], err[1])
 
     def state_symbol_build(self, d, n, alpha, beta, prec=TP_FP64, terms=0, directional=False):
@@ -316,7 +329,8 @@ class Context:
                     "applies": info.op_applies, "err_est": info.err_est}
 
 
-def _desc(d, n, alpha, c_neg, c_pos, prec, op_terms, pre_terms):
+def _desc(d, n, alpha, c_neg, c_pos, prec, op_terms, pre_terms, **kw):
+    """tp_symbol_desc; kw sets further fields by name (method, sinc_kl, c0, beta, pre_rank, ...)."""
     desc = tp_symbol_desc()
     desc.d = d
     ns = mode_sizes(d, n)
@@ -325,7 +339,12 @@ def _desc(d, n, alpha, c_neg, c_pos, prec, op_terms, pre_terms):
     desc.alpha, desc.c_neg, desc.c_pos = alpha, c_neg, c_pos
     desc.method, desc.op_terms, desc.pre_terms = TP_SYM_FIT, op_terms, pre_terms
     desc.prec = prec
+    for k, v in kw.items():
+        setattr(desc, k, v)
     return desc
+
+
+_DESC_KEYS = ("method", "sinc_kl", "sinc_kr", "sinc_h", "pre_rank", "directional")
 
 
 def workspace_query(d, n, alpha, settings, rhs_rank, c_neg=1.0, c_pos=1e-2, **desc_kw):
@@ -353,14 +372,17 @@ def batch_solve(ctx, problems, settings, sketches, streams=8, workspace_per_stre
     keep, outs = [], []
     for i, p in enumerate(problems):
         s = settings(p)
-        descs[i] = _desc(p.d, p.n, p.alpha, p.c_neg, p.c_pos, s["prec"], s["op_terms"], s["pre_terms"])
+        extra = {k: s[k] for k in _DESC_KEYS if k in s}
+        descs[i] = _desc(p.d, p.n, p.alpha, p.c_neg, p.c_pos, s["prec"], s["op_terms"], s["pre_terms"],
+                         c0=getattr(p, "c0", 0.0) or 0.0, beta=getattr(p, "beta", None) or 0.0, **extra)
         k, cp = cp_struct(p.weights, p.factors)
         keep.append(k)
         cps[i] = cp
         X = Tensor(p.d, p.n, s["cap"], s["prec"])
         outs.append(X)
         tens[i] = X.s
-        opts[i] = tp_pcg_opts(s["tau"], 100, s["eps"], s["cap"], 0, 0, 0, 1 if s.get("spectral") else 0, 0)
+        opts[i] = tp_pcg_opts(s["tau"], s.get("kmax", 100), s["eps"], s["cap"], 0, s.get("stop_rule", 0),
+                              1 if s.get("recursive_residual") else 0, 1 if s.get("spectral") else 0, 0)
         sk, k2 = sketch_struct(sketches[p.n])
         sks[i] = sk
     _check(ctx.lib.tp_pcg_solve_batched(ctx.h, cnt, descs, cps, tens, opts, sks, infos, streams,
@@ -377,6 +399,7 @@ def batch_solve(ctx, problems, settings, sketches, streams=8, workspace_per_stre
 class Symbol:
     def __init__(self, ctx, h, d, prec):
         self.ctx, self.h, self.d, self.prec = ctx, h, d, prec
+        self.indefinite = False
 
     def info(self):
         r, e = C.c_int32(), C.c_double()

@@ -97,9 +97,11 @@ struct tp_symbol {
   int K = 0;             // exponentials
   int R = 0;             // canonical rank (d*K for the operator, +1 with a constant term)
   double err = 0;
+  double pmin = 1.0;     // preconditioner: smallest p s on the checked points (rank-r lattice)
   double c0 = 0;         // constant term of the operator symbol (factors all ones)
   double wexact = 0;     // weight of the exact tau = 0 exponential (c_pos rho for beta = 1)
   int tucker = 0;        // > 0: rank-r recompressed preconditioner (general canonical factors)
+  double sinc_h = 0;     // step of the sinc rule (TP_SYM_SINC)
   bool arena = false;    // memory in a batched worker's workspace (nothing to free)
   double* weights = nullptr;   // R (device)
   void* factors[3] = {nullptr, nullptr, nullptr};  // n x R (device, T)
@@ -177,9 +179,9 @@ bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 tp_status check_grid(int n, int prec) {
   if (n < 1) return fail(TP_EINVAL, "grid size n=%d must be >= 1", n);
   if (!pow2(n + 1)) return fail(TP_EINVAL, "grid size n=%d: n+1 must be a power of two", n);
-  int lim = prec == TP_FP64 ? 16384 : 32768;
-  if (n + 1 > lim) return fail(TP_EINVAL, "grid size n=%d exceeds the %s sine-transform limit n+1<=%d", n,
-                               prec == TP_FP64 ? "FP64" : "mixed", lim);
+  (void)prec;
+  // up to n+1 = 16384 the transform's work array sits in LDS, beyond it in the workspace
+  if (n + 1 > 32768) return fail(TP_EINVAL, "grid size n=%d exceeds the sine-transform limit n+1<=32768", n);
   return TP_OK;
 }
 
@@ -1392,10 +1394,11 @@ tp_status recompress_pre(tp_ctx* c, tp_symbol* s, int r) {
   return TP_OK;
 }
 
-// max |p s - 1| of a recompressed preconditioner p over a lattice of grid points whose indices
-// are geometric in every mode (64 per mode in 2D, 16 in 3D), s the exact symbol of fn in
+// max |p s - 1| and min p s of a recompressed preconditioner p over a lattice of grid points whose
+// indices are geometric in every mode (64 per mode in 2D, 16 in 3D), s the exact symbol of fn in
 // rho = sum_l lambda_{i_l}^power.
-tp_status pre_lattice_error(tp_ctx* c, const tp_symbol* s, const SymFn& fn, double power, double* err) {
+tp_status pre_lattice_error(tp_ctx* c, const tp_symbol* s, const SymFn& fn, double power, double* err,
+                            double* pmin) {
   WsScope scope(c);
   const int d = s->d, L = d == 2 ? 64 : 16;
   std::vector<int> ax[3];
@@ -1436,12 +1439,15 @@ tp_status pre_lattice_error(tp_ctx* c, const tp_symbol* s, const SymFn& fn, doub
     HIPCHK(cp_eval<float>(d, di, cnt, s->n, F, s->R, s->weights, dout, c->stream));
   }
   TPCHK(sync_to_host(c, dout, sizeof(double) * cnt, pv.data()));
-  double mx = 0;
+  double mx = 0, mn = HUGE_VAL;
   for (int p = 0; p < cnt; ++p) {
-    double e = std::fabs(pv[p] * sv[p] - 1.0);
+    const double ps = pv[p] * sv[p];
+    const double e = std::fabs(ps - 1.0);
     if (!(e <= mx)) mx = e;
+    if (!(ps >= mn)) mn = ps;
   }
   *err = mx;
+  *pmin = mn;
   return TP_OK;
 }
 
@@ -1553,6 +1559,35 @@ tp_status fit_expsum_multi(tp_ctx* c, std::vector<FitSpec>& fits) {
     HIPCHK((convert<double, double>(b.t + (size_t)best * F.K, F.tau_out, F.K, c->stream)));
     HIPCHK((convert<double, double>(b.wsol + (size_t)best * F.K, F.w_out, F.K, c->stream)));
   }
+  return TP_OK;
+}
+
+// Step hh of the sinc rule u_k = k hh, k = -kl..kr, for g (kind 0 of fit_error): the candidates
+// hh = c pi / sqrt(M), M = (kl + kr) / 2, c geometric in [0.4, 4], are all evaluated on 4096
+// log-spaced points of [rho_min, rho_max] in one launch; the smallest measured error wins.
+tp_status sinc_step_scan(tp_ctx* c, double alpha, double cn, double cp, const SymFn& fn, double rho0, double B,
+                         int kl, int kr, double* hh) {
+  WsScope scope(c);
+  constexpr int nc = 24;
+  const int K = kl + kr + 1 + (std::fabs(1.0 - alpha) < 1e-15 ? 1 : 0);
+  const double M = std::max(1.0, 0.5 * (kl + kr));
+  double *t, *w, *part;
+  TPCHK(wsalloc(c, (size_t)nc * K, &t));
+  TPCHK(wsalloc(c, (size_t)nc * K, &w));
+  TPCHK(wsalloc(c, (size_t)16 * nc, &part));
+  double cand[nc];
+  for (int j = 0; j < nc; ++j) {
+    cand[j] = 0.4 * std::pow(10.0, (double)j / (nc - 1)) * M_PI / std::sqrt(M);
+    HIPCHK(sinc_g_nodes(alpha, cn, cp, rho0, kl, kr, cand[j], t + (size_t)j * K, w + (size_t)j * K, c->stream));
+  }
+  // the nodes come out as tau = t / rho0; the error kernel works in y = rho / rho0
+  HIPCHK(scale(t, (long)nc * K, rho0, c->stream));
+  HIPCHK(fit_error(0, fn, rho0, B, K, t, w, nc, 4096, c->dmap, part, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  int best = 0;
+  for (int j = 1; j < nc; ++j)
+    if (c->hmap[j] < c->hmap[best] || std::isnan(c->hmap[best])) best = j;
+  *hh = cand[best];
   return TP_OK;
 }
 
@@ -1777,9 +1812,16 @@ tp_status tp_symbol_build(tp_ctx* c, const tp_symbol_desc* desc, tp_symbol** op,
       }
       so->err = 0.0;
     } else {
+      if (D.sinc_h <= 0) {
+        // the paper leaves the step constant of hh = c pi / sqrt(M) open: the library takes the c of
+        // a geometric scan over [0.4, 4] whose rule has the smallest measured error on [rho_min, rho_max]
+        tp_status st = sinc_step_scan(c, alpha, D.c_neg, D.c_pos, fn, rho0, B, kl, kr, &hh);
+        if (st != TP_OK) return cleanup(st);
+      }
       if (sinc_g_nodes(alpha, D.c_neg, D.c_pos, rho0, kl, kr, hh, so->tau, so->w, c->stream) != hipSuccess)
         return cleanup(fail(TP_EHIP, "sinc kernel failed"));
       so->err = -1;
+      so->sinc_h = hh;
     }
   }
   // preconditioner
@@ -1819,7 +1861,7 @@ tp_status tp_symbol_build(tp_ctx* c, const tp_symbol_desc* desc, tp_symbol** op,
   }
   if (D.pre_rank > 0) {
     // measured error of the recompressed preconditioner: max |p s - 1| over a lattice of grid points
-    tp_status st = pre_lattice_error(c, s[1], fn, power, &s[1]->err);
+    tp_status st = pre_lattice_error(c, s[1], fn, power, &s[1]->err, &s[1]->pmin);
     if (st != TP_OK) return cleanup(st);
   }
   if (s[0]->err < 0) {
@@ -1839,9 +1881,17 @@ tp_status tp_symbol_build(tp_ctx* c, const tp_symbol_desc* desc, tp_symbol** op,
   }
   if (hipStreamSynchronize(c->stream) != hipSuccess) return cleanup(fail(TP_EHIP, "stream sync failed"));
   if (err) { err[0] = s[0]->err; err[1] = s[1]->err; }
+  // positivity of the preconditioner on the checked points: a fitted sum with relative error
+  // below 1 is positive there; a rank-r recompression is checked on its lattice
+  if (D.pre_rank == 0) s[1]->pmin = 1.0 - s[1]->err;
+  const bool indefinite = !(s[1]->pmin > 0.0);
+  const double pmin = s[1]->pmin;
   *op = s[0];
   *pre = s[1];
   s[0] = s[1] = nullptr;
+  if (indefinite)
+    return fail(TP_EINDEF, "preconditioner not positive: min p*s = %g on the checked points (max |p*s - 1| = %g)",
+                pmin, (*pre)->err);
   return TP_OK;
 }
 
@@ -2204,17 +2254,22 @@ tp_status pcg_impl(tp_ctx* c, const tp_symbol* op, const tp_symbol* pre, const t
   double rz = 0;
   TPCHK(inner_impl<T>(c, &R, &Z, &rz));
   bool converged = false, stalled = false;
+  // breakdown: <R,Z> <= 0 or <P,fun(P)> <= 0 (a preconditioner or operator that is not
+  // positive definite); the loop ends there and the best iterate so far is returned
+  double breakdown_val = 0.0;
+  const char* breakdown = !(rz > 0) ? "<R,Z>" : nullptr;
+  if (breakdown) breakdown_val = rz;
   double best = HUGE_VAL;  // smallest error estimate so far; its iterate is kept in Xb
   int kbest = 0;
   int k = 0;
-  for (; k < o->kmax; ++k) {
+  for (; k < o->kmax && !breakdown; ++k) {
     // S = fun(P) stays in exact factored form (canonical symbol times P): <P,S> is computed
     // without truncation, and by default the residual is recomputed from X each step,
     // R = trunc(B - fun(X)), so residual components a truncation drops are seen again at the
     // next step
     double ps = 0;
     TPCHK(inner_sym_impl<T>(c, &P, op, &P, &ps));
-    if (!(ps > 0)) return fail(TP_ENOCONV, "PCG breakdown: <P,S> = %g", ps);
+    if (!(ps > 0)) { breakdown = "<P,fun(P)>"; breakdown_val = ps; break; }
     const double a = rz / ps;
     if (k == 0 && !warm) {
       // X0 = 0: X1 = a P exactly (P is already truncated, a sum with zero adds nothing to cut)
@@ -2292,6 +2347,7 @@ tp_status pcg_impl(tp_ctx* c, const tp_symbol* op, const tp_symbol* pre, const t
     }
     double rz_new = 0;
     TPCHK(inner_impl<T>(c, &R, &Z, &rz_new));
+    if (!(rz_new > 0)) { breakdown = "<R,Z>"; breakdown_val = rz_new; ++k; break; }
     const double beta = rz_new / rz;
     rz = rz_new;
     {
@@ -2325,6 +2381,9 @@ tp_status pcg_impl(tp_ctx* c, const tp_symbol* op, const tp_symbol* pre, const t
   }
   if (!converged) {
     info->status = TP_ENOCONV;
+    if (breakdown)
+      return fail(TP_ENOCONV, "PCG breakdown after %d iterations: %s = %g (operator or preconditioner not "
+                  "positive definite); x holds the best iterate", k, breakdown, breakdown_val);
     if (stalled)
       return fail(TP_ENOCONV, "PCG stalled at error estimate %g > tau=%g after %d iterations (precision or rank-cap "
                   "floor); x holds the best iterate", info->err_est, o->tau, k);
@@ -2474,13 +2533,18 @@ extern "C" tp_status tp_pcg_solve_batched(tp_ctx* c, int32_t count, const tp_sym
       double errs[2];
       const size_t mark = cw->ws_top;  // the symbols go to the workspace below the solve's scopes
       tp_status st = tp_symbol_build(cw, &descs[i], &op, &pre, errs);
-      if (st == TP_OK) st = tp_pcg_solve(cw, op, pre, &bs[i], &xs[i], &opts[i], &sks[i], &infos[i]);
-      else infos[i].status = st;
+      const bool indefinite = st == TP_EINDEF;  // symbols returned; the solve may break down
+      if (st == TP_OK || indefinite) {
+        st = tp_pcg_solve(cw, op, pre, &bs[i], &xs[i], &opts[i], &sks[i], &infos[i]);
+        if (indefinite && st == TP_OK) infos[i].status = st = TP_EINDEF;
+      } else {
+        infos[i].status = st;
+      }
       if (op) tp_symbol_free(op);
       if (pre) tp_symbol_free(pre);
       (void)hipStreamSynchronize(cw->stream);  // the next problem reuses the symbols' workspace
       cw->ws_top = mark;
-      if (st != TP_OK && st != TP_ERANK && st != TP_ENOCONV && wst[w] == TP_OK) {
+      if (st != TP_OK && st != TP_ERANK && st != TP_ENOCONV && st != TP_EINDEF && wst[w] == TP_OK) {
         wst[w] = st;
         werr[w] = g_err;
       }

@@ -37,15 +37,18 @@ def solve(ctx, p, prec, eps, tau, cap=64, q=None, op_terms=32, pre_terms=28, spe
 
 
 def test_cfg1_2d_fp64_against_full_grid_and_brute_force(ctx):
+    """The 2D workload (n = 63) in FP64 against the full-grid O1 and the dense brute force
+    (3969 x 3969 Kronecker-sum matrix, numpy eigh, no sine transform)."""
     p = workloads.cfg1()
     log("cfg1 fp64")
     X, st, info = solve(ctx, p, 0, eps=1e-8, tau=4e-8, op_terms=40, pre_terms=36)
     f = tensor.cp_full(p.weights, p.factors)
     u = exact.solve_full(f, p.alpha, p.c_neg, p.c_pos)
+    ub = exact.brute_force(f, p.alpha, p.c_neg, p.c_pos)
     got = ctx.eval_grid(X, [np.arange(p.n)] * 2)
-    err = rel(got, u)
-    log("  cfg1 err %.2e info %s" % (err, info))
-    assert err < FP64_TOL
+    err, errb = rel(got, u), rel(got, ub)
+    log("  cfg1 err %.2e (brute force %.2e) info %s" % (err, errb, info))
+    assert err < FP64_TOL and errb < FP64_TOL
     assert info["iters"] <= 20
 
 
@@ -106,8 +109,11 @@ def test_cfg2_type_n63_fp64(ctx, alpha, gamma):
     assert err < FP64_TOL
 
 
-@pytest.mark.parametrize("alpha,gamma", [(0.5, 1e-1), (0.25, 1e-3), (0.75, 1e-1)])
+@pytest.mark.parametrize("alpha,gamma", [(0.25, 1e-1), (0.25, 1e-3), (0.5, 1e-1), (0.5, 1e-3), (0.75, 1e-1),
+                                         (0.75, 1e-3)])
 def test_cfg2_n255_fp64(ctx, alpha, gamma):
+    """All six problems of the n = 255 configuration, FP64, the rank cap raised to what the tolerance
+    needs (96), against the full-grid O1."""
     p = workloads.cfg2(alpha=alpha, gamma=gamma)
     log("cfg2 n=255 alpha=%g gamma=%g" % (alpha, gamma))
     assert p.n == 255

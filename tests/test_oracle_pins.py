@@ -385,3 +385,82 @@ def test_directional_differs_from_the_fractional_laplacian():
     rp = spectral.rho_directional((5, 6), 0.5)
     r = spectral.rho_grid((5, 6)) ** 0.5
     assert np.all(r < rp)
+
+
+# ---------------------------------------------------------------- golden file and its generator
+def test_golden_sine_mode_file_is_what_its_generator_writes():
+    """The stored worked example is the committed 50-digit script's output, byte for byte."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("make_cfg1_sine_mode",
+                                                  os.path.join(GOLDEN, "make_cfg1_sine_mode.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    with open(os.path.join(GOLDEN, "cfg1_sine_mode.txt")) as fh:
+        assert fh.read() == mod.render()
+
+
+# ---------------------------------------------------------------- state and cost (Sec. 3.1)
+def _control_problem(shape, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(shape)
+
+
+@pytest.mark.parametrize("shape,alpha", [((9, 7), 0.5), ((5, 4, 6), 0.3), ((6, 6, 5), 0.8)])
+def test_state_matches_dense_fractional_power(shape, alpha):
+    """y = beta A^-alpha u (eqn:State) against the dense Kronecker-sum Laplacian, whose
+    eigenpairs come from numpy.linalg.eigh (no sine transform)."""
+    beta = 1.7
+    u = _control_problem(shape, 11)
+    A = exact.laplacian_full(shape)
+    lam, Q = np.linalg.eigh(A)
+    y_ref = ((Q * (beta * lam ** (-alpha))) @ Q.T @ u.reshape(-1)).reshape(shape)
+    np.testing.assert_allclose(exact.state_full(u, alpha, beta), y_ref, rtol=1e-11,
+                               atol=1e-12 * np.abs(y_ref).max())
+
+
+@pytest.mark.parametrize("shape,alpha,beta,gamma", [((9, 7), 0.5, 2.0, 0.3), ((5, 4, 6), 0.3, 0.6, 1e-2),
+                                                    ((6, 6, 5), 0.75, 1.5, 1e-3)])
+def test_exact_control_minimises_the_cost(shape, alpha, beta, gamma):
+    """The exact control u* = (beta A^-alpha + (gamma/beta) A^alpha)^-1 y_Omega (eqn:forControl) is
+    the minimiser of the reduced cost j(u) = J(y(u), u) with the state y(u) = beta A^-alpha u
+    (eqn:State) and J = 1/2 ||y - y_Omega||^2 + gamma/2 ||u||^2 (Sec. 3.1).  j is quadratic, so
+    for every direction v and step t:  j(u* + t v) - j(u*) = t^2/2 (||y(v)||^2 + gamma ||v||^2)
+    exactly (the linear term vanishes only at the minimiser).  beta != 1 separates the paper's
+    form from the others: a state without beta, the cost with gamma/beta, or the coefficients
+    swapped each leave a linear term and fail."""
+    y_om = _control_problem(shape, 5)
+    u = exact.solve_full(y_om, alpha, beta, gamma / beta)
+
+    def j(v):
+        return exact.cost_functional(exact.state_full(v, alpha, beta), v, y_om, gamma)
+
+    j0 = j(u)
+    rng = np.random.default_rng(7)
+    for _ in range(4):
+        v = rng.standard_normal(shape)
+        yv = exact.state_full(v, alpha, beta)
+        curv = float(np.sum(yv * yv)) + gamma * float(np.sum(v * v))
+        for t in (1e-3, 0.1, 1.0, -0.5):
+            inc = j(u + t * v) - j0
+            assert inc > 0
+            assert inc == pytest.approx(0.5 * t * t * curv, rel=1e-6, abs=1e-9 * abs(j0))
+
+
+def test_cost_stationarity_fails_for_the_other_operator_forms():
+    """Planted mistakes: the controls of the literal form (beta A^alpha + gamma A^-alpha), of the
+    form without the 1/beta, and of a sign-flipped power are not minimisers of the same cost,
+    so the exact identity above rejects them."""
+    shape, alpha, beta, gamma = (8, 7), 0.5, 2.0, 0.3
+    y_om = _control_problem(shape, 5)
+    wrong = [exact.solve_full(y_om, alpha, gamma, beta),          # literal north-star form
+             exact.solve_full(y_om, alpha, beta, gamma),          # gamma instead of gamma/beta
+             exact.solve_full(y_om, -alpha, beta, gamma / beta)]  # rho^+alpha in the state term
+    v = np.random.default_rng(3).standard_normal(shape)
+    yv = exact.state_full(v, alpha, beta)
+    curv = float(np.sum(yv * yv)) + gamma * float(np.sum(v * v))
+    for u in wrong:
+        def j(w):
+            return exact.cost_functional(exact.state_full(w, alpha, beta), w, y_om, gamma)
+        t = 1e-2
+        inc = j(u + t * v) - j(u)
+        assert abs(inc - 0.5 * t * t * curv) > 1e-3 * abs(inc)
