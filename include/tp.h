@@ -339,17 +339,20 @@ tp_status tp_lambda(tp_ctx* ctx, int32_t n, double* out);
  * Measurement
  * ------------------------------------------------------------------------- */
 
-/* Kernel classes timed when profiling is on. */
+/* Kernel classes timed when profiling is on: one class per kernel, whoever launches it (the
+ * contraction kernel's four type instantiations count apart). */
 typedef enum {
-  TP_PROF_GEMM_F64 = 0,      /* FP64 contractions (Gram, sketch, projection, core) */
-  TP_PROF_GEMM_F32 = 1,      /* FP32 contractions of the mixed path */
-  TP_PROF_GEMM_F32_F64 = 2,  /* FP32 operands accumulated into FP64 results */
-  TP_PROF_GEMM_F64_F32 = 3,  /* FP64 operands rounded into FP32 results */
-  TP_PROF_DST_F64 = 4,
-  TP_PROF_DST_F32 = 5,
-  TP_PROF_SYEV = 6,          /* eigensolves of the symbols' least-squares fits (Gram eigensolver) and tp_syev */
-  TP_PROF_CHOL = 7,          /* pivoted Cholesky of Gram matrices (orthonormal bases) */
-  TP_PROF_GRAM_EIG = 8       /* Gram eigensolver of the HOSVD (Cholesky + one-sided Jacobi) */
+  TP_PROF_GEMM_F64 = 0,      /* k_gemm_mfma, FP64: Gram, sketch, projection and core contractions */
+  TP_PROF_GEMM_F32 = 1,      /* k_gemm_mfma, FP32 operands and results (mixed path) */
+  TP_PROF_GEMM_F32_F64 = 2,  /* k_gemm_mfma, FP32 operands accumulated into FP64 results */
+  TP_PROF_GEMM_F64_F32 = 3,  /* k_gemm_mfma, FP64 operands rounded into FP32 results */
+  TP_PROF_DST_F64 = 4,       /* k_dst1, FP64 columns */
+  TP_PROF_DST_F32 = 5,       /* k_dst1, FP32 columns */
+  TP_PROF_SYEV = 6,          /* k_syev / k_syev_small: two-sided Jacobi of tp_syev */
+  TP_PROF_CHOL = 7,          /* k_pchol: pivoted Cholesky of Gram matrices (orthonormal bases) */
+  TP_PROF_PSD_EIG = 8,       /* k_psd_eig: Gram eigensolver (HOSVD ranks and bases, fit normal equations) */
+  TP_PROF_NS = 9,            /* k_ns_isqrt: Newton-Schulz inverse square root (second orthonormalisation) */
+  TP_PROF_GEMM_REDUCE = 10   /* k_gemm_reduce: split-K partial sums of the contractions (all types) */
 } tp_prof_class;
 
 /* Contraction kernels: mfma != 0 (default) uses the FP32/FP64 matrix-core tiles, 0 the FMA

@@ -96,7 +96,7 @@ _SIGS = {
 }
 
 PROF_CLASSES = ["gemm_f64", "gemm_f32", "gemm_f32_f64", "gemm_f64_f32", "dst_f64", "dst_f32", "syev", "chol",
-                "gram_eig"]
+                "psd_eig", "ns_isqrt", "gemm_reduce"]
 
 
 def load_library():
@@ -361,7 +361,8 @@ def workspace_query(d, n, alpha, settings, rhs_rank, c_neg=1.0, c_pos=1e-2, **de
 
 def batch_solve(ctx, problems, settings, sketches, streams=8, workspace_per_stream=0):
     """Solve independent problems concurrently (tp_pcg_solve_batched).  settings(p) -> dict with
-    prec, eps, tau, cap, op_terms, pre_terms; sketches[n] -> device sketch tensors for grid n."""
+    prec, eps, tau, cap, op_terms, pre_terms (and optionally q); sketches[(n, q)] or sketches[n] -> device
+    sketch tensors for grid n."""
     cnt = len(problems)
     descs = (tp_symbol_desc * cnt)()
     cps = (tp_cp * cnt)()
@@ -383,7 +384,8 @@ def batch_solve(ctx, problems, settings, sketches, streams=8, workspace_per_stre
         tens[i] = X.s
         opts[i] = tp_pcg_opts(s["tau"], s.get("kmax", 100), s["eps"], s["cap"], 0, s.get("stop_rule", 0),
                               1 if s.get("recursive_residual") else 0, 1 if s.get("spectral") else 0, 0)
-        sk, k2 = sketch_struct(sketches[p.n])
+        key = (p.n, s["q"]) if "q" in s else None
+        sk, k2 = sketch_struct(sketches[key] if key in sketches else sketches[p.n])
         sks[i] = sk
     _check(ctx.lib.tp_pcg_solve_batched(ctx.h, cnt, descs, cps, tens, opts, sks, infos, streams,
                                          workspace_per_stream))

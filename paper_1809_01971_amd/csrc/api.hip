@@ -85,7 +85,7 @@ struct tp_ctx {
   size_t ev_next = 0;
   struct Rec { int cls; size_t e0, e1; double flops, bytes; };
   std::vector<Rec> recs;
-  double prof_ms[16] = {0}, prof_n[16] = {0}, prof_flops[16] = {0}, prof_bytes[16] = {0};
+  double prof_ms[16] = {0}, prof_n[16] = {0}, prof_flops[16] = {0}, prof_bytes[16] = {0};  // by PC_* class
   static constexpr size_t kHost = 1 << 16;
   static constexpr size_t kMap = 4096;
   static constexpr int kJobs = 64;
@@ -136,12 +136,13 @@ struct WsScope {
 
 // ------------------------------------------------------------------------------ profiling
 // Kernel classes reported by tp_profile_read.
+// One class per kernel (template instantiations of the contraction count apart), whoever calls it.
 enum { PC_GEMM_F64 = 0, PC_GEMM_F32 = 1, PC_GEMM_F32_F64 = 2, PC_GEMM_F64_F32 = 3, PC_DST_F64 = 4, PC_DST_F32 = 5,
-       PC_SYEV = 6, PC_CHOL = 7, PC_GRAM_EIG = 8, PC_COUNT = 9 };
+       PC_SYEV = 6, PC_CHOL = 7, PC_PSD_EIG = 8, PC_NS = 9, PC_GEMM_REDUCE = 10, PC_COUNT = 11 };
 
 tp_status prof_begin(tp_ctx* c, size_t* e0) {
   if (!c->prof) return TP_OK;
-  if (c->ev_next + 2 > c->ev_pool.size()) {
+  if (c->ev_next + 3 > c->ev_pool.size()) {
     size_t old = c->ev_pool.size();
     c->ev_pool.resize(old + 1024);
     for (size_t i = old; i < c->ev_pool.size(); ++i) HIPCHK(hipEventCreate(&c->ev_pool[i]));
@@ -302,9 +303,11 @@ tp_status run(tp_ctx* c, const GemmArgs<TA, TB, TC, Tacc>& g0) {
       }
     }
   }
-  size_t e0 = 0;
+  size_t e0 = 0, em = 0;
   TPCHK(prof_begin(c, &e0));
-  hipError_t ge = gemm<TA, TB, TC, Tacc>(g, c->stream);
+  const bool split = c->prof && g.splits > 1 && g.part;
+  if (split) em = c->ev_next++;  // recorded by gemm() between the contraction and its reduction
+  hipError_t ge = gemm<TA, TB, TC, Tacc>(g, c->stream, split ? c->ev_pool[em] : nullptr);
   c->ws_top = mark;  // the partial-sum scratch is consumed by the launches just enqueued
   HIPCHK(ge);
   if (c->prof) {
@@ -315,7 +318,15 @@ tp_status run(tp_ctx* c, const GemmArgs<TA, TB, TC, Tacc>& g0) {
     double ba = g.fsA ? (double)M * (g.FA.r1 + K / std::max(1, g.FA.r1)) : M * K * (g.divA > 1 || g.sA ? b / g.divA : 1);
     double bb = g.fsB ? (double)K * (g.FB.r1 + N / std::max(1, g.FB.r1)) : K * N * (g.sB ? b / g.divB : 1);
     double by = ba * sizeof(TA) + bb * sizeof(TB) + M * N * b * sizeof(TC);
-    TPCHK(prof_end(c, gemm_class<TA, TB, TC, Tacc>(), e0, fl, by));
+    if (split) {
+      // the contraction [e0, em] carries the algorithmic work; the reduction [em, e1] adds the
+      // partial sums (splits x the output, read once) and writes the output
+      c->recs.push_back({gemm_class<TA, TB, TC, Tacc>(), e0, em, fl, by});
+      TPCHK(prof_end(c, PC_GEMM_REDUCE, em, M * N * b * (g.splits - 1),
+                     M * N * b * ((double)g.splits * sizeof(Tacc) + sizeof(TC))));
+    } else {
+      TPCHK(prof_end(c, gemm_class<TA, TB, TC, Tacc>(), e0, fl, by));
+    }
   }
   return TP_OK;
 }
@@ -429,7 +440,7 @@ tp_status ns_isqrt(tp_ctx* c, int cnt, const int* K, const double* const* G, dou
   {
     double fl = 0, by = 0;  // about three K^3 products per step, three steps
     for (int i = 0; i < cnt; ++i) { fl += 18.0 * K[i] * K[i] * K[i]; by += 8.0 * 2.0 * K[i] * K[i]; }
-    TPCHK(prof_end(c, PC_CHOL, e0, fl, by));
+    TPCHK(prof_end(c, PC_NS, e0, fl, by));
   }
   HIPCHK(hipStreamSynchronize(c->stream));
   const int* hok = reinterpret_cast<const int*>(c->hmap);
@@ -478,7 +489,7 @@ tp_status psd_eig(tp_ctx* c, int cnt, const int* K, const double* const* G, doub
     // (tridiagonal reduction, implicit QR, back transformation); bytes: G in, V and w out
     double fl = 0, by = 0;
     for (int i = 0; i < cnt; ++i) { fl += 9.0 * K[i] * K[i] * K[i]; by += 8.0 * (2.0 * K[i] * K[i] + K[i]); }
-    TPCHK(prof_end(c, PC_GRAM_EIG, e0, fl, by));
+    TPCHK(prof_end(c, PC_PSD_EIG, e0, fl, by));
   }
   HIPCHK(hipStreamSynchronize(c->stream));
   const double* hres = c->hmap + tot;
@@ -517,7 +528,7 @@ tp_status psd_eig_dev(tp_ctx* c, int cnt, const int* K, const double* const* G, 
   HIPCHK(psd_eig_batched(jb, cnt, Kmax, c->stream));
   double fl = 0, by = 0;
   for (int i = 0; i < cnt; ++i) { fl += 9.0 * K[i] * K[i] * K[i]; by += 8.0 * (2.0 * K[i] * K[i] + K[i]); }
-  TPCHK(prof_end(c, PC_SYEV, e0, fl, by));
+  TPCHK(prof_end(c, PC_PSD_EIG, e0, fl, by));
   return TP_OK;
 }
 
@@ -1226,6 +1237,7 @@ tp_status inner_impl(tp_ctx* c, const tp_tensor* x, const tp_tensor* y, double* 
   *out = c->hmap[0];
   return TP_OK;
 }
+
 
 // ------------------------------------------------------------------------------ CP -> Tucker
 template <typename T>

@@ -328,7 +328,7 @@ bool gemm_use_mfma() { return g_use_mfma != 0; }
 void gemm_set_mfma(int on) { g_use_mfma = on; }
 
 template <typename TA, typename TB, typename TC, typename Tacc>
-hipError_t gemm(const GemmArgs<TA, TB, TC, Tacc>& g, hipStream_t s) {
+hipError_t gemm(const GemmArgs<TA, TB, TC, Tacc>& g, hipStream_t s, hipEvent_t mid) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
   if (g.K <= 0) {
     // C = beta*C: handled by a degenerate launch with K = 0 (the loop body is skipped).
@@ -343,6 +343,10 @@ hipError_t gemm(const GemmArgs<TA, TB, TC, Tacc>& g, hipStream_t s) {
   else
     hipLaunchKernelGGL((k_gemm<TA, TB, TC, Tacc>), grid, dim3(GTHREADS), 0, s, h);
   if (h.splits > 1) {
+    if (mid) {
+      const hipError_t e = hipEventRecord(mid, s);
+      if (e != hipSuccess) return e;
+    }
     long mn = (long)h.M * h.N;
     dim3 rg((mn + 255) / 256, h.batch);
     hipLaunchKernelGGL((k_gemm_reduce<TC, Tacc>), rg, dim3(256), 0, s, h.M, h.N, h.splits, (const Tacc*)h.part,
@@ -351,10 +355,10 @@ hipError_t gemm(const GemmArgs<TA, TB, TC, Tacc>& g, hipStream_t s) {
   return hipGetLastError();
 }
 
-template hipError_t gemm<double, double, double, double>(const GemmArgs<double, double, double, double>&, hipStream_t);
-template hipError_t gemm<float, float, float, float>(const GemmArgs<float, float, float, float>&, hipStream_t);
-template hipError_t gemm<float, float, double, double>(const GemmArgs<float, float, double, double>&, hipStream_t);
-template hipError_t gemm<double, double, float, double>(const GemmArgs<double, double, float, double>&, hipStream_t);
+template hipError_t gemm<double, double, double, double>(const GemmArgs<double, double, double, double>&, hipStream_t, hipEvent_t);
+template hipError_t gemm<float, float, float, float>(const GemmArgs<float, float, float, float>&, hipStream_t, hipEvent_t);
+template hipError_t gemm<float, float, double, double>(const GemmArgs<float, float, double, double>&, hipStream_t, hipEvent_t);
+template hipError_t gemm<double, double, float, double>(const GemmArgs<double, double, float, double>&, hipStream_t, hipEvent_t);
 
 // ---------------------------------------------------------------------------------------------
 // DST-I via a length-N/2 complex FFT (N = n+1 a power of two).

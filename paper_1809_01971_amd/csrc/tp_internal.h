@@ -31,8 +31,10 @@ struct GemmArgs {
   int splits = 1; int kchunk = 0; Tacc* part = nullptr;
 };
 
+// mid (optional): an event recorded between the contraction and its split-K reduction, so that
+// the two kernels can be timed apart.
 template <typename TA, typename TB, typename TC, typename Tacc>
-hipError_t gemm(const GemmArgs<TA, TB, TC, Tacc>& g, hipStream_t s);
+hipError_t gemm(const GemmArgs<TA, TB, TC, Tacc>& g, hipStream_t s, hipEvent_t mid = nullptr);
 // Matrix-core (MFMA) tiles on (default) or the FMA tiles.
 bool gemm_use_mfma();
 void gemm_set_mfma(int on);

@@ -154,7 +154,9 @@ def test_rank_r_preconditioner_against_oracle(ctx, eq, d, n, r, prec):
     truncated HOSVD of the exact inverse symbol (in 2D its rank-r SVD), alpha = 1/2."""
     p = workloads.precond_problem(eq, 0.5, n, d)
     log("rank-%d preconditioner %s d=%d n=%d prec=%d" % (r, p.name, d, n, prec))
-    op, pre, (eo, ep) = _build(ctx, p, prec, pre_terms=36, pre_rank=r)
+    # values are compared whatever their sign: an indefinite rank-r approximation (TP_EINDEF) is
+    # still the oracle's truncated HOSVD, and its reported flag must agree with the grid's minimum
+    op, pre, (eo, ep) = _build(ctx, p, prec, pre_terms=36, pre_rank=r, allow_indefinite=True)
     idx = np.indices((n,) * d).reshape(d, -1).T.copy()
     got = pre.eval(idx).reshape((n,) * d)
     want = exact.precond_rank_r((n,) * d, r, p.alpha, p.c_neg, p.c_pos, p.c0, p.beta)
@@ -166,6 +168,8 @@ def test_rank_r_preconditioner_against_oracle(ctx, eq, d, n, r, prec):
     assert R == (r if d == 2 else r * r)
     assert e < (1e-6 if prec == 0 else 1e-5)
     assert ep <= lat * (1 + 1e-6) + 1e-12
+    if getattr(pre, "indefinite", False):
+        assert (got * (1.0 / P)).min() <= 0.0
 
 
 # ------------------------------------------------------------------ Sec. 6 iteration counts
@@ -257,7 +261,8 @@ def test_iteration_counts_2d_alpha_half_g4(ctx, n):
         paper = g["0.5"]["g_4"][r - 1][j]
         rows.append((r, count, paper, indef))
         if indef:
-            assert count is None or paper is None or count > paper, (r, count, paper)
+            # an indefinite preconditioner may still converge (r = 3 at n + 1 = 256: 22 iterations
+            # where the paper prints 99), but the entry is not the paper's construction
             not_reproduced.append(r)
         elif paper is not None and count is None:
             not_reproduced.append(r)
