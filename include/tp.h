@@ -232,6 +232,23 @@ tp_status tp_truncate(tp_ctx* ctx, int32_t count, const double* coef,
  * cores; out is host. */
 tp_status tp_inner(tp_ctx* ctx, const tp_tensor* x, const tp_tensor* y, double* out);
 
+/* For callers that cannot allocate device memory or wait on the host (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): <x, y> as tp_inner computes it
+ * (same kernels, same arguments), with every temporary (factor Gram matrices, FP64 cores,
+ * contraction intermediates, partial sums) in a fixed device array of TP_NOALLOC_SCRATCH_BYTES per
+ * GPU, allocated when the library is loaded and held until the process ends, and the result
+ * written to out_dev (device, one double) without synchronising the stream.  The call allocates
+ * nothing, waits for nothing and records no event.
+ * Limit: the temporaries of x and y must fit the array: 8 bytes times (sum_l rank_x[l] rank_y[l] +
+ * prod rank_y + 2 prod rank_x + rank_x[0] rank_y[1] rank_y[2] + rank_x[0] rank_x[1] rank_y[2] + 257),
+ * each term rounded up to 256 bytes (every 3D pair with ranks <= 64 fits); beyond it the call returns
+ * TP_EINVAL before enqueuing anything.  Every call on one GPU shares that GPU's array and it keeps
+ * the last call's contents (every temporary is written before it is read): calls that overlap on one
+ * GPU (several streams or threads, or contexts on the same device) race and must be serialised by
+ * the caller. */
+#define TP_NOALLOC_SCRATCH_BYTES (16u << 20)
+tp_status tp_inner_noalloc(tp_ctx* ctx, const tp_tensor* x, const tp_tensor* y, double* out_dev);
+
 /* Values of x on the sub-grid rows[0] x rows[1] (x rows[2]) (device int32 arrays
  * of m[l] 0-based indices) into out (device, m[0]*m[1]*m[2] doubles, column-major).
  * An index outside [0, n[l]) gives NaN in the points it enters. */

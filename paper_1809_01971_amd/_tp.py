@@ -74,6 +74,7 @@ _SIGS = {
     "tp_truncate": ([P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.POINTER(tp_tensor)),
                      C.POINTER(tp_tensor), C.c_double, C.c_int32], C.c_int),
     "tp_inner": ([P, C.POINTER(tp_tensor), C.POINTER(tp_tensor), C.POINTER(C.c_double)], C.c_int),
+    "tp_inner_noalloc": ([P, C.POINTER(tp_tensor), C.POINTER(tp_tensor), P], C.c_int),
     "tp_inner_sym": ([P, C.POINTER(tp_tensor), P, C.POINTER(tp_tensor), C.POINTER(C.c_double)], C.c_int),
     "tp_apply_sum": ([P, C.c_int32, C.POINTER(P), C.POINTER(C.POINTER(tp_tensor)), C.POINTER(C.c_double),
                       C.POINTER(tp_tensor), C.c_double, C.c_int32, C.POINTER(tp_sketch)], C.c_int),
@@ -301,6 +302,14 @@ class Context:
         out = C.c_double()
         _check(self.lib.tp_inner(self.h, C.byref(x.s), C.byref(y.s), C.byref(out)))
         return out.value
+
+    def inner_noalloc(self, x, y, out=None):
+        """tp_inner_noalloc: <x, y> into a device double (a 1-element float64 CUDA tensor, returned)."""
+        t = _torch()
+        if out is None:
+            out = t.empty(1, dtype=t.float64, device="cuda")
+        _check(self.lib.tp_inner_noalloc(self.h, C.byref(x.s), C.byref(y.s), P(out.data_ptr())))
+        return out
 
     def eval_grid(self, x, rows):
         t = _torch()

@@ -14,6 +14,7 @@
 #include <atomic>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <thread>
 #include <string>
 #include <vector>
@@ -56,8 +57,17 @@ constexpr int kMaxSketch = 192; // sketch width
 
 }  // namespace
 
+// ------------------------------------------------------------------------------ no-allocation scratch
+// Temporaries of tp_inner_noalloc live in this fixed array: one copy per GPU the library runs on,
+// held until the process ends.  Host code never passes the array's name to a kernel (on the host it
+// is only a stand-in symbol); it uses the device address that hipGetSymbolAddress returned for the
+// current device, recorded once per device by tp_create.
+constexpr size_t kNoAllocScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
 struct tp_ctx {
   int device = 0;
+  char* scratch = nullptr;       // device address of `scratch` on this context's device
   hipStream_t stream = nullptr;
   char* ws = nullptr;
   size_t ws_size = 0, ws_top = 0;
@@ -1204,10 +1214,17 @@ tp_status unit_symbol(tp_ctx* c, int n, const T** f, const double** w) {
 }
 
 // ------------------------------------------------------------------------------ inner product
+// out is host memory (the stream is synchronised), or device memory when dev_out is set (nothing
+// waits: the result is ready when the stream reaches it).
 template <typename T>
-tp_status inner_impl(tp_ctx* c, const tp_tensor* x, const tp_tensor* y, double* out) {
+tp_status inner_impl(tp_ctx* c, const tp_tensor* x, const tp_tensor* y, double* out, bool dev_out = false) {
   WsScope scope(c);
-  if (is_zero(x) || is_zero(y)) { *out = 0.0; return TP_OK; }
+  if (is_zero(x) || is_zero(y)) {
+    if (!dev_out) { *out = 0.0; return TP_OK; }
+    // an empty dot product writes 0 with one kernel (no memset node for graph capture)
+    HIPCHK(dot<double>(nullptr, nullptr, 0, out, nullptr, c->stream));
+    return TP_OK;
+  }
   const int d = x->d;
   double* G[3];
   int px[3] = {1, 1, 1}, ry[3] = {1, 1, 1};
@@ -1231,6 +1248,10 @@ tp_status inner_impl(tp_ctx* c, const tp_tensor* x, const tp_tensor* y, double* 
   int lda[3] = {px[0], px[1], px[2]};
   bool tA[3] = {false, false, false};
   TPCHK(tucker_contract(c, d, ry, Cy, A, lda, tA, px, 1.0, 0.0, Z));
+  if (dev_out) {
+    HIPCHK(dot<double>(Cx, Z, (long)cx, out, res + 1, c->stream));
+    return TP_OK;
+  }
   // the sum lands in mapped host memory: no copy command, only the synchronisation
   HIPCHK(dot<double>(Cx, Z, (long)cx, c->dmap, res + 1, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
@@ -1238,6 +1259,28 @@ tp_status inner_impl(tp_ctx* c, const tp_tensor* x, const tp_tensor* y, double* 
   return TP_OK;
 }
 
+// Bytes of workspace that inner_impl takes for x and y (3D or 2D), apart from the split-K partial
+// sums of its contractions, which are only used when they fit.
+size_t ws_bytes(size_t count, size_t elem) {
+  size_t b = ((count * elem) + 255) & ~size_t(255);
+  return b ? b : 256;
+}
+size_t inner_ws_bytes(const tp_tensor* x, const tp_tensor* y) {
+  if (is_zero(x) || is_zero(y)) return 0;
+  const int d = x->d;
+  size_t px[3] = {1, 1, 1}, ry[3] = {1, 1, 1};
+  size_t b = 0;
+  for (int m = 0; m < d; ++m) {
+    px[m] = (size_t)x->rank[m];
+    ry[m] = (size_t)y->rank[m];
+    b += ws_bytes(px[m] * ry[m], 8);
+  }
+  const size_t cy = ry[0] * ry[1] * ry[2], cx = px[0] * px[1] * px[2];
+  b += ws_bytes(cy, 8) + 2 * ws_bytes(cx, 8) + ws_bytes(257, 8);
+  if (d == 3) b += ws_bytes(px[0] * ry[1] * ry[2], 8) + ws_bytes(px[0] * px[1] * ry[2], 8);
+  else b += ws_bytes(px[0] * ry[1], 8);
+  return b;
+}
 
 // ------------------------------------------------------------------------------ CP -> Tucker
 template <typename T>
@@ -1650,6 +1693,24 @@ tp_status tp_create(int device, void* stream, size_t workspace_bytes, tp_ctx** o
   HIPCHK(hipHostMalloc(&c->host, sizeof(double) * tp_ctx::kHost, hipHostMallocDefault));
   HIPCHK(hipHostMalloc(&c->hmap, sizeof(double) * tp_ctx::kMap, hipHostMallocMapped | hipHostMallocCoherent));
   HIPCHK(hipHostGetDevicePointer((void**)&c->dmap, c->hmap, 0));
+  {
+    // address of the no-allocation scratch on this device (the device is current), looked up once
+    // per device and shared by every context on it
+    static std::mutex mu;
+    static std::map<int, char*> addr;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = addr.find(device);
+    if (it == addr.end()) {
+      void* p = nullptr;
+      hipError_t se = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (se != hipSuccess || !p) {
+        tp_destroy(c);
+        return fail(TP_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", device, hipGetErrorString(se));
+      }
+      it = addr.emplace(device, (char*)p).first;
+    }
+    c->scratch = it->second;
+  }
   *out = c;
   return TP_OK;
 }
@@ -2111,6 +2172,30 @@ tp_status tp_inner(tp_ctx* c, const tp_tensor* x, const tp_tensor* y, double* ou
   TPCHK(check_tensor(y, "y", true));
   if (!same_shape(x, y)) return fail(TP_EINVAL, "x and y differ in shape or precision");
   return x->prec == TP_FP64 ? inner_impl<double>(c, x, y, out) : inner_impl<float>(c, x, y, out);
+}
+
+tp_status tp_inner_noalloc(tp_ctx* c, const tp_tensor* x, const tp_tensor* y, double* out_dev) {
+  if (!c || !x || !y || !out_dev) return fail(TP_EINVAL, "NULL argument");
+  TPCHK(check_tensor(x, "x", true));
+  TPCHK(check_tensor(y, "y", true));
+  if (!same_shape(x, y)) return fail(TP_EINVAL, "x and y differ in shape or precision");
+  const size_t need = inner_ws_bytes(x, y);
+  if (need > kNoAllocScratchBytes)
+    return fail(TP_EINVAL, "tp_inner_noalloc: ranks (%d,%d,%d) x (%d,%d,%d) need %zu bytes of scratch, more than its %zu",
+                x->rank[0], x->rank[1], x->d == 3 ? x->rank[2] : 1, y->rank[0], y->rank[1],
+                y->d == 3 ? y->rank[2] : 1, need, kNoAllocScratchBytes);
+  if (!c->scratch) return fail(TP_EHIP, "no scratch address for device %d", c->device);
+  // the same kernels as tp_inner, with the context's workspace replaced by the scratch for the call
+  // (profiling events are not recorded: creating them could allocate)
+  struct Swap {
+    tp_ctx* c;
+    char* ws; size_t size, top, peak; bool prof;
+    explicit Swap(tp_ctx* cc) : c(cc), ws(cc->ws), size(cc->ws_size), top(cc->ws_top), peak(cc->ws_peak), prof(cc->prof) {
+      c->ws = c->scratch; c->ws_size = kNoAllocScratchBytes; c->ws_top = 0; c->prof = false;
+    }
+    ~Swap() { c->ws = ws; c->ws_size = size; c->ws_top = top; c->ws_peak = peak; c->prof = prof; }
+  } swap(c);
+  return x->prec == TP_FP64 ? inner_impl<double>(c, x, y, out_dev, true) : inner_impl<float>(c, x, y, out_dev, true);
 }
 
 tp_status tp_eval_grid(tp_ctx* c, const tp_tensor* x, const int32_t* const* rows, const int32_t* mm_, double* out) {
