@@ -58,6 +58,7 @@ CLASSES = {
     "syev": ("k_syev", "alu", PEAK["fp64_tflops"], "TFLOP/s"),
     "chol": ("k_pchol", "alu", PEAK["fp64_tflops"], "TFLOP/s"),
     "psd_eig": ("k_psd_eig", "alu", PEAK["fp64_tflops"], "TFLOP/s"),
+    "psd_tri": ("k_psd_tri", "alu", PEAK["fp64_tflops"], "TFLOP/s"),
     "ns_isqrt": ("k_ns_isqrt", "alu", PEAK["fp64_tflops"], "TFLOP/s"),
 }
 

@@ -348,6 +348,19 @@ tp_status tp_dst(tp_ctx* ctx, int32_t n, int32_t cols, int32_t prec, const void*
  * count*K), eigenvectors into v (device, count*K*K).  K <= 256. */
 tp_status tp_syev(tp_ctx* ctx, int32_t K, int32_t count, const double* a, double* w, double* v);
 
+/* Eigenpairs of `count` (<= 24) positive semidefinite K x K matrices g (device, count*K*K,
+ * column-major, FP64) by the solvers of the truncations (Sec. 5, the HOSVD's side-matrix
+ * decompositions): eigenvalues descending into w (device, count*K, zero past the rank),
+ * eigenvectors into v (device, count*K*K, zero columns past the rank), ranks into rank (host,
+ * count) and the eigenvalue mass not represented into rest (host, count, may be NULL).
+ * cut = 0: pivoted Cholesky, then one-sided Jacobi (rank = the Cholesky's numerical rank, rest =
+ * the trace it left).  cut >= 1e-13 with K <= 64: reduction to tridiagonal form, eigenvalues by
+ * multisection, eigenvectors by twisted factorisations; eigenpairs with eigenvalue <= cut * trace
+ * are dropped (rank = the number kept, rest = their sum); a matrix whose kept eigenvectors are not
+ * orthogonal to 1e-10 (clustered eigenvalues) is solved by the Jacobi path instead.  K <= 256. */
+tp_status tp_gram_eig(tp_ctx* ctx, int32_t K, int32_t count, const double* g, double* w, double* v,
+                      double cut, int32_t* rank, double* rest);
+
 /* 1D eigenvalues lambda_k = (4/h^2) sin^2(pi k h/2), h = 1/(n+1), into out
  * (device, n doubles). */
 tp_status tp_lambda(tp_ctx* ctx, int32_t n, double* out);
@@ -369,7 +382,8 @@ typedef enum {
   TP_PROF_CHOL = 7,          /* k_pchol: pivoted Cholesky of Gram matrices (orthonormal bases) */
   TP_PROF_PSD_EIG = 8,       /* k_psd_eig: Gram eigensolver (HOSVD ranks and bases, fit normal equations) */
   TP_PROF_NS = 9,            /* k_ns_isqrt: Newton-Schulz inverse square root (second orthonormalisation) */
-  TP_PROF_GEMM_REDUCE = 10   /* k_gemm_reduce: split-K partial sums of the contractions (all types) */
+  TP_PROF_GEMM_REDUCE = 10,  /* k_gemm_reduce: split-K partial sums of the contractions (all types) */
+  TP_PROF_PSD_TRI = 11       /* k_psd_tri: Gram eigensolver by tridiagonal reduction (HOSVD ranks and bases) */
 } tp_prof_class;
 
 /* Contraction kernels: mfma != 0 (default) uses the FP32/FP64 matrix-core tiles, 0 the FMA

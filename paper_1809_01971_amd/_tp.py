@@ -90,6 +90,8 @@ _SIGS = {
                               C.c_size_t], C.c_int),
     "tp_syev": ([P, C.c_int32, C.c_int32, P, P, P], C.c_int),
     "tp_lambda": ([P, C.c_int32, P], C.c_int),
+    "tp_gram_eig": ([P, C.c_int32, C.c_int32, P, P, P, C.c_double, C.POINTER(C.c_int32), C.POINTER(C.c_double)],
+                    C.c_int),
     "tp_profile": ([P, C.c_int32], C.c_int),
     "tp_gemm_mode": ([C.c_int32], C.c_int),
     "tp_profile_read": ([P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
@@ -97,7 +99,7 @@ _SIGS = {
 }
 
 PROF_CLASSES = ["gemm_f64", "gemm_f32", "gemm_f32_f64", "gemm_f64_f32", "dst_f64", "dst_f32", "syev", "chol",
-                "psd_eig", "ns_isqrt", "gemm_reduce"]
+                "psd_eig", "ns_isqrt", "gemm_reduce", "psd_tri"]
 
 
 def load_library():
@@ -172,6 +174,20 @@ class Context:
         out_t = t.empty_like(xc) if out is None else out
         _check(self.lib.tp_dst(self.h, n, cols, prec, P(xc.data_ptr()), P(out_t.data_ptr())))
         return out_t.t() if x.dim() == 2 else out_t
+
+    def gram_eig(self, a, cut=0.0):
+        """a: (count, K, K) float64 CUDA tensor of positive semidefinite matrices -> (w, v, ranks, rest):
+        w (count, K) descending, v (count, K, K) with v[b][:, i] the i-th eigenvector (column-major
+        rows of the torch tensor are columns), ranks and rest as lists."""
+        t = _torch()
+        a = a.contiguous()
+        cnt, K, _ = a.shape
+        w = t.empty((cnt, K), dtype=t.float64, device=a.device)
+        v = t.empty((cnt, K, K), dtype=t.float64, device=a.device)
+        rk = (C.c_int32 * cnt)()
+        rs = (C.c_double * cnt)()
+        _check(self.lib.tp_gram_eig(self.h, K, cnt, P(a.data_ptr()), P(w.data_ptr()), P(v.data_ptr()), cut, rk, rs))
+        return w, v, list(rk), list(rs)
 
     def syev(self, a):
         """a: (count, K, K) float64 CUDA tensor of symmetric matrices."""

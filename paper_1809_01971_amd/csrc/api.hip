@@ -148,7 +148,7 @@ struct WsScope {
 // Kernel classes reported by tp_profile_read.
 // One class per kernel (template instantiations of the contraction count apart), whoever calls it.
 enum { PC_GEMM_F64 = 0, PC_GEMM_F32 = 1, PC_GEMM_F32_F64 = 2, PC_GEMM_F64_F32 = 3, PC_DST_F64 = 4, PC_DST_F32 = 5,
-       PC_SYEV = 6, PC_CHOL = 7, PC_PSD_EIG = 8, PC_NS = 9, PC_GEMM_REDUCE = 10, PC_COUNT = 11 };
+       PC_SYEV = 6, PC_CHOL = 7, PC_PSD_EIG = 8, PC_NS = 9, PC_GEMM_REDUCE = 10, PC_PSD_TRI = 11, PC_COUNT = 12 };
 
 tp_status prof_begin(tp_ctx* c, size_t* e0) {
   if (!c->prof) return TP_OK;
@@ -463,8 +463,14 @@ tp_status ns_isqrt(tp_ctx* c, int cnt, const int* K, const double* const* G, dou
 // eigenvectors to V (device), eigenvalues (descending) on the host in host_w, numerical ranks in
 // q, and the trace the Cholesky left unresolved in rest (it belongs to the discarded tail).  The
 // kernel writes eigenvalues, ranks and traces straight into mapped host memory.
+// cut > 0 (relative to the trace, at least kTriCutMin): eigenpairs with eigenvalue <= cut * trace(G)
+// are not needed, which lets matrices of order <= kTriMax go to the tridiagonal solver; a matrix
+// whose kept eigenvectors it cannot certify orthogonal (clustered eigenvalues) is redone by the
+// Jacobi solver.
+constexpr double kTriCutMin = 1e-13;
+constexpr double kTriOrthTol = 1e-10;
 tp_status psd_eig(tp_ctx* c, int cnt, const int* K, const double* const* G, double* const* V, double jtol,
-                  std::vector<std::vector<double>>* host_w, int* q, double* rest) {
+                  std::vector<std::vector<double>>* host_w, int* q, double* rest, double cut = 0.0) {
   if (cnt > kBatchJobs) return fail(TP_EINVAL, "too many eigen jobs");
   int Kmax = 0;
   size_t tot = 0;
@@ -491,19 +497,48 @@ tp_status psd_eig(tp_ctx* c, int cnt, const int* K, const double* const* G, doub
                      work ? work + (size_t)2 * Kmax * Kmax * i : nullptr, 1e-16, jtol};
     off += K[i];
   }
-  size_t e0 = 0;
-  TPCHK(prof_begin(c, &e0));
-  HIPCHK(psd_eig_batched(jb, cnt, Kmax, c->stream));
-  {
-    // algorithmic work: that of a symmetric eigendecomposition with vectors, about 9 K^3 flops
-    // (tridiagonal reduction, implicit QR, back transformation); bytes: G in, V and w out
-    double fl = 0, by = 0;
-    for (int i = 0; i < cnt; ++i) { fl += 9.0 * K[i] * K[i] * K[i]; by += 8.0 * (2.0 * K[i] * K[i] + K[i]); }
-    TPCHK(prof_end(c, PC_PSD_EIG, e0, fl, by));
+  // algorithmic work: that of a symmetric eigendecomposition with vectors, about 9 K^3 flops
+  // (tridiagonal reduction, eigenvalues, back transformation); bytes: G in, V and w out
+  auto work_of = [&](const std::vector<int>& idx, double* fl, double* by) {
+    *fl = *by = 0;
+    for (int i : idx) { *fl += 9.0 * K[i] * K[i] * K[i]; *by += 8.0 * (2.0 * K[i] * K[i] + K[i]); }
+  };
+  std::vector<int> jacobi;
+  const int* hq = reinterpret_cast<const int*>(c->hmap + tot + cnt);
+  if (cut >= kTriCutMin && Kmax <= kTriMax) {
+    JobBatch<PsdJob> jt = jb;
+    for (int i = 0; i < cnt; ++i) { jt.j[i].ctol = cut; jt.j[i].jtol = kTriOrthTol; jt.j[i].work = nullptr; }
+    size_t e0 = 0;
+    TPCHK(prof_begin(c, &e0));
+    HIPCHK(psd_tri_batched(jt, cnt, Kmax, c->stream));
+    std::vector<int> all(cnt);
+    for (int i = 0; i < cnt; ++i) all[i] = i;
+    double fl, by;
+    work_of(all, &fl, &by);
+    TPCHK(prof_end(c, PC_PSD_TRI, e0, fl, by));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int i = 0; i < cnt; ++i)
+      if (hq[i] < 0) jacobi.push_back(i);
+  } else {
+    for (int i = 0; i < cnt; ++i) jacobi.push_back(i);
   }
-  HIPCHK(hipStreamSynchronize(c->stream));
+  if (!jacobi.empty()) {
+    JobBatch<PsdJob> jj;
+    int kmj = 0;
+    for (size_t t = 0; t < jacobi.size(); ++t) {
+      jj.j[t] = jb.j[jacobi[t]];
+      if (work) jj.j[t].work = work + (size_t)2 * Kmax * Kmax * t;
+      kmj = std::max(kmj, K[jacobi[t]]);
+    }
+    size_t e0 = 0;
+    TPCHK(prof_begin(c, &e0));
+    HIPCHK(psd_eig_batched(jj, (int)jacobi.size(), kmj, c->stream));
+    double fl, by;
+    work_of(jacobi, &fl, &by);
+    TPCHK(prof_end(c, PC_PSD_EIG, e0, fl, by));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  }
   const double* hres = c->hmap + tot;
-  const int* hq = reinterpret_cast<const int*>(hres + cnt);
   off = 0;
   for (int i = 0; i < cnt; ++i) {
     rest[i] = hres[i];
@@ -660,7 +695,11 @@ tp_status hosvd(tp_ctx* c, int d, const int* q, const T* M, double tol, int cap,
   // Jacobi rotations stop once every column pair is orthogonal to 1e-2 tol relative: that
   // resolves every eigenvalue to 1e-2 tol of itself (the rank rule needs far less) and moves the
   // kept subspace, hence the truncation error, by about 1e-2 tol ||M||.
-  TPCHK(psd_eig(c, d, q, Ap, E, std::max(1e-14, 1e-2 * tol), &hw, qr, rest));
+  // eigenvalues below tol^2 trace / (2 d K) may be dropped: together they stay under half of the
+  // rank rule's threshold tol^2 ||M||^2 / d
+  int qmax = 1;
+  for (int m = 0; m < d; ++m) qmax = std::max(qmax, q[m]);
+  TPCHK(psd_eig(c, d, q, Ap, E, std::max(1e-14, 1e-2 * tol), &hw, qr, rest, tol * tol / (2.0 * d * qmax)));
   *capped = false;
   for (int m = 0; m < d; ++m) {
     double tot = rest[m];
@@ -1754,6 +1793,35 @@ tp_status tp_profile_read(tp_ctx* c, int32_t cls, double* ms, double* launches, 
   if (launches) *launches = c->prof_n[cls];
   if (flops) *flops = c->prof_flops[cls];
   if (bytes) *bytes = c->prof_bytes[cls];
+  return TP_OK;
+}
+
+tp_status tp_gram_eig(tp_ctx* c, int32_t K, int32_t count, const double* g, double* w, double* v, double cut,
+                      int32_t* rank, double* rest) {
+  if (!c || !g || !w || !v || !rank) return fail(TP_EINVAL, "NULL argument");
+  if (K < 1 || K > kMaxRank) return fail(TP_EINVAL, "K=%d outside [1,%d]", K, kMaxRank);
+  if (count < 1 || count > kBatchJobs) return fail(TP_EINVAL, "count=%d outside [1,%d]", count, kBatchJobs);
+  if (cut != 0.0 && !(cut >= kTriCutMin)) return fail(TP_EINVAL, "cut=%g must be 0 or >= %g", cut, kTriCutMin);
+  if (cut != 0.0 && K > kTriMax) return fail(TP_EINVAL, "cut > 0 needs K <= %d", kTriMax);
+  WsScope scope(c);
+  std::vector<int> Ks(count, K);
+  std::vector<const double*> G(count);
+  std::vector<double*> V(count);
+  for (int i = 0; i < count; ++i) {
+    G[i] = g + (size_t)K * K * i;
+    V[i] = v + (size_t)K * K * i;
+  }
+  std::vector<std::vector<double>> hw;
+  std::vector<int> q(count);
+  std::vector<double> rs(count);
+  TPCHK(psd_eig(c, count, Ks.data(), G.data(), V.data(), 1e-14, &hw, q.data(), rs.data(), cut));
+  for (int i = 0; i < count; ++i) {
+    std::memcpy(c->host + (size_t)K * i, hw[i].data(), sizeof(double) * K);
+    rank[i] = q[i];
+    if (rest) rest[i] = rs[i];
+  }
+  HIPCHK(hipMemcpyAsync(w, c->host, sizeof(double) * K * count, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
   return TP_OK;
 }
 

@@ -1431,6 +1431,445 @@ hipError_t psd_eig_batched(const JobBatch<PsdJob>& jobs_dev, int count, int Kmax
   return launch_gram<false, 1024>(k_psd_eig<false, 1024>, jobs_dev, count, extra, s);
 }
 
+// ---------------------------------------------------------------------------------------------
+// Gram eigenpairs by reduction to tridiagonal form, K <= kTriMax, one workgroup of 512 threads
+// (8 waves) per matrix, in registers and LDS:
+//  1. Householder reduction G = Q T Q^T with Q accumulated.  Thread (l, c) = (tid % 64, tid / 64)
+//     holds row l, columns = c (mod 8), of A and of Q in registers; every wave forms the reflector
+//     from the published row by itself, and two barriers per step separate the products B v, Q v
+//     from the rank-2 and rank-1 updates.
+//  2. T + sigma I = L D L^T with every pivot positive (sigma = 0, or a multiple of eps ||T|| when
+//     rounding left T without a positive definite factorisation): a representation that fixes
+//     its eigenvalues to high relative accuracy.
+//  3. Eigenvalue i by multisection: four lanes per eigenvalue with two points each (nine
+//     subintervals per step, geometric while the interval spans more than a factor two), every
+//     point counted by the stationary qd transform L D L^T - x I = L+ D+ L+^T (the number of
+//     negative D+), down to a relative width of 2^-46.
+//  4. Eigenvector i (lane i of wave 0) from the twisted factorisation at its eigenvalue: the
+//     stationary transform from the top and the progressive one from the bottom meet at the index
+//     r of smallest |gamma_r|; z_r = 1 and the multipliers of the two factorisations give the rest.
+//     For a positive definite L D L^T these vectors are accurate to about eps / (relative gap).
+//  5. Check |Z^T Z - I| over the kept eigenvectors (eigenvalue > ctol * trace) where the theory
+//     does not already bound it (eigenvalues within 1 % of each other, and every norm): above jtol
+//     (clustered eigenvalues) the job reports q = -1 and writes nothing else.
+//  6. V = Q Z, kept eigenvectors in descending order of eigenvalue, zero columns after them.
+// ---------------------------------------------------------------------------------------------
+constexpr int TRI_NT = 512;                  // 8 waves: column classes of the reduction
+constexpr int TRI_NW = TRI_NT / 64;
+constexpr int TRI_CPT = kTriMax / TRI_NW;    // columns of A and Q per thread
+constexpr int TRI_LD = kTriMax + 1;   // odd leading dimension: the rows of a column sit in distinct banks
+constexpr double kTiny = 2.2250738585072014e-308;
+
+// Sum / maximum over the 64 lanes (DPP within rows of 16, then the four row results read into
+// scalars); every lane receives the result, and the order of the additions is fixed.
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)b, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double wave_sum_f64(double v) {
+  v = group_sum(v, 16);
+  return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+__device__ __forceinline__ double wave_max_f64(double v) {
+  v = fmax(v, dpp_f64<0xB1>(v));
+  v = fmax(v, dpp_f64<0x4E>(v));
+  v = fmax(v, dpp_f64<0x141>(v));
+  v = fmax(v, dpp_f64<0x140>(v));
+  return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)), fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
+}
+// Minimum over the four lanes of a quad (DPP quad permutations).
+__device__ __forceinline__ int quad_min(int v) {
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false));
+  return min(v, __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false));
+}
+// 1/p from the hardware reciprocal and one Newton step (a few ulps).
+__device__ __forceinline__ double recip(double p) {
+  const double r = __builtin_amdgcn_rcp(p);
+  return r * fma(-p, r, 2.0);
+}
+
+// Orders this wave's LDS writes before its later LDS reads of other lanes' entries.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Negative pivots of L D L^T - x I at two points at once (independent chains): the stationary qd
+// transform D+_k = D_k + s_k, s_{k+1} = (s_k / D+_k) D_k L_k^2 - x, the quotient from the refined
+// hardware reciprocal (an error of a few ulps in it is a perturbation of the representation of that
+// relative size).  The loop carries no guard; a zero pivot or an overflow ends in a non-finite s, and
+// that chain is counted again with a zero pivot taken as the smallest negative number and a
+// quotient inf / inf as 1.
+__device__ __forceinline__ int sturm_guarded(const double* D, const double* DL2, int K, double x) {
+  double s = -x;
+  int n = 0;
+  for (int k = 0; k + 1 < K; ++k) {
+    double p = D[k] + s;
+    if (p == 0.0) p = -kTiny;
+    n += p < 0.0 ? 1 : 0;
+    double t = s * recip(p);
+    if (t != t) t = 1.0;
+    s = t * DL2[k] - x;
+  }
+  return n + ((D[K - 1] + s) < 0.0 ? 1 : 0);
+}
+__device__ __forceinline__ void sturm2(const double* D, const double* DL2, int K, double x0, double x1, int& c0,
+                                       int& c1) {
+  double s0 = -x0, s1 = -x1;
+  int n0 = 0, n1 = 0;
+#pragma unroll 8
+  for (int k = 0; k + 1 < K; ++k) {
+    const double dk = D[k], dl = DL2[k];
+    const double p0 = dk + s0, p1 = dk + s1;
+    n0 += p0 < 0.0 ? 1 : 0;
+    n1 += p1 < 0.0 ? 1 : 0;
+    s0 = (s0 * recip(p0)) * dl - x0;
+    s1 = (s1 * recip(p1)) * dl - x1;
+  }
+  c0 = n0 + ((D[K - 1] + s0) < 0.0 ? 1 : 0);
+  c1 = n1 + ((D[K - 1] + s1) < 0.0 ? 1 : 0);
+  if (!isfinite(s0)) c0 = sturm_guarded(D, DL2, K, x0);
+  if (!isfinite(s1)) c1 = sturm_guarded(D, DL2, K, x1);
+}
+
+// Point k (0..TRI_SEC) of the multisection of [a, b] into TRI_SEC parts: geometric while
+// b > 2a > 0, else equidistant.
+constexpr int TRI_SEC = 9;
+__device__ __forceinline__ double tri_split(double a, double b, int k) {
+  if (k <= 0) return a;
+  if (k >= TRI_SEC) return b;
+  if (a > 0.0 && b > 2.0 * a) {
+    const double la = log2(a), lb = log2(b);
+    return exp2(la + (lb - la) * (k * (1.0 / TRI_SEC)));
+  }
+  return a + (b - a) * (k * (1.0 / TRI_SEC));
+}
+
+// C (K x K) = X^T Y or X Y over LDS operands with leading dimension TRI_LD, 4 x 4 outputs per
+// thread (rows 4 (tid % 16) .., columns 4 (tid / 16) ..).  TX: X is read transposed (X^T Y).
+template <bool TX>
+__device__ __forceinline__ void tri_mm44(const double* X, const double* Y, int K, double acc[4][4]) {
+  const int r0 = 4 * (threadIdx.x % 16), c0 = 4 * (threadIdx.x / 16);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  for (int k = 0; k < K; ++k) {
+    double x[4], y[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int r = min(r0 + a, K - 1);
+      x[a] = TX ? X[k + TRI_LD * r] : X[r + TRI_LD * k];
+      y[a] = Y[k + TRI_LD * min(c0 + a, K - 1)];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] += x[a] * y[b];
+  }
+}
+
+__global__ __launch_bounds__(TRI_NT) void k_psd_tri(JobBatch<PsdJob> jobs) {
+  extern __shared__ double sm[];
+  const PsdJob J = jobs.j[blockIdx.x];
+  const int K = J.K;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (K <= 0) {
+    if (tid == 0) { *J.q = 0; *J.rest = 0.0; }
+    return;
+  }
+  double* A = sm;                          // Z (eigenvectors of T)
+  double* Q = A + kTriMax * TRI_LD;        // K x K: the accumulated reflections, after the reduction
+  double* Lp = Q + kTriMax * TRI_LD;       // [k][lane]: multipliers of the eigenvector phase
+  double* Um = Lp + kTriMax * 64;
+  double* dv = Um + kTriMax * 64;          // diagonal of T
+  double* ev = dv + kTriMax;               // off-diagonal of T
+  double* D = ev + kTriMax;                // T + sigma I = L D L^T
+  double* L = D + kTriMax;
+  double* DL2 = L + kTriMax;               // D_k L_k^2
+  double* lam = DL2 + kTriMax;             // eigenvalues of T + sigma I, ascending
+  double* vw = lam + kTriMax;              // per-wave copies of the reflector v (by absolute index), 8 x 64
+  double* ww = vw + TRI_NW * 64;           // per-wave copies of w, 8 x 64
+  double* pw = ww + TRI_NW * 64;           // partial B v per column class, 8 x 64
+  double* qw = pw + TRI_NW * 64;           // partial Q v per column class, 8 x 64
+  double* xb = qw + TRI_NW * 64;           // the row of A that the next reflection starts from, 64
+  double* red = xb + 64;                   // 16 scalars
+  // ---- 1. Householder reduction.  Thread (l, w) keeps A[l][w + 8t] and Q[l][w + 8t], t < 8, in
+  // registers; the reflector of step j comes from row j (= column j), which the owners of that row
+  // publish in xb at the end of the previous step.
+  double ar[TRI_CPT], qr[TRI_CPT];
+#pragma unroll
+  for (int t = 0; t < TRI_CPT; ++t) {
+    const int k = wave + TRI_NW * t;
+    ar[t] = (lane < K && k < K) ? J.g[lane + (long)K * k] : 0.0;
+    qr[t] = (lane == k && k < K) ? 1.0 : 0.0;
+  }
+  if (lane == 0)
+#pragma unroll
+    for (int t = 0; t < TRI_CPT; ++t)
+      if (wave + TRI_NW * t < K) xb[wave + TRI_NW * t] = ar[t];
+  __syncthreads();
+  for (int j = 0; j + 2 < K; ++j) {
+    const int o = j + 1;
+    const double xl = (lane >= o && lane < K) ? xb[lane] : 0.0;   // A[l][j], l > j
+    const double a2 = wave_sum_f64(xl * xl);
+    const double x0 = readlane_f64(xl, o);
+    const double al = sqrt(a2);
+    const double beta = x0 >= 0.0 ? -al : al;
+    const double tau = a2 > 0.0 ? 1.0 / (al * (al + fabs(x0))) : 0.0;
+    const double vl = lane == o ? x0 - beta : xl;                  // v by absolute index, zero above o
+    double* v = vw + 64 * wave;
+    double* w = ww + 64 * wave;
+    v[lane] = vl;
+    wave_lds_sync();
+    double pb = 0.0, pq = 0.0;
+#pragma unroll
+    for (int t = 0; t < TRI_CPT; ++t) {
+      const double vk = v[wave + TRI_NW * t];
+      pb += ar[t] * vk;
+      pq += qr[t] * vk;
+    }
+    pw[64 * wave + lane] = pb;
+    qw[64 * wave + lane] = pq;
+    if (tid == 0) {
+      dv[j] = xb[j];
+      ev[j] = a2 > 0.0 ? beta : x0;
+    }
+    __syncthreads();
+    // p = tau B v on the trailing rows, w = p - (tau/2)(p.v) v; every wave forms all of w
+    double sp = 0.0, sq = 0.0;
+#pragma unroll
+    for (int c = 0; c < TRI_NW; ++c) {
+      sp += pw[64 * c + lane];
+      sq += qw[64 * c + lane];
+    }
+    const double pl = lane >= o ? tau * sp : 0.0;
+    const double ql = tau * sq;
+    const double k2 = wave_sum_f64(pl * vl);
+    const double wl = pl - 0.5 * tau * k2 * vl;
+    w[lane] = wl;
+    wave_lds_sync();
+    // B -= v w^T + w v^T, Q -= (Q v) tau v^T: v and w vanish outside the trailing block
+#pragma unroll
+    for (int t = 0; t < TRI_CPT; ++t) {
+      const int k = wave + TRI_NW * t;
+      const double vk = v[k], wk = w[k];
+      ar[t] -= vl * wk + wl * vk;
+      qr[t] -= ql * vk;
+    }
+    if (lane == o)
+#pragma unroll
+      for (int t = 0; t < TRI_CPT; ++t)
+        if (wave + TRI_NW * t < K) xb[wave + TRI_NW * t] = ar[t];
+    __syncthreads();
+  }
+  // Q to LDS for the back transformation
+#pragma unroll
+  for (int t = 0; t < TRI_CPT; ++t)
+    if (lane < K && wave + TRI_NW * t < K) Q[lane + TRI_LD * (wave + TRI_NW * t)] = qr[t];
+  // ---- 2. the last 2 x 2 block (row K-2 is in xb; A[K-1][K-1] is in its owner's registers), then
+  // L D L^T of T + sigma I (one thread)
+  if (lane == K - 1)
+#pragma unroll
+    for (int t = 0; t < TRI_CPT; ++t)
+      if (wave + TRI_NW * t == K - 1) red[4] = ar[t];
+  __syncthreads();
+  if (wave == 0) {
+    // lane i holds d_i and e_i; the factorisation runs through them with readlane / writelane
+    double di = lane < K - 2 ? dv[lane] : 0.0;
+    double ei = lane < K - 2 ? ev[lane] : 0.0;
+    if (K >= 2) {
+      if (lane == K - 2) { di = xb[K - 2]; ei = xb[K - 1]; }
+      if (lane == K - 1) di = red[4];
+    } else if (lane == 0) {
+      di = xb[0];
+    }
+    const double eim1 = __shfl_up(ei, 1);
+    const double off = (lane > 0 ? fabs(eim1) : 0.0) + (lane + 1 < K ? fabs(ei) : 0.0);
+    const double tn = wave_max_f64(lane < K ? fabs(di) + off : 0.0);
+    const double tr = wave_sum_f64(lane < K ? di : 0.0);
+    double sigma = 0.0, Di = 0.0, Li = 0.0, DLi = 0.0;
+    bool ok = false;
+    for (int tries = 0; tries < 24 && !ok && tn > 0.0; ++tries) {
+      double dp = readlane_f64(di, 0) + sigma;
+      ok = dp > 0.0;
+      if (lane == 0) Di = dp;
+      for (int i = 0; i + 1 < K && ok; ++i) {
+        const double e = readlane_f64(ei, i);
+        const double li = e * recip(dp);
+        if (lane == i) { Li = li; DLi = e * li; }
+        dp = readlane_f64(di, i + 1) + sigma - li * e;
+        if (lane == i + 1) Di = dp;
+        ok = dp > 0.0;
+      }
+      if (!ok) sigma = sigma == 0.0 ? 2.220446049250313e-16 * tn : 4.0 * sigma;
+    }
+    if (lane < K) {
+      dv[lane] = di;
+      D[lane] = Di;
+      L[lane] = Li;
+      DL2[lane] = DLi;
+    }
+    if (lane == 0) {
+      red[0] = sigma;
+      red[1] = tn;
+      red[2] = tr;
+      red[3] = ok ? 1.0 : (tn > 0.0 ? -1.0 : 0.0);
+    }
+  }
+  __syncthreads();
+  const double sigma = red[0], tn = red[1], tr = red[2], st = red[3];
+  if (st <= 0.0) {
+    // zero matrix: no eigenpair kept; no positive definite shift found: let the caller decide
+    if (st == 0.0) {
+      for (int e = tid; e < K * K; e += TRI_NT) J.v[e] = 0.0;
+      for (int o = tid; o < K; o += TRI_NT) J.w[o] = 0.0;
+    }
+    if (tid == 0) {
+      *J.q = st == 0.0 ? 0 : -1;
+      if (st == 0.0) *J.rest = 0.0;
+    }
+    return;
+  }
+  // ---- 3. eigenvalues of T + sigma I by multisection (eigenvalue tid / 4, ascending): the four
+  // lanes of a quad count at the 8 interior points of TRI_SEC subintervals
+  {
+    const int i = tid >> 2, qd = tid & 3;
+    double a = (tn + sigma) * 0x1p-60, b = tn + sigma;
+    bool done = i >= K;   // the second half of the workgroup has no eigenvalue
+    if (!done) {
+      int c0, c1;
+      sturm2(D, DL2, K, a, a, c0, c1);
+      if (c0 > i) { b = a; a = 0.0; done = true; }   // below 2^-60 ||T||: zero for every use here
+    }
+    int iters = 0;
+    while (!done) {
+      const int k0 = 2 * qd + 1;
+      int c0, c1;
+      sturm2(D, DL2, K, tri_split(a, b, k0), tri_split(a, b, k0 + 1), c0, c1);
+      int kf = c0 > i ? k0 : (c1 > i ? k0 + 1 : TRI_SEC);
+      kf = quad_min(kf);
+      const double na = tri_split(a, b, kf - 1), nb = tri_split(a, b, kf);
+      a = na;
+      b = nb;
+      done = (b - a) <= 0x1p-46 * b || ++iters >= 64;
+    }
+    if (i < K && qd == 0) lam[i] = 0.5 * (a + b);
+  }
+  __syncthreads();
+  // ---- 4. eigenvectors by twisted factorisations (lane i of wave 0), Z in A
+  if (tid == 0) red[15] = 0.0;
+  if (wave == 0 && lane < K) {
+    const int i = lane;
+    const double lm = lam[i];
+    double* z = A + TRI_LD * i;
+    double s = -lm;
+#pragma unroll 8
+    for (int k = 0; k + 1 < K; ++k) {
+      z[k] = s;                                  // s_k, kept for gamma
+      double dp = D[k] + s;
+      if (dp == 0.0) dp = -kTiny;
+      const double lpk = D[k] * L[k] * recip(dp);
+      Lp[64 * k + i] = lpk;
+      s = lpk * L[k] * s - lm;
+    }
+    z[K - 1] = s;
+    double p = D[K - 1] - lm;
+    int r = K - 1;
+    double gmin = fabs(s + p + lm);
+#pragma unroll 8
+    for (int k = K - 2; k >= 0; --k) {
+      double dm = DL2[k] + p;
+      if (dm == 0.0) dm = -kTiny;
+      const double t = D[k] * recip(dm);
+      Um[64 * k + i] = L[k] * t;
+      p = p * t - lm;
+      const double g = fabs(z[k] + p + lm);
+      if (g < gmin) { gmin = g; r = k; }
+    }
+    double zz = 1.0, nrm = 1.0;
+    z[r] = 1.0;
+    for (int k = r - 1; k >= 0; --k) {
+      zz = -Lp[64 * k + i] * zz;
+      z[k] = zz;
+      nrm += zz * zz;
+    }
+    zz = 1.0;
+    for (int k = r; k + 1 < K; ++k) {
+      zz = -Um[64 * k + i] * zz;
+      z[k + 1] = zz;
+      nrm += zz * zz;
+    }
+    const double sc = 1.0 / sqrt(nrm);
+    for (int k = 0; k < K; ++k) z[k] *= sc;
+    if (!isfinite(sc) || !(sc > 0.0)) red[15] = 1.0;   // a vector the recurrences could not form
+  }
+  __syncthreads();
+  // ---- 5. orthogonality of the kept eigenvectors (indices K - q .. K - 1).  Twisted-factorisation
+  // vectors of an L D L^T whose eigenvalues are resolved to relative width 2^-46 differ from exact
+  // ones by about K eps / relgap, so pairs whose eigenvalues differ by more than 1 % are orthogonal to
+  // far below the tolerance; the other pairs are checked by dot products (and every vector was
+  // normalised, non-finite ones flagged).
+  const double cut = J.ctol * tr;
+  int q = 0;
+  for (int i = 0; i < K; ++i) q += (lam[i] - sigma > cut) ? 1 : 0;
+  const int i0 = K - q;
+  {
+    double dev = red[15];
+    for (int e = tid; e < q * q; e += TRI_NT) {
+      const int ia = i0 + e % q, ib = i0 + e / q;
+      if (ia >= ib) continue;
+      const double la = lam[ia], lb = lam[ib];
+      if (fabs(la - lb) > 0.01 * fmax(la, lb)) continue;
+      double g = 0.0;
+      for (int k = 0; k < K; ++k) g += A[k + TRI_LD * ia] * A[k + TRI_LD * ib];
+      dev = fmax(dev, g != g ? 1.0 : fabs(g));
+    }
+    dev = wave_max_f64(dev);
+    if (lane == 0) red[4 + wave] = dev;
+  }
+  __syncthreads();
+  double dev = 0.0;
+  for (int c = 0; c < TRI_NW; ++c) dev = fmax(dev, red[4 + c]);
+  if (!(dev <= J.jtol)) {
+    if (tid == 0) *J.q = -1;
+    return;
+  }
+  // ---- 6. V = Q Z, column o = eigenvector K - 1 - o
+  if (tid < 256) {
+    double acc[4][4];
+    tri_mm44<false>(Q, A, K, acc);
+    const int r0 = 4 * (tid % 16), c0 = 4 * (tid / 16);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int r = r0 + a, i = c0 + b;
+        if (r < K && i < K) {
+          const int o = K - 1 - i;
+          J.v[r + (long)K * o] = o < q ? acc[a][b] : 0.0;
+        }
+      }
+  }
+  for (int o = tid; o < K; o += TRI_NT) J.w[o] = o < q ? lam[K - 1 - o] - sigma : 0.0;
+  if (tid == 0) {
+    double rest = 0.0;
+    for (int i = 0; i < i0; ++i) rest += fmax(lam[i] - sigma, 0.0);
+    *J.q = q;
+    *J.rest = rest;
+  }
+}
+
+hipError_t psd_tri_batched(const JobBatch<PsdJob>& jobs_dev, int count, int Kmax, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (count > kBatchJobs || Kmax > kTriMax) return hipErrorInvalidValue;
+  const size_t shm = sizeof(double) * ((size_t)2 * kTriMax * TRI_LD + 2 * kTriMax * 64 + 6 * kTriMax + 4 * TRI_NW * 64 + 64 + 16);
+  return launch_gram<true, TRI_NT>(k_psd_tri, jobs_dev, count, shm, s);
+}
+
 hipError_t syev_batched(const JobBatch<EigJob>& jobs_dev, int count, int Kmax, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   if (count > kBatchJobs) return hipErrorInvalidValue;

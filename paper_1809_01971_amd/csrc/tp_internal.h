@@ -95,6 +95,16 @@ hipError_t ns_isqrt_batched(const JobBatch<NsJob>& jobs, int count, int Kmax, hi
 struct PsdJob { int K; const double* g; double* w; double* v; int* q; double* rest; double* work; double ctol; double jtol; };
 hipError_t psd_eig_batched(const JobBatch<PsdJob>& jobs, int count, int Kmax, hipStream_t s);
 
+// The same eigenpairs by reduction to tridiagonal form (K <= kTriMax, one workgroup per matrix,
+// everything in LDS): Householder reduction, multisection on qd Sturm counts of a positive
+// definite L D L^T, twisted-factorisation eigenvectors.  The job's fields mean: ctol = cut,
+// eigenpairs with eigenvalue <= cut * trace(G) are dropped (q counts the others, rest = the
+// dropped eigenvalues' sum); jtol = the largest tolerated |Z^T Z - I| over the kept eigenvectors.
+// When the check fails the kernel writes q = -1 and nothing else for that job (the caller then
+// runs psd_eig_batched on it).
+constexpr int kTriMax = 64;
+hipError_t psd_tri_batched(const JobBatch<PsdJob>& jobs, int count, int Kmax, hipStream_t s);
+
 // Elementwise helpers.
 template <typename TI, typename TO>
 hipError_t convert(const TI* in, TO* out, long count, hipStream_t s);
