@@ -262,28 +262,33 @@ __global__ __launch_bounds__(GTHREADS) void k_gemm_mfma(GemmArgs<TA, TB, TC, Tac
     }
     __syncthreads();
     if (k0 + MBK < kend) mfma_fetch(g, A, B, FA, FB, invA, invB, m0, n0, k0 + MBK, kend, tid, ra, rb);
+    // the blocks are formed transposed, D = (A B)^T = B^T A^T (B's values in the first operand):
+    // a lane's results then lie along a column of C, so each store instruction writes runs of
+    // 16 consecutive rows (64 or 128 contiguous bytes) instead of 16 different columns
 #pragma unroll
     for (int kk = 0; kk < MBK; kk += 4) {
       const int kr = kk + (lane >> 4), c16 = lane & 15;
       Tacc a0 = As[kr][wm + c16], a1 = As[kr][wm + 16 + c16];
       Tacc b0 = Bs[kr][wn + c16], b1 = Bs[kr][wn + 16 + c16];
-      acc[0][0] = mfma16(a0, b0, acc[0][0]);
-      acc[0][1] = mfma16(a0, b1, acc[0][1]);
-      acc[1][0] = mfma16(a1, b0, acc[1][0]);
-      acc[1][1] = mfma16(a1, b1, acc[1][1]);
+      acc[0][0] = mfma16(b0, a0, acc[0][0]);
+      acc[0][1] = mfma16(b1, a0, acc[0][1]);
+      acc[1][0] = mfma16(b0, a1, acc[1][0]);
+      acc[1][1] = mfma16(b1, a1, acc[1][1]);
     }
     __syncthreads();
   }
+  // element v of lane l of block (i, j) is C[16 i + l % 16][16 j + cbase + cstep v] of the wave's
+  // quarter (the 16x16 result layouts of the FP32 and FP64 instructions, transposed)
   const bool f64 = std::is_same<Tacc, double>::value;
-  const int rbase = f64 ? (lane >> 4) : 4 * (lane >> 4), rstep = f64 ? 4 : 1, cl = lane & 15;
+  const int cbase = f64 ? (lane >> 4) : 4 * (lane >> 4), cstep = f64 ? 4 : 1, rl = lane & 15;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        int row = m0 + wm + 16 * i + rbase + rstep * v;
-        int col = n0 + wn + 16 * j + cl;
+        int row = m0 + wm + 16 * i + rl;
+        int col = n0 + wn + 16 * j + cbase + cstep * v;
         if (row >= g.M || col >= g.N) continue;
         Tacc x = acc[i][j][v];
         if (g.part) {
