@@ -165,56 +165,88 @@ __device__ __forceinline__ d4_t mfma16(double a, double b, d4_t c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// One stage of the MFMA kernel covers MBK contraction indices; each thread holds 8 elements of
-// the A tile and 8 of the B tile in registers, so the next stage's global loads are in flight
-// while the current stage is multiplied out of LDS.
+// One stage of the MFMA kernel covers MBK contraction indices; each thread loads 8 elements of
+// the A tile and 8 of the B tile per stage.
 constexpr int MBK = 32;
 
-template <typename TA, typename TB, typename TC, typename Tacc>
-__device__ __forceinline__ void mfma_fetch(const GemmArgs<TA, TB, TC, Tacc>& g, const TA* A, const TB* B,
-                                           const FaceSplit<TA>& FA, const FaceSplit<TB>& FB, float invA, float invB,
-                                           int m0, int n0, int k0, int kend, int tid, Tacc (&ra)[8], Tacc (&rb)[8]) {
-  if (!g.tA) {
+// How an operand's tile elements are read: column-major, transposed, or face-split.
+enum { OP_N = 0, OP_T = 1, OP_FS = 2 };
+
+// The raw loads of one operand's share of a stage.  They are issued without a bounds branch
+// (indices clamped into the matrix) and combined - bounds mask, face-split product, weight,
+// conversion to the accumulation type - only when the stage is written to LDS: a load under a
+// divergent branch, or an arithmetic use of a loaded value, makes the compiler wait for it on the
+// spot, while these stay in flight through the previous stage's MFMAs.
+template <typename T, int KIND>
+struct OpRegs {
+  T x[8];
+  T y[KIND == OP_FS ? 8 : 1];
+  double w[KIND == OP_FS ? 8 : 1];
+  unsigned ok;
+};
+
+// Element i of the thread's share: A tiles are M x K, B tiles K x N.  For a column-major A tile
+// (or a face-split one) lane groups run along M; for a transposed one along K; B the other way.
+template <bool IS_A, int KIND>
+__device__ __forceinline__ void tile_pos(int tid, int i, int& outer, int& kk) {
+  const bool alongK = IS_A ? (KIND == OP_T) : (KIND != OP_T);
+  if (alongK) { kk = tid & 31; outer = (tid >> 5) + 8 * i; }
+  else { outer = tid & 63; kk = (tid >> 6) + 4 * i; }
+}
+
+// Loads op's stage at (o0 along M or N, k0 along K); nout is M or N, the contraction runs to kend.
+// P: the operand's matrix (OP_N, OP_T), F: its face-split description (OP_FS).
+template <bool IS_A, int KIND, typename T>
+__device__ __forceinline__ void op_fetch(const T* P, int ld, const FaceSplit<T>& F, float inv, int o0, int nout,
+                                         int k0, int kend, int tid, OpRegs<T, KIND>& r) {
+  r.ok = 0;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      int m = tid & 63, kk = (tid >> 6) + 4 * i;
-      int row = m0 + m, col = k0 + kk;
-      Tacc v = 0;
-      if (row < g.M && col < kend) v = g.fsA ? (Tacc)fs_load(FA, row, col, invA) : (Tacc)A[row + (long)g.lda * col];
-      ra[i] = v;
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      int kk = tid & 31, m = (tid >> 5) + 8 * i;
-      int row = m0 + m, col = k0 + kk;
-      Tacc v = 0;
-      if (row < g.M && col < kend) v = (Tacc)A[col + (long)g.lda * row];
-      ra[i] = v;
-    }
-  }
-  if (!g.tB) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      int kk = tid & 31, n = (tid >> 5) + 8 * i;
-      int row = k0 + kk, col = n0 + n;
-      Tacc v = 0;
-      if (row < kend && col < g.N) v = g.fsB ? (Tacc)fs_load(FB, row, col, invB) : (Tacc)B[row + (long)g.ldb * col];
-      rb[i] = v;
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      int n = tid & 63, kk = (tid >> 6) + 4 * i;
-      int row = k0 + kk, col = n0 + n;
-      Tacc v = 0;
-      if (row < kend && col < g.N) v = (Tacc)B[col + (long)g.ldb * row];
-      rb[i] = v;
+  for (int i = 0; i < 8; ++i) {
+    int o, kk;
+    tile_pos<IS_A, KIND>(tid, i, o, kk);
+    const int oi = o0 + o, ki = k0 + kk;
+    r.ok |= (unsigned)(oi < nout && ki < kend) << i;
+    const int oc = min(oi, nout - 1), kc = min(ki, kend - 1);
+    // row and column of the stored matrix
+    const int row = IS_A ? (KIND == OP_T ? kc : oc) : (KIND == OP_T ? oc : kc);
+    const int col = IS_A ? (KIND == OP_T ? oc : kc) : (KIND == OP_T ? kc : oc);
+    if (KIND == OP_FS) {
+      int a, b;
+      fast_divmod(col, F.r1, inv, b, a);
+      r.x[i] = F.x1[row + (long)F.ld1 * a];
+      r.y[i] = F.x2[row + (long)F.ld2 * b];
+      r.w[i] = F.w ? F.w[b] : 1.0;
+    } else {
+      r.x[i] = P[row + (long)ld * col];
     }
   }
 }
 
-template <typename TA, typename TB, typename TC, typename Tacc>
+template <typename Tacc, typename T, int KIND>
+__device__ __forceinline__ Tacc op_value(const OpRegs<T, KIND>& r, int i) {
+  Tacc v;
+  if (KIND == OP_FS) {
+    T p = r.x[i] * r.y[i];
+    p = (T)((double)p * r.w[i]);
+    v = (Tacc)p;
+  } else {
+    v = (Tacc)r.x[i];
+  }
+  return ((r.ok >> i) & 1u) ? v : (Tacc)0;
+}
+
+// Writes the stage to LDS as T[k][m] (A) or T[k][n] (B).
+template <bool IS_A, int KIND, typename Tacc, typename T>
+__device__ __forceinline__ void op_store(Tacc (*S)[GBM + 4], int tid, const OpRegs<T, KIND>& r) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    int o, kk;
+    tile_pos<IS_A, KIND>(tid, i, o, kk);
+    S[kk][o] = op_value<Tacc>(r, i);
+  }
+}
+
+template <typename TA, typename TB, typename TC, typename Tacc, int AK, int BK>
 __global__ __launch_bounds__(GTHREADS) void k_gemm_mfma(GemmArgs<TA, TB, TC, Tacc> g) {
   typedef typename std::conditional<std::is_same<Tacc, double>::value, d4_t, f4_t>::type V4;
   __shared__ Tacc As[MBK][GBM + 4];
@@ -226,13 +258,13 @@ __global__ __launch_bounds__(GTHREADS) void k_gemm_mfma(GemmArgs<TA, TB, TC, Tac
   const int sp = blockIdx.z - b * g.splits;
   const int kbeg = sp * g.kchunk;
   const int kend = min(g.K, kbeg + g.kchunk);
-  const TA* A = g.A ? g.A + (long)(b / g.divA) * g.sA : nullptr;
-  const TB* B = g.B ? g.B + (long)(b / g.divB) * g.sB : nullptr;
+  const TA* A = AK != OP_FS ? g.A + (long)(b / g.divA) * g.sA : nullptr;
+  const TB* B = BK != OP_FS ? g.B + (long)(b / g.divB) * g.sB : nullptr;
   FaceSplit<TA> FA = g.FA;
   FaceSplit<TB> FB = g.FB;
-  if (g.fsA) { FA.x1 += (long)(b / g.divA) * g.sA; FA.x2 += (long)(b / g.divA) * g.sA; }
-  if (g.fsB) { FB.x1 += (long)(b / g.divB) * g.sB; FB.x2 += (long)(b / g.divB) * g.sB; }
-  const float invA = g.fsA ? 1.0f / (float)FA.r1 : 0.0f, invB = g.fsB ? 1.0f / (float)FB.r1 : 0.0f;
+  if (AK == OP_FS) { FA.x1 += (long)(b / g.divA) * g.sA; FA.x2 += (long)(b / g.divA) * g.sA; }
+  if (BK == OP_FS) { FB.x1 += (long)(b / g.divB) * g.sB; FB.x2 += (long)(b / g.divB) * g.sB; }
+  const float invA = AK == OP_FS ? 1.0f / (float)FA.r1 : 0.0f, invB = BK == OP_FS ? 1.0f / (float)FB.r1 : 0.0f;
   TC* C = g.C + (long)b * g.sC;
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
   V4 acc[2][2];
@@ -243,25 +275,20 @@ __global__ __launch_bounds__(GTHREADS) void k_gemm_mfma(GemmArgs<TA, TB, TC, Tac
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
 
-  Tacc ra[8], rb[8];
-  if (kbeg < kend) mfma_fetch(g, A, B, FA, FB, invA, invB, m0, n0, kbeg, kend, tid, ra, rb);
+  OpRegs<TA, AK> ra;
+  OpRegs<TB, BK> rb;
+  if (kbeg < kend) {
+    op_fetch<true, AK>(A, g.lda, FA, invA, m0, g.M, kbeg, kend, tid, ra);
+    op_fetch<false, BK>(B, g.ldb, FB, invB, n0, g.N, kbeg, kend, tid, rb);
+  }
   for (int k0 = kbeg; k0 < kend; k0 += MBK) {
-    if (!g.tA) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) As[(tid >> 6) + 4 * i][tid & 63] = ra[i];
-    } else {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) As[tid & 31][(tid >> 5) + 8 * i] = ra[i];
-    }
-    if (!g.tB) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) Bs[tid & 31][(tid >> 5) + 8 * i] = rb[i];
-    } else {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) Bs[(tid >> 6) + 4 * i][tid & 63] = rb[i];
-    }
+    op_store<true, AK>(As, tid, ra);
+    op_store<false, BK>(Bs, tid, rb);
     __syncthreads();
-    if (k0 + MBK < kend) mfma_fetch(g, A, B, FA, FB, invA, invB, m0, n0, k0 + MBK, kend, tid, ra, rb);
+    if (k0 + MBK < kend) {
+      op_fetch<true, AK>(A, g.lda, FA, invA, m0, g.M, k0 + MBK, kend, tid, ra);
+      op_fetch<false, BK>(B, g.ldb, FB, invB, n0, g.N, k0 + MBK, kend, tid, rb);
+    }
     // the blocks are formed transposed, D = (A B)^T = B^T A^T (B's values in the first operand):
     // a lane's results then lie along a column of C, so each store instruction writes runs of
     // 16 consecutive rows (64 or 128 contiguous bytes) instead of 16 different columns
@@ -332,6 +359,26 @@ static int g_use_mfma = 1;
 bool gemm_use_mfma() { return g_use_mfma != 0; }
 void gemm_set_mfma(int on) { g_use_mfma = on; }
 
+// The operand kinds are template parameters: each kernel holds only its own loads and registers.
+template <typename TA, typename TB, typename TC, typename Tacc, int AK>
+static void launch_mfma_b(const GemmArgs<TA, TB, TC, Tacc>& h, dim3 grid, hipStream_t s) {
+  if (h.fsB)
+    hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TC, Tacc, AK, OP_FS>), grid, dim3(GTHREADS), 0, s, h);
+  else if (h.tB)
+    hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TC, Tacc, AK, OP_T>), grid, dim3(GTHREADS), 0, s, h);
+  else
+    hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TC, Tacc, AK, OP_N>), grid, dim3(GTHREADS), 0, s, h);
+}
+template <typename TA, typename TB, typename TC, typename Tacc>
+static void launch_mfma(const GemmArgs<TA, TB, TC, Tacc>& h, dim3 grid, hipStream_t s) {
+  if (h.fsA)
+    launch_mfma_b<TA, TB, TC, Tacc, OP_FS>(h, grid, s);
+  else if (h.tA)
+    launch_mfma_b<TA, TB, TC, Tacc, OP_T>(h, grid, s);
+  else
+    launch_mfma_b<TA, TB, TC, Tacc, OP_N>(h, grid, s);
+}
+
 template <typename TA, typename TB, typename TC, typename Tacc>
 hipError_t gemm(const GemmArgs<TA, TB, TC, Tacc>& g, hipStream_t s, hipEvent_t mid) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
@@ -344,7 +391,7 @@ hipError_t gemm(const GemmArgs<TA, TB, TC, Tacc>& g, hipStream_t s, hipEvent_t m
   h.kchunk = h.splits > 1 ? ((h.K + h.splits - 1) / h.splits + MBK - 1) / MBK * MBK : h.K;
   dim3 grid((h.M + GBM - 1) / GBM, (h.N + GBN - 1) / GBN, h.batch * h.splits);
   if (gemm_use_mfma())
-    hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TC, Tacc>), grid, dim3(GTHREADS), 0, s, h);
+    launch_mfma<TA, TB, TC, Tacc>(h, grid, s);
   else
     hipLaunchKernelGGL((k_gemm<TA, TB, TC, Tacc>), grid, dim3(GTHREADS), 0, s, h);
   if (h.splits > 1) {
