@@ -296,44 +296,61 @@ int gemm_class() {
 }
 
 // ------------------------------------------------------------------------------ GEMM helpers
+// Up to kGemmGroup independent products with the same operand kinds in one launch.  Few output
+// tiles and a long contraction: K is split over workgroups (chunks of at least 64) so that about
+// 512 workgroups share the launch; the partial sums are added by a second kernel.
 template <typename TA, typename TB, typename TC, typename Tacc>
-tp_status run(tp_ctx* c, const GemmArgs<TA, TB, TC, Tacc>& g0) {
-  GemmArgs<TA, TB, TC, Tacc> g = g0;
-  // few output tiles and a long contraction: split K over workgroups (chunks of at least 64)
-  // so that about 512 workgroups share the launch; the partial sums are added by a second kernel
-  const long tiles = (long)((g.M + 63) / 64) * ((g.N + 63) / 64) * g.batch;
+tp_status run_group(tp_ctx* c, const GemmArgs<TA, TB, TC, Tacc>* g0, int count) {
+  GemmArgs<TA, TB, TC, Tacc> g[kGemmGroup];
+  if (count < 1 || count > kGemmGroup) return fail(TP_EINVAL, "GEMM group of %d products", count);
+  long tiles = 0;
+  for (int i = 0; i < count; ++i) {
+    g[i] = g0[i];
+    if (g[i].M > 0 && g[i].N > 0) tiles += (long)((g[i].M + 63) / 64) * ((g[i].N + 63) / 64) * g[i].batch;
+  }
   size_t mark = c->ws_top;
-  if (tiles < 256 && g.K >= 128) {
-    int splits = (int)std::min<long>((g.K + 63) / 64, std::max<long>(1, 512 / tiles));
-    if (splits > 1) {
-      Tacc* part = nullptr;
-      if (wsalloc(c, (size_t)g.batch * splits * g.M * g.N, &part) == TP_OK) {
-        g.splits = splits;
-        g.part = part;
-      }
+  bool split = false;
+  for (int i = 0; i < count; ++i) {
+    if (tiles >= 256 || g[i].K < 128 || g[i].M <= 0 || g[i].N <= 0) continue;
+    int splits = (int)std::min<long>((g[i].K + 63) / 64, std::max<long>(1, 512 / tiles));
+    if (splits < 2) continue;
+    Tacc* part = nullptr;
+    if (wsalloc(c, (size_t)g[i].batch * splits * g[i].M * g[i].N, &part) == TP_OK) {
+      g[i].splits = splits;
+      g[i].part = part;
+      split = true;
     }
   }
   size_t e0 = 0, em = 0;
   TPCHK(prof_begin(c, &e0));
-  const bool split = c->prof && g.splits > 1 && g.part;
-  if (split) em = c->ev_next++;  // recorded by gemm() between the contraction and its reduction
-  hipError_t ge = gemm<TA, TB, TC, Tacc>(g, c->stream, split ? c->ev_pool[em] : nullptr);
+  split = split && c->prof;
+  if (split) em = c->ev_next++;  // recorded between the contraction and its reduction
+  hipError_t ge = gemm_group<TA, TB, TC, Tacc>(g, count, c->stream, split ? c->ev_pool[em] : nullptr);
   c->ws_top = mark;  // the partial-sum scratch is consumed by the launches just enqueued
   HIPCHK(ge);
   if (c->prof) {
     // algorithmic work: 2 M N K per product; bytes: operands once + result once (face-split
     // operands count their two factor matrices)
-    double M = g.M, N = g.N, K = g.K, b = g.batch;
-    double fl = 2.0 * M * N * K * b;
-    double ba = g.fsA ? (double)M * (g.FA.r1 + K / std::max(1, g.FA.r1)) : M * K * (g.divA > 1 || g.sA ? b / g.divA : 1);
-    double bb = g.fsB ? (double)K * (g.FB.r1 + N / std::max(1, g.FB.r1)) : K * N * (g.sB ? b / g.divB : 1);
-    double by = ba * sizeof(TA) + bb * sizeof(TB) + M * N * b * sizeof(TC);
+    double fl = 0, by = 0, rfl = 0, rby = 0;
+    for (int i = 0; i < count; ++i) {
+      double M = g[i].M, N = g[i].N, K = g[i].K, b = g[i].batch;
+      if (M <= 0 || N <= 0 || b <= 0) continue;
+      fl += 2.0 * M * N * K * b;
+      double ba = g[i].fsA ? (double)M * (g[i].FA.r1 + K / std::max(1, g[i].FA.r1))
+                           : M * K * (g[i].divA > 1 || g[i].sA ? b / g[i].divA : 1);
+      double bb = g[i].fsB ? (double)K * (g[i].FB.r1 + N / std::max(1, g[i].FB.r1))
+                           : K * N * (g[i].sB ? b / g[i].divB : 1);
+      by += ba * sizeof(TA) + bb * sizeof(TB) + M * N * b * sizeof(TC);
+      if (g[i].splits > 1) {
+        // the reduction adds the partial sums (splits x the output, read once) and writes the output
+        rfl += M * N * b * (g[i].splits - 1);
+        rby += M * N * b * ((double)g[i].splits * sizeof(Tacc) + sizeof(TC));
+      }
+    }
     if (split) {
-      // the contraction [e0, em] carries the algorithmic work; the reduction [em, e1] adds the
-      // partial sums (splits x the output, read once) and writes the output
+      // the contraction [e0, em] carries the algorithmic work, the reduction is [em, e1]
       c->recs.push_back({gemm_class<TA, TB, TC, Tacc>(), e0, em, fl, by});
-      TPCHK(prof_end(c, PC_GEMM_REDUCE, em, M * N * b * (g.splits - 1),
-                     M * N * b * ((double)g.splits * sizeof(Tacc) + sizeof(TC))));
+      TPCHK(prof_end(c, PC_GEMM_REDUCE, em, rfl, rby));
     } else {
       TPCHK(prof_end(c, gemm_class<TA, TB, TC, Tacc>(), e0, fl, by));
     }
@@ -341,17 +358,28 @@ tp_status run(tp_ctx* c, const GemmArgs<TA, TB, TC, Tacc>& g0) {
   return TP_OK;
 }
 
+template <typename TA, typename TB, typename TC, typename Tacc>
+tp_status run(tp_ctx* c, const GemmArgs<TA, TB, TC, Tacc>& g) {
+  return run_group(c, &g, 1);
+}
+
 // C (M x N) = alpha op(A) op(B) + beta C, plain operands.
 template <typename TA, typename TB, typename TC, typename Tacc>
-tp_status mm(tp_ctx* c, bool tA, bool tB, int M, int N, int K, double alpha, const TA* A, int lda, const TB* B,
-             int ldb, double beta, TC* C, int ldc) {
+GemmArgs<TA, TB, TC, Tacc> mm_args(bool tA, bool tB, int M, int N, int K, double alpha, const TA* A, int lda,
+                                   const TB* B, int ldb, double beta, TC* C, int ldc) {
   GemmArgs<TA, TB, TC, Tacc> g;
   g.M = M; g.N = N; g.K = K;
   g.alpha = (Tacc)alpha; g.beta = (Tacc)beta;
   g.A = A; g.lda = lda; g.tA = tA;
   g.B = B; g.ldb = ldb; g.tB = tB;
   g.C = C; g.ldc = ldc;
-  return run(c, g);
+  return g;
+}
+
+template <typename TA, typename TB, typename TC, typename Tacc>
+tp_status mm(tp_ctx* c, bool tA, bool tB, int M, int N, int K, double alpha, const TA* A, int lda, const TB* B,
+             int ldb, double beta, TC* C, int ldc) {
+  return run(c, mm_args<TA, TB, TC, Tacc>(tA, tB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc));
 }
 
 // ------------------------------------------------------------------------------ eigen
@@ -584,26 +612,36 @@ tp_status psd_eig_dev(tp_ctx* c, int cnt, const int* K, const double* const* G, 
 // matrix.
 tp_status ortho_batch(tp_ctx* c, int cnt, const int* n, const int* K, const double* const* V, double reltol,
                       double** Qout, int* qout) {
+  typedef GemmArgs<double, double, double, double> GA;
   double *G[3], *W[3], *Q1[3];
   int q1[3];
+  GA gs[3];
+  int ng = 0;
   for (int i = 0; i < cnt; ++i) {
     qout[i] = 0;
     Qout[i] = nullptr;
     TPCHK(wsalloc(c, (size_t)K[i] * K[i], &G[i]));
     TPCHK(wsalloc(c, (size_t)K[i] * K[i], &W[i]));
     if (K[i] > 0)
-      TPCHK(mm<double, double, double, double>(c, true, false, K[i], K[i], n[i], 1.0, V[i], n[i], V[i], n[i], 0.0, G[i], K[i]));
+      gs[ng++] = mm_args<double, double, double, double>(true, false, K[i], K[i], n[i], 1.0, V[i], n[i], V[i], n[i], 0.0, G[i], K[i]);
   }
+  if (ng) TPCHK(run_group(c, gs, ng));
   const double* Gc[3] = {G[0], G[1], G[2]};
   TPCHK(chol(c, cnt, K, Gc, reltol, W, q1));
   int q1c[3];
+  ng = 0;
+  GA gg[3];
   for (int i = 0; i < cnt; ++i) {
     q1c[i] = q1[i];
     Q1[i] = nullptr;
     if (q1[i] == 0) continue;
     TPCHK(wsalloc(c, (size_t)n[i] * q1[i], &Q1[i]));
-    TPCHK(mm<double, double, double, double>(c, false, false, n[i], q1[i], K[i], 1.0, V[i], n[i], W[i], K[i], 0.0, Q1[i], n[i]));
-    TPCHK(mm<double, double, double, double>(c, true, false, q1[i], q1[i], n[i], 1.0, Q1[i], n[i], Q1[i], n[i], 0.0, G[i], q1[i]));
+    gs[ng] = mm_args<double, double, double, double>(false, false, n[i], q1[i], K[i], 1.0, V[i], n[i], W[i], K[i], 0.0, Q1[i], n[i]);
+    gg[ng++] = mm_args<double, double, double, double>(true, false, q1[i], q1[i], n[i], 1.0, Q1[i], n[i], Q1[i], n[i], 0.0, G[i], q1[i]);
+  }
+  if (ng) {
+    TPCHK(run_group(c, gs, ng));
+    TPCHK(run_group(c, gg, ng));
   }
   int q2[3];
   // second pass: Q1^T Q1 = I + E with E of the first pass's loss of orthogonality.  Its inverse
@@ -617,12 +655,14 @@ tp_status ortho_batch(tp_ctx* c, int cnt, const int* n, const int* K, const doub
   } else {
     TPCHK(chol(c, cnt, q1c, Gc, 1e-14, W, q2));
   }
+  ng = 0;
   for (int i = 0; i < cnt; ++i) {
     if (q1[i] == 0 || q2[i] == 0) continue;
     TPCHK(wsalloc(c, (size_t)n[i] * q2[i], &Qout[i]));
-    TPCHK(mm<double, double, double, double>(c, false, false, n[i], q2[i], q1[i], 1.0, Q1[i], n[i], W[i], q1[i], 0.0, Qout[i], n[i]));
+    gs[ng++] = mm_args<double, double, double, double>(false, false, n[i], q2[i], q1[i], 1.0, Q1[i], n[i], W[i], q1[i], 0.0, Qout[i], n[i]);
     qout[i] = q2[i];
   }
+  if (ng) TPCHK(run_group(c, gs, ng));
   return TP_OK;
 }
 
@@ -680,12 +720,15 @@ tp_status hosvd(tp_ctx* c, int d, const int* q, const T* M, double tol, int cap,
       TPCHK((mm<T, T, double, Tacc>(c, true, false, q[1], q[1], q[0], 1.0, M, q[0], M, q[0], 0.0, G[1], q[1])));
     } else {
       int q23 = q[1] * q[2], q12 = q[0] * q[1];
-      TPCHK((mm<T, T, double, Tacc>(c, false, true, q[0], q[0], q23, 1.0, M, q[0], M, q[0], 0.0, G[0], q[0])));
-      TPCHK((mm<T, T, double, Tacc>(c, true, false, q[2], q[2], q12, 1.0, M, q12, M, q12, 0.0, G[2], q[2])));
       T* Mp;
       TPCHK(wsalloc(c, (size_t)q[0] * q[1] * q[2], &Mp));
       HIPCHK(permute3<T>(M, q[0], q[1], q[2], Mp, 1, 0, 2, c->stream));
-      TPCHK((mm<T, T, double, Tacc>(c, false, true, q[1], q[1], q[0] * q[2], 1.0, Mp, q[1], Mp, q[1], 0.0, G[1], q[1])));
+      // the mode-1 and mode-2 Grams (same operand kinds) share a launch
+      GemmArgs<T, T, double, Tacc> g01[2] = {
+          mm_args<T, T, double, Tacc>(false, true, q[0], q[0], q23, 1.0, M, q[0], M, q[0], 0.0, G[0], q[0]),
+          mm_args<T, T, double, Tacc>(false, true, q[1], q[1], q[0] * q[2], 1.0, Mp, q[1], Mp, q[1], 0.0, G[1], q[1])};
+      TPCHK(run_group(c, g01, 2));
+      TPCHK((mm<T, T, double, Tacc>(c, true, false, q[2], q[2], q12, 1.0, M, q12, M, q12, 0.0, G[2], q[2])));
     }
   }
   std::vector<std::vector<double>> hw;
@@ -842,11 +885,15 @@ tp_status truncate_impl(tp_ctx* c, int count, const double* coef, const tp_tenso
     const double* Vc[3] = {V[0], V[1], V[2]};
     TPCHK(ortho_batch(c, d, y->n, K, Vc, 1e-15, Q, q));
   }
-  for (int m = 0; m < d; ++m) {
-    int n = y->n[m];
-    if (q[m] == 0) return set_zero<T>(c, y);
-    TPCHK(wsalloc(c, (size_t)q[m] * K[m], &R[m]));
-    TPCHK((mm<double, double, double, double>(c, true, false, q[m], K[m], n, 1.0, Q[m], n, V[m], n, 0.0, R[m], q[m])));
+  {
+    GemmArgs<double, double, double, double> gs[3];
+    for (int m = 0; m < d; ++m) {
+      int n = y->n[m];
+      if (q[m] == 0) return set_zero<T>(c, y);
+      TPCHK(wsalloc(c, (size_t)q[m] * K[m], &R[m]));
+      gs[m] = mm_args<double, double, double, double>(true, false, q[m], K[m], n, 1.0, Q[m], n, V[m], n, 0.0, R[m], q[m]);
+    }
+    TPCHK(run_group(c, gs, d));
   }
   size_t msz = (size_t)q[0] * q[1] * (d == 3 ? q[2] : 1);
   double* M;
@@ -874,11 +921,13 @@ tp_status truncate_impl(tp_ctx* c, int count, const double* coef, const tp_tenso
   int rn[3] = {1, 1, 1};
   double* U[3];
   TPCHK((hosvd<double, T>(c, d, q, M, tol, cap, rn, U, (T*)y->core, capped)));
+  GemmArgs<double, double, T, double> gf[3];
   for (int m = 0; m < d; ++m) {
     int n = y->n[m];
-    TPCHK((mm<double, double, T, double>(c, false, false, n, rn[m], q[m], 1.0, Q[m], n, U[m], q[m], 0.0, (T*)y->factor[m], n)));
+    gf[m] = mm_args<double, double, T, double>(false, false, n, rn[m], q[m], 1.0, Q[m], n, U[m], q[m], 0.0, (T*)y->factor[m], n);
     y->rank[m] = rn[m];
   }
+  TPCHK(run_group(c, gf, d));
   return TP_OK;
 }
 
@@ -977,30 +1026,33 @@ tp_status combo_impl(tp_ctx* c, const Term* terms, int nt, tp_tensor* y, double 
       P.R = 1;
       for (int m = 0; m < d; ++m) TPCHK(unit_symbol<T>(c, x->n[m], &P.S[m], &P.w));
     }
-    // A_m[i + r_m (k + R q)] = sum_x Vh_m(x,i) S_m(x,k) Om_m(x,q)
+    // A_m[i + r_m (k + R q)] = sum_x Vh_m(x,i) S_m(x,k) Om_m(x,q), the modes in one launch
+    GemmArgs<T, T, T, Tacc> ga[3];
     for (int m = 0; m < d; ++m) {
       TPCHK(wsalloc(c, (size_t)P.r[m] * P.R * Qs, &P.A[m]));
-      GemmArgs<T, T, T, Tacc> g;
+      GemmArgs<T, T, T, Tacc>& g = ga[m];
       g.M = P.r[m]; g.N = P.R * Qs; g.K = x->n[m];
       g.A = P.Vh[m]; g.lda = x->n[m]; g.tA = true;
       g.fsB = true; g.FB.x1 = P.S[m]; g.FB.ld1 = x->n[m]; g.FB.r1 = P.R;
       g.FB.x2 = Om[m]; g.FB.ld2 = x->n[m];
       g.C = P.A[m]; g.ldc = P.r[m];
-      TPCHK(run(c, g));
     }
+    TPCHK(run_group(c, ga, d));
   }
-  // sketches Y_m (double)
+  // sketches Y_m (double); per term the d contractions with the face-split operands share a launch
   double* Y[3];
-  for (int m = 0; m < d; ++m) {
-    const int n = y->n[m];
-    TPCHK(wsalloc(c, (size_t)n * Qs, &Y[m]));
-    for (int t = 0; t < nterm; ++t) {
-      Prep& P = pr[t];
-      const int* r = P.r;
-      const int R = P.R;
-      WsScope s2(c);
+  for (int m = 0; m < d; ++m) TPCHK(wsalloc(c, (size_t)y->n[m] * Qs, &Y[m]));
+  for (int t = 0; t < nterm; ++t) {
+    Prep& P = pr[t];
+    const int* r = P.r;
+    const int R = P.R;
+    WsScope s2(c);
+    GemmArgs<T, T, double, double> gy[3];
+    for (int m = 0; m < d; ++m) {
+      const int n = y->n[m];
       T* tt;
       TPCHK(wsalloc(c, (size_t)r[m] * R * Qs, &tt));
+      WsScope s2m(c);
       size_t csz = (size_t)r[0] * r[1] * r[2];
       if (d == 3) {
         int o1 = m == 0 ? 1 : 0, o2 = m == 2 ? 1 : 2;
@@ -1022,15 +1074,15 @@ tp_status combo_impl(tp_ctx* c, const Term* terms, int nt, tp_tensor* y, double 
         }
         TPCHK((mm<T, T, T, Tacc>(c, false, false, r[m], R * Qs, r[o], 1.0, Cm, r[m], P.A[o], r[o], 0.0, tt, r[m])));
       }
-      GemmArgs<T, T, double, double> g;
+      GemmArgs<T, T, double, double>& g = gy[m];
       g.M = n; g.N = Qs; g.K = r[m] * R;
       g.alpha = tv[t].coef; g.beta = t == 0 ? 0.0 : 1.0;
       g.fsA = true; g.FA.x1 = P.Vh[m]; g.FA.ld1 = n; g.FA.r1 = r[m];
       g.FA.x2 = P.S[m]; g.FA.ld2 = n; g.FA.w = P.w;
       g.B = tt; g.ldb = r[m] * R;
       g.C = Y[m]; g.ldc = n;
-      TPCHK(run(c, g));
     }
+    TPCHK(run_group(c, gy, d));
   }
   // orthonormal bases of the sketches
   double* Qb[3];
@@ -1061,17 +1113,18 @@ tp_status combo_impl(tp_ctx* c, const Term* terms, int nt, tp_tensor* y, double 
     const int R = P.R;
     WsScope s3(c);
     T* Pm[3];
+    GemmArgs<T, T, T, Tacc> gps[3];
     for (int m = 0; m < d; ++m) {
       const int n = y->n[m];
       TPCHK(wsalloc(c, (size_t)q[m] * r[m] * R, &Pm[m]));
-      GemmArgs<T, T, T, Tacc> gp;
+      GemmArgs<T, T, T, Tacc>& gp = gps[m];
       gp.M = q[m]; gp.N = r[m] * R; gp.K = n;
       gp.A = Qt[m]; gp.lda = n; gp.tA = true;
       gp.fsB = true; gp.FB.x1 = P.Vh[m]; gp.FB.ld1 = n; gp.FB.r1 = r[m];
       gp.FB.x2 = P.S[m]; gp.FB.ld2 = n; gp.FB.w = (m == d - 1) ? P.w : nullptr;
       gp.C = Pm[m]; gp.ldc = q[m];
-      TPCHK(run(c, gp));
     }
+    TPCHK(run_group(c, gps, d));
     const double beta = t == 0 ? 0.0 : 1.0;
     if (d == 3) {
       T *D, *E;
@@ -1117,18 +1170,20 @@ tp_status combo_impl(tp_ctx* c, const Term* terms, int nt, tp_tensor* y, double 
   T* W[3] = {nullptr, nullptr, nullptr};
   int yn[3];
   T* yf[3];
+  GemmArgs<double, double, T, double> gw[3];
   for (int m = 0; m < d; ++m) {
     int n = y->n[m];
     yn[m] = n;
     yf[m] = (T*)y->factor[m];
     if (c->spectral) {
-      TPCHK((mm<double, double, T, double>(c, false, false, n, rn[m], q[m], 1.0, Qb[m], n, U[m], q[m], 0.0,
-                                          (T*)y->factor[m], n)));
+      gw[m] = mm_args<double, double, T, double>(false, false, n, rn[m], q[m], 1.0, Qb[m], n, U[m], q[m], 0.0,
+                                                 (T*)y->factor[m], n);
       continue;
     }
     TPCHK(wsalloc(c, (size_t)n * rn[m], &W[m]));
-    TPCHK((mm<double, double, T, double>(c, false, false, n, rn[m], q[m], 1.0, Qb[m], n, U[m], q[m], 0.0, W[m], n)));
+    gw[m] = mm_args<double, double, T, double>(false, false, n, rn[m], q[m], 1.0, Qb[m], n, U[m], q[m], 0.0, W[m], n);
   }
+  TPCHK(run_group(c, gw, d));
   if (!c->spectral) {
     const T* Wc[3] = {W[0], W[1], W[2]};
     TPCHK(dst_cols_batch<T>(c, d, yn, rn, Wc, yf));
@@ -1175,18 +1230,19 @@ tp_status inner_sym_impl(tp_ctx* c, const tp_tensor* x, const tp_symbol* S, cons
     }
     TPCHK(dst_cols_batch<T>(c, nj, jn, jc, ji, jo));
   }
+  GemmArgs<T, T, double, double> gs[3];
   for (int m = 0; m < d; ++m) {
     int n = x->n[m];
     // G[i + rx (j + ry k)] (sigma folded into the last mode)
     TPCHK(wsalloc(c, (size_t)rx[m] * ry[m] * R, &G[m]));
-    GemmArgs<T, T, double, double> g;
+    GemmArgs<T, T, double, double>& g = gs[m];
     g.M = rx[m]; g.N = ry[m] * R; g.K = n;
     g.A = Vx[m]; g.lda = n; g.tA = true;
     g.fsB = true; g.FB.x1 = Vy[m]; g.FB.ld1 = n; g.FB.r1 = ry[m];
     g.FB.x2 = (const T*)S->factors[m]; g.FB.ld2 = n; g.FB.w = (m == d - 1) ? S->weights : nullptr;
     g.C = G[m]; g.ldc = rx[m];
-    TPCHK(run(c, g));
   }
+  TPCHK(run_group(c, gs, d));
   size_t cx = (size_t)rx[0] * rx[1] * rx[2], cy = (size_t)ry[0] * ry[1] * ry[2];
   double *Cx, *Cy, *Z, *res;
   TPCHK(wsalloc(c, cx, &Cx));
@@ -1267,14 +1323,15 @@ tp_status inner_impl(tp_ctx* c, const tp_tensor* x, const tp_tensor* y, double* 
   const int d = x->d;
   double* G[3];
   int px[3] = {1, 1, 1}, ry[3] = {1, 1, 1};
+  GemmArgs<T, T, double, double> gs[3];
   for (int m = 0; m < d; ++m) {
     px[m] = x->rank[m];
     ry[m] = y->rank[m];
     TPCHK(wsalloc(c, (size_t)px[m] * ry[m], &G[m]));
-    using Tc = double;
-    TPCHK((mm<T, T, Tc, double>(c, true, false, px[m], ry[m], x->n[m], 1.0, (const T*)x->factor[m], x->n[m],
-                                (const T*)y->factor[m], y->n[m], 0.0, G[m], px[m])));
+    gs[m] = mm_args<T, T, double, double>(true, false, px[m], ry[m], x->n[m], 1.0, (const T*)x->factor[m], x->n[m],
+                                          (const T*)y->factor[m], y->n[m], 0.0, G[m], px[m]);
   }
+  TPCHK(run_group(c, gs, d));
   size_t cy = (size_t)ry[0] * ry[1] * ry[2], cx = (size_t)px[0] * px[1] * px[2];
   double *Cy, *Cx, *Z, *res;
   TPCHK(wsalloc(c, cy, &Cy));
@@ -1331,13 +1388,19 @@ tp_status from_cp_impl(tp_ctx* c, const tp_cp* b, tp_tensor* out, double tol, bo
   double* Q[3];
   double* Rm[3];
   int q[3] = {1, 1, 1};
+  {
+    int Ks[3] = {R, R, R};
+    const double* F[3] = {b->factor[0], b->factor[1], d == 3 ? b->factor[2] : nullptr};
+    TPCHK(ortho_batch(c, d, b->n, Ks, F, 1e-15, Q, q));
+  }
+  GemmArgs<double, double, double, double> gs[3];
   for (int m = 0; m < d; ++m) {
     int n = b->n[m];
-    TPCHK(ortho(c, n, R, b->factor[m], 1e-15, &Q[m], &q[m]));
     if (q[m] == 0) return set_zero<T>(c, out);
     TPCHK(wsalloc(c, (size_t)q[m] * R, &Rm[m]));
-    TPCHK((mm<double, double, double, double>(c, true, false, q[m], R, n, 1.0, Q[m], n, b->factor[m], n, 0.0, Rm[m], q[m])));
+    gs[m] = mm_args<double, double, double, double>(true, false, q[m], R, n, 1.0, Q[m], n, b->factor[m], n, 0.0, Rm[m], q[m]);
   }
+  TPCHK(run_group(c, gs, d));
   // R1 diag(w)
   HIPCHK(scale_cols_d(Rm[0], q[0], R, q[0], b->weight, c->stream));
   size_t msz = (size_t)q[0] * q[1] * (d == 3 ? q[2] : 1);
@@ -1355,11 +1418,13 @@ tp_status from_cp_impl(tp_ctx* c, const tp_cp* b, tp_tensor* out, double tol, bo
     int rn[3] = {1, 1, 1};
     double* U[3];
     TPCHK((hosvd<double, T>(c, d, q, M, tol, out->cap, rn, U, (T*)out->core, capped)));
+    GemmArgs<double, double, T, double> gf[3];
     for (int m = 0; m < d; ++m) {
       int n = b->n[m];
-      TPCHK((mm<double, double, T, double>(c, false, false, n, rn[m], q[m], 1.0, Q[m], n, U[m], q[m], 0.0, (T*)out->factor[m], n)));
+      gf[m] = mm_args<double, double, T, double>(false, false, n, rn[m], q[m], 1.0, Q[m], n, U[m], q[m], 0.0, (T*)out->factor[m], n);
       out->rank[m] = rn[m];
     }
+    TPCHK(run_group(c, gf, d));
     return TP_OK;
   }
   for (int m = 0; m < d; ++m)

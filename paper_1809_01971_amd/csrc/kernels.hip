@@ -168,6 +168,7 @@ __device__ __forceinline__ d4_t mfma16(double a, double b, d4_t c) {
 // One stage of the MFMA kernel covers MBK contraction indices; each thread loads 8 elements of
 // the A tile and 8 of the B tile per stage.
 constexpr int MBK = 32;
+constexpr int MNE = MBK / 4;  // elements of each operand per thread per stage
 
 // How an operand's tile elements are read: column-major, transposed, or face-split.
 enum { OP_N = 0, OP_T = 1, OP_FS = 2 };
@@ -179,9 +180,9 @@ enum { OP_N = 0, OP_T = 1, OP_FS = 2 };
 // spot, while these stay in flight through the previous stage's MFMAs.
 template <typename T, int KIND>
 struct OpRegs {
-  T x[8];
-  T y[KIND == OP_FS ? 8 : 1];
-  double w[KIND == OP_FS ? 8 : 1];
+  T x[MNE];
+  T y[KIND == OP_FS ? MNE : 1];
+  double w[KIND == OP_FS ? MNE : 1];
   unsigned ok;
 };
 
@@ -190,7 +191,7 @@ struct OpRegs {
 template <bool IS_A, int KIND>
 __device__ __forceinline__ void tile_pos(int tid, int i, int& outer, int& kk) {
   const bool alongK = IS_A ? (KIND == OP_T) : (KIND != OP_T);
-  if (alongK) { kk = tid & 31; outer = (tid >> 5) + 8 * i; }
+  if (alongK) { kk = tid % MBK; outer = tid / MBK + (GTHREADS / MBK) * i; }
   else { outer = tid & 63; kk = (tid >> 6) + 4 * i; }
 }
 
@@ -201,7 +202,7 @@ __device__ __forceinline__ void op_fetch(const T* P, int ld, const FaceSplit<T>&
                                          int k0, int kend, int tid, OpRegs<T, KIND>& r) {
   r.ok = 0;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
+  for (int i = 0; i < MNE; ++i) {
     int o, kk;
     tile_pos<IS_A, KIND>(tid, i, o, kk);
     const int oi = o0 + o, ki = k0 + kk;
@@ -239,7 +240,7 @@ __device__ __forceinline__ Tacc op_value(const OpRegs<T, KIND>& r, int i) {
 template <bool IS_A, int KIND, typename Tacc, typename T>
 __device__ __forceinline__ void op_store(Tacc (*S)[GBM + 4], int tid, const OpRegs<T, KIND>& r) {
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
+  for (int i = 0; i < MNE; ++i) {
     int o, kk;
     tile_pos<IS_A, KIND>(tid, i, o, kk);
     S[kk][o] = op_value<Tacc>(r, i);
@@ -247,15 +248,21 @@ __device__ __forceinline__ void op_store(Tacc (*S)[GBM + 4], int tid, const OpRe
 }
 
 template <typename TA, typename TB, typename TC, typename Tacc, int AK, int BK>
-__global__ __launch_bounds__(GTHREADS) void k_gemm_mfma(GemmArgs<TA, TB, TC, Tacc> g) {
+__global__ __launch_bounds__(GTHREADS) void k_gemm_mfma(GemmGroup<TA, TB, TC, Tacc> grp) {
   typedef typename std::conditional<std::is_same<Tacc, double>::value, d4_t, f4_t>::type V4;
   __shared__ Tacc As[MBK][GBM + 4];
   __shared__ Tacc Bs[MBK][GBN + 4];
+  // the product this workgroup belongs to: blockIdx.z runs over the products' batch x split ranges
+  int z = blockIdx.z, j = 0;
+  while (j + 1 < grp.count && z >= grp.z0[j + 1]) ++j;
+  const GemmArgs<TA, TB, TC, Tacc>& g = grp.g[j];
+  z -= grp.z0[j];
+  const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
+  if (m0 >= g.M || n0 >= g.N) return;  // the grid spans the largest product of the group
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
-  const int b = blockIdx.z / g.splits;
-  const int sp = blockIdx.z - b * g.splits;
+  const int b = z / g.splits;
+  const int sp = z - b * g.splits;
   const int kbeg = sp * g.kchunk;
   const int kend = min(g.K, kbeg + g.kchunk);
   const TA* A = AK != OP_FS ? g.A + (long)(b / g.divA) * g.sA : nullptr;
@@ -319,7 +326,7 @@ __global__ __launch_bounds__(GTHREADS) void k_gemm_mfma(GemmArgs<TA, TB, TC, Tac
         if (row >= g.M || col >= g.N) continue;
         Tacc x = acc[i][j][v];
         if (g.part) {
-          g.part[(long)blockIdx.z * g.M * g.N + row + (long)g.M * col] = x;
+          g.part[(long)z * g.M * g.N + row + (long)g.M * col] = x;
         } else {
           long o = row + (long)g.ldc * col;
           Tacc y = g.alpha * x;
@@ -329,15 +336,20 @@ __global__ __launch_bounds__(GTHREADS) void k_gemm_mfma(GemmArgs<TA, TB, TC, Tac
       }
 }
 
-template <typename TC, typename Tacc>
-__global__ void k_gemm_reduce(int M, int N, int splits, const Tacc* part, Tacc alpha, Tacc beta, TC* C, int ldc,
-                              long sC) {
-  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  int b = blockIdx.y;
-  long mn = (long)M * N;
-  if (e >= mn) return;
-  int row = (int)(e % M), col = (int)(e / M);
-  const Tacc* p = part + (long)b * splits * mn + e;
+// Split-K reduction of a group: blockIdx.y runs over the products' batches (z0 of the group's
+// reduction offsets), blockIdx.x over the largest product's M x N elements.
+template <typename TA, typename TB, typename TC, typename Tacc>
+__global__ void k_gemm_reduce(GemmGroup<TA, TB, TC, Tacc> grp) {
+  int y = blockIdx.y, j = 0;
+  while (j + 1 < grp.count && y >= grp.r0[j + 1]) ++j;
+  const GemmArgs<TA, TB, TC, Tacc>& g = grp.g[j];
+  const int b = y - grp.r0[j];
+  const long mn = (long)g.M * g.N;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= mn || g.splits < 2) return;
+  const int splits = g.splits;
+  int row = (int)(e % g.M), col = (int)(e / g.M);
+  const Tacc* p = g.part + (long)b * splits * mn + e;
   // four independent partial sums keep four loads in flight (fixed order: deterministic)
   Tacc a0 = 0, a1 = 0, a2 = 0, a3 = 0;
   int s = 0;
@@ -349,10 +361,10 @@ __global__ void k_gemm_reduce(int M, int N, int splits, const Tacc* part, Tacc a
   }
   for (; s < splits; ++s) a0 += p[(long)s * mn];
   Tacc acc = (a0 + a1) + (a2 + a3);
-  long o = (long)b * sC + row + (long)ldc * col;
-  Tacc v = alpha * acc;
-  if (beta != (Tacc)0) v += beta * (Tacc)C[o];
-  C[o] = (TC)v;
+  long o = (long)b * g.sC + row + (long)g.ldc * col;
+  Tacc v = g.alpha * acc;
+  if (g.beta != (Tacc)0) v += g.beta * (Tacc)g.C[o];
+  g.C[o] = (TC)v;
 }
 
 static int g_use_mfma = 1;
@@ -361,54 +373,83 @@ void gemm_set_mfma(int on) { g_use_mfma = on; }
 
 // The operand kinds are template parameters: each kernel holds only its own loads and registers.
 template <typename TA, typename TB, typename TC, typename Tacc, int AK>
-static void launch_mfma_b(const GemmArgs<TA, TB, TC, Tacc>& h, dim3 grid, hipStream_t s) {
-  if (h.fsB)
+static void launch_mfma_b(const GemmGroup<TA, TB, TC, Tacc>& h, bool fsB, bool tB, dim3 grid, hipStream_t s) {
+  if (fsB)
     hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TC, Tacc, AK, OP_FS>), grid, dim3(GTHREADS), 0, s, h);
-  else if (h.tB)
+  else if (tB)
     hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TC, Tacc, AK, OP_T>), grid, dim3(GTHREADS), 0, s, h);
   else
     hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TC, Tacc, AK, OP_N>), grid, dim3(GTHREADS), 0, s, h);
 }
-template <typename TA, typename TB, typename TC, typename Tacc>
-static void launch_mfma(const GemmArgs<TA, TB, TC, Tacc>& h, dim3 grid, hipStream_t s) {
-  if (h.fsA)
-    launch_mfma_b<TA, TB, TC, Tacc, OP_FS>(h, grid, s);
-  else if (h.tA)
-    launch_mfma_b<TA, TB, TC, Tacc, OP_T>(h, grid, s);
-  else
-    launch_mfma_b<TA, TB, TC, Tacc, OP_N>(h, grid, s);
-}
 
 template <typename TA, typename TB, typename TC, typename Tacc>
-hipError_t gemm(const GemmArgs<TA, TB, TC, Tacc>& g, hipStream_t s, hipEvent_t mid) {
-  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
-  if (g.K <= 0) {
-    // C = beta*C: handled by a degenerate launch with K = 0 (the loop body is skipped).
+hipError_t gemm_group(const GemmArgs<TA, TB, TC, Tacc>* gs, int count, hipStream_t s, hipEvent_t mid) {
+  if (count < 1 || count > kGemmGroup) return hipErrorInvalidValue;
+  GemmGroup<TA, TB, TC, Tacc> h;
+  h.count = 0;
+  int gx = 0, gy = 0, z = 0, r = 0;
+  bool split = false;
+  for (int i = 0; i < count; ++i) {
+    GemmArgs<TA, TB, TC, Tacc> a = gs[i];
+    if (a.M <= 0 || a.N <= 0 || a.batch <= 0) continue;
+    // one operand kind per launch: the kernels are specialised on it
+    if (h.count > 0 && (a.fsA != h.g[0].fsA || a.tA != h.g[0].tA || a.fsB != h.g[0].fsB || a.tB != h.g[0].tB))
+      return hipErrorInvalidValue;
+    if (a.splits < 1 || !a.part) { a.splits = 1; a.part = nullptr; }
+    // split chunks are multiples of the stage depth
+    a.kchunk = a.splits > 1 ? ((a.K + a.splits - 1) / a.splits + MBK - 1) / MBK * MBK : a.K;
+    gx = std::max(gx, (a.M + GBM - 1) / GBM);
+    gy = std::max(gy, (a.N + GBN - 1) / GBN);
+    h.z0[h.count] = z;
+    h.r0[h.count] = r;
+    z += a.batch * a.splits;
+    if (a.splits > 1) { r += a.batch; split = true; }
+    h.g[h.count++] = a;
   }
-  GemmArgs<TA, TB, TC, Tacc> h = g;
-  if (h.splits < 1 || !h.part) { h.splits = 1; h.part = nullptr; }
-  // split chunks are multiples of both kernels' stage depths
-  h.kchunk = h.splits > 1 ? ((h.K + h.splits - 1) / h.splits + MBK - 1) / MBK * MBK : h.K;
-  dim3 grid((h.M + GBM - 1) / GBM, (h.N + GBN - 1) / GBN, h.batch * h.splits);
-  if (gemm_use_mfma())
-    launch_mfma<TA, TB, TC, Tacc>(h, grid, s);
-  else
-    hipLaunchKernelGGL((k_gemm<TA, TB, TC, Tacc>), grid, dim3(GTHREADS), 0, s, h);
-  if (h.splits > 1) {
+  if (h.count == 0) return hipSuccess;
+  h.z0[h.count] = z;
+  h.r0[h.count] = r;
+  const GemmArgs<TA, TB, TC, Tacc>& f = h.g[0];
+  dim3 grid(gx, gy, z);
+  if (gemm_use_mfma()) {
+    if (f.fsA)
+      launch_mfma_b<TA, TB, TC, Tacc, OP_FS>(h, f.fsB, f.tB, grid, s);
+    else if (f.tA)
+      launch_mfma_b<TA, TB, TC, Tacc, OP_T>(h, f.fsB, f.tB, grid, s);
+    else
+      launch_mfma_b<TA, TB, TC, Tacc, OP_N>(h, f.fsB, f.tB, grid, s);
+  } else {
+    for (int i = 0; i < h.count; ++i) {
+      const GemmArgs<TA, TB, TC, Tacc>& a = h.g[i];
+      dim3 g1((a.M + GBM - 1) / GBM, (a.N + GBN - 1) / GBN, a.batch * a.splits);
+      hipLaunchKernelGGL((k_gemm<TA, TB, TC, Tacc>), g1, dim3(GTHREADS), 0, s, a);
+    }
+  }
+  if (split) {
     if (mid) {
       const hipError_t e = hipEventRecord(mid, s);
       if (e != hipSuccess) return e;
     }
-    long mn = (long)h.M * h.N;
-    dim3 rg((mn + 255) / 256, h.batch);
-    hipLaunchKernelGGL((k_gemm_reduce<TC, Tacc>), rg, dim3(256), 0, s, h.M, h.N, h.splits, (const Tacc*)h.part,
-                       h.alpha, h.beta, h.C, h.ldc, h.sC);
+    long mn = 0;
+    for (int i = 0; i < h.count; ++i)
+      if (h.g[i].splits > 1) mn = std::max(mn, (long)h.g[i].M * h.g[i].N);
+    dim3 rg((mn + 255) / 256, r);
+    hipLaunchKernelGGL((k_gemm_reduce<TA, TB, TC, Tacc>), rg, dim3(256), 0, s, h);
   }
   return hipGetLastError();
 }
 
+template <typename TA, typename TB, typename TC, typename Tacc>
+hipError_t gemm(const GemmArgs<TA, TB, TC, Tacc>& g, hipStream_t s, hipEvent_t mid) {
+  return gemm_group<TA, TB, TC, Tacc>(&g, 1, s, mid);
+}
+
 template hipError_t gemm<double, double, double, double>(const GemmArgs<double, double, double, double>&, hipStream_t, hipEvent_t);
 template hipError_t gemm<float, float, float, float>(const GemmArgs<float, float, float, float>&, hipStream_t, hipEvent_t);
+template hipError_t gemm_group<double, double, double, double>(const GemmArgs<double, double, double, double>*, int, hipStream_t, hipEvent_t);
+template hipError_t gemm_group<float, float, float, float>(const GemmArgs<float, float, float, float>*, int, hipStream_t, hipEvent_t);
+template hipError_t gemm_group<float, float, double, double>(const GemmArgs<float, float, double, double>*, int, hipStream_t, hipEvent_t);
+template hipError_t gemm_group<double, double, float, double>(const GemmArgs<double, double, float, double>*, int, hipStream_t, hipEvent_t);
 template hipError_t gemm<float, float, double, double>(const GemmArgs<float, float, double, double>&, hipStream_t, hipEvent_t);
 template hipError_t gemm<double, double, float, double>(const GemmArgs<double, double, float, double>&, hipStream_t, hipEvent_t);
 

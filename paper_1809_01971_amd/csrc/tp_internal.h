@@ -35,6 +35,21 @@ struct GemmArgs {
 // the two kernels can be timed apart.
 template <typename TA, typename TB, typename TC, typename Tacc>
 hipError_t gemm(const GemmArgs<TA, TB, TC, Tacc>& g, hipStream_t s, hipEvent_t mid = nullptr);
+
+// Up to kGemmGroup independent products with the same operand kinds (plain, transposed or
+// face-split A and B) in one launch, and their split-K reductions in a second one.  The group
+// travels in the kernel arguments; z0 / r0 (prefix sums of batch x splits and of the split
+// products' batches) are set by the launch.
+constexpr int kGemmGroup = 3;
+template <typename TA, typename TB, typename TC, typename Tacc>
+struct GemmGroup {
+  GemmArgs<TA, TB, TC, Tacc> g[kGemmGroup];
+  int z0[kGemmGroup + 1];
+  int r0[kGemmGroup + 1];
+  int count;
+};
+template <typename TA, typename TB, typename TC, typename Tacc>
+hipError_t gemm_group(const GemmArgs<TA, TB, TC, Tacc>* g, int count, hipStream_t s, hipEvent_t mid = nullptr);
 // Matrix-core (MFMA) tiles on (default) or the FMA tiles.
 bool gemm_use_mfma();
 void gemm_set_mfma(int on);
