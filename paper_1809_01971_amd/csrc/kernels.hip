@@ -932,6 +932,50 @@ __global__ __launch_bounds__(EIG_NT) void k_syev_small(JobBatch<EigJob> jobs) {
   for (int i = tid; i < K; i += EIG_NT) J.w[rk[i]] = diag[i];
 }
 
+// DPP row permutations on doubles and sums over aligned lane groups of 4, 8 and 16 (quad
+// xor 1, quad xor 2, half-row mirror, row mirror); every lane of a group receives its sum.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+__device__ __forceinline__ double group_sum(double v, int lanes) {
+  if (lanes >= 2) v += dpp_f64<0xB1>(v);
+  if (lanes >= 4) v += dpp_f64<0x4E>(v);
+  if (lanes >= 8) v += dpp_f64<0x141>(v);
+  if (lanes >= 16) v += dpp_f64<0x140>(v);
+  return v;
+}
+// Lanes per group for the DPP sums: the largest power of two <= 16 with lanes * groups <= nt
+// (at least 1).
+__device__ __forceinline__ int lanes_for(int nt, int groups) {
+  int l = 16;
+  while (l > 1 && l * groups > nt) l >>= 1;
+  return l;
+}
+
+// Sum / maximum over the 64 lanes (DPP within rows of 16, then the four row results read into
+// scalars); every lane receives the result, and the order of the additions is fixed.
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)b, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double wave_sum_f64(double v) {
+  v = group_sum(v, 16);
+  return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+__device__ __forceinline__ double wave_max_f64(double v) {
+  v = fmax(v, dpp_f64<0xB1>(v));
+  v = fmax(v, dpp_f64<0x4E>(v));
+  v = fmax(v, dpp_f64<0x141>(v));
+  v = fmax(v, dpp_f64<0x140>(v));
+  return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)), fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
+}
+
 // ---------------------------------------------------------------------------------------------
 // Pivoted Cholesky of Gram matrices, shared by the orthonormalisation (k_pchol) and the Gram
 // eigensolver (k_psd_eig).  G[P,P] = R^T R, the pivot of each step being the largest remaining
@@ -980,6 +1024,131 @@ __device__ __forceinline__ unsigned long long wave_max_key(unsigned long long v)
   v = umax64(v, dpp_u64<0x141>(v));
   v = umax64(v, dpp_u64<0x140>(v));
   return umax64(umax64(readlane64(v, 0), readlane64(v, 16)), umax64(readlane64(v, 32), readlane64(v, 48)));
+}
+
+// The same factorisation for K <= 64, blocked (the pivoted scheme of LAPACK's dpstrf): panels of
+// 16 pivots are factored left-looking by wave 0 alone, lane i owning row i, with no barrier:
+// the Schur diagonal d_i lives in lane i's register, the pivot is the lane maximum of 32-bit keys
+// (the diagonal relative to the largest initial one, as float bits, the low 6 bits replaced by
+// 63 - index: ties to 2^-18 relative go to the lower index), and column k is
+// (S[:, p] - L[:, panel] L[p, panel]^T) / sqrt(d_p) with L[p, panel] read from lane p's registers.
+// After each panel the whole workgroup applies it to the trailing matrix S (one barrier on each
+// side), which is full and symmetric in LDS.  Output: Lc[k K + i] = L(i, k) (column k of L in the
+// original row order, so R(k, l) = Lc[k K + perm[l]] in pivot order), dk[k] = sqrt(pivot k), perm
+// (the pivots, then the unpivoted indices in increasing order), sh.rest (the Schur trace left).
+// S is overwritten.
+__device__ __forceinline__ unsigned pivot_key32(double v, double scale, int i) {
+  return v > 0.0 ? ((__float_as_uint((float)(v * scale)) & ~63u) | (unsigned)(63 - i)) : 0u;
+}
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+  v = max(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false));
+  v = max(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false));
+  v = max(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, false));
+  v = max(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, false));
+  const unsigned r0 = (unsigned)__builtin_amdgcn_readlane((int)v, 0), r1 = (unsigned)__builtin_amdgcn_readlane((int)v, 16);
+  const unsigned r2 = (unsigned)__builtin_amdgcn_readlane((int)v, 32), r3 = (unsigned)__builtin_amdgcn_readlane((int)v, 48);
+  return max(max(r0, r1), max(r2, r3));
+}
+
+constexpr int CHOL_NB = 16;
+
+__device__ __forceinline__ int chol_phase_blk(const double* G, int K, double ctol, double* S, double* Lc, double* dk,
+                                              int* perm, int* mark, CholShared& sh) {
+  __shared__ int pstate[2];  // rank so far, 1 once the factorisation has stopped
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int e = tid; e < K * K; e += 256) {
+    const int i = e % K, j = e / K;
+    S[e] = G[min(i, j) + (long)K * max(i, j)];
+  }
+  // wave 0: the Schur diagonal, the scale of the pivot keys and the stopping threshold
+  double d = 0.0, dmax0 = 0.0, scale = 0.0, stop = 0.0;
+  bool alive = false;  // lane's row not pivoted yet
+  if (wave == 0) {
+    d = lane < K ? G[lane + (long)K * lane] : 0.0;
+    alive = lane < K;
+    dmax0 = wave_max_f64(lane < K ? d : 0.0);
+    scale = dmax0 > 0.0 ? 1.0 / dmax0 : 0.0;
+    stop = ctol * dmax0;
+    if (lane == 0) { pstate[0] = 0; pstate[1] = dmax0 > 0.0 ? 0 : 1; }
+  }
+  __syncthreads();
+  for (int kb = 0; kb < K; kb += CHOL_NB) {
+    if (wave == 0) {
+      int k = kb;
+      bool done = false;
+      double lrow[CHOL_NB];
+#pragma unroll
+      for (int t = 0; t < CHOL_NB; ++t) {
+        lrow[t] = 0.0;
+        if (done || kb + t >= K) continue;  // uniform
+        const unsigned key = wave_max_u32(alive ? pivot_key32(d, scale, lane) : 0u);
+        const int p = 63 - (int)(key & 63u);
+        const double dp = readlane_f64(d, p);
+        if (!key || !(dp > stop)) { done = true; continue; }  // uniform
+        const double sp = sqrt(dp), rs = 1.0 / sp;
+        double c = lane < K ? S[lane + K * p] : 0.0;
+#pragma unroll
+        for (int u = 0; u < t; ++u) c = fma(-lrow[u], readlane_f64(lrow[u], p), c);
+        const double l = lane == p ? sp : c * rs;
+        lrow[t] = l;
+        if (lane < K) Lc[(kb + t) * K + lane] = l;
+        if (lane == p) alive = false;
+        d = alive ? fma(-l, l, d) : 0.0;
+        if (lane == 0) { perm[kb + t] = p; dk[kb + t] = sp; }
+        k = kb + t + 1;
+      }
+      if (lane == 0) { pstate[0] = k; pstate[1] = done ? 1 : 0; }
+    }
+    __syncthreads();
+    if (pstate[1] || pstate[0] >= K) break;  // uniform
+    // trailing update S -= L_panel L_panel^T (thread (tx, ty) owns (tx + 16 a, ty + 16 b))
+    {
+      const int tx = tid & 15, ty = tid >> 4;
+      double acc[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[e] = 0.0;
+#pragma unroll 4
+      for (int t = 0; t < CHOL_NB; ++t) {
+        const double* Lt = Lc + (kb + t) * K;
+        double li[4], lj[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) li[a] = tx + 16 * a < K ? Lt[tx + 16 * a] : 0.0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) lj[b] = ty + 16 * b < K ? Lt[ty + 16 * b] : 0.0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+          for (int a = 0; a < 4; ++a) acc[a + 4 * b] = fma(li[a], lj[b], acc[a + 4 * b]);
+      }
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const int i = tx + 16 * a, j = ty + 16 * b;
+          if (i < K && j < K) S[i + K * j] -= acc[a + 4 * b];
+        }
+    }
+    __syncthreads();
+  }
+  const int q = pstate[0];
+  // unpivoted indices (in increasing order) after the pivots, and their remaining trace
+  for (int i = tid; i < K; i += 256) mark[i] = 0;
+  __syncthreads();
+  for (int k = tid; k < q; k += 256) mark[perm[k]] = 1;
+  if (wave == 0) {
+    double r = alive ? fmax(d, 0.0) : 0.0;
+    for (int o = 32; o > 0; o >>= 1) r += __shfl_xor(r, o);
+    if (lane == 0) { sh.rest = r; sh.q = q; }
+  }
+  __syncthreads();
+  for (int i = tid; i < K; i += 256)
+    if (!mark[i]) {
+      int c = 0;
+      for (int j = 0; j < i; ++j) c += mark[j] ? 0 : 1;
+      perm[q + c] = i;
+    }
+  __syncthreads();
+  return q;
 }
 
 // Returns the rank q (the same in every thread).  dk[k] = sqrt(pivot k); perm holds the pivots,
@@ -1087,29 +1256,6 @@ __device__ __forceinline__ double chol_r(const double* S, const double* dk, cons
   return S[min(a, b) + K * max(a, b)] / dk[i];
 }
 
-// DPP row permutations on doubles and sums over aligned lane groups of 4, 8 and 16 (quad
-// xor 1, quad xor 2, half-row mirror, row mirror); every lane of a group receives its sum.
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
-  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
-}
-__device__ __forceinline__ double group_sum(double v, int lanes) {
-  if (lanes >= 2) v += dpp_f64<0xB1>(v);
-  if (lanes >= 4) v += dpp_f64<0x4E>(v);
-  if (lanes >= 8) v += dpp_f64<0x141>(v);
-  if (lanes >= 16) v += dpp_f64<0x140>(v);
-  return v;
-}
-// Lanes per group for the DPP sums: the largest power of two <= 16 with lanes * groups <= nt
-// (at least 1).
-__device__ __forceinline__ int lanes_for(int nt, int groups) {
-  int l = 16;
-  while (l > 1 && l * groups > nt) l >>= 1;
-  return l;
-}
 
 // Rank-revealing orthonormalisation factor: W (K x q, ld K) = P[:, :q] R^-1, so that V W has
 // orthonormal columns spanning V's numerically independent columns (G = V^T V); q to *J.q.
@@ -1117,6 +1263,54 @@ __device__ __forceinline__ int lanes_for(int nt, int groups) {
 // X = R^-1 column by column, 4 to 16 lanes per column: row i of column j needs
 // sum_{i<l<=j} R(i, l) X(l, j), which the lanes split by l mod (lanes) and add with DPP; each
 // lane keeps the X(l, j) of its own residue class, so no barrier is needed.
+// K <= 64 on 256 threads: the blocked factorisation, then X = R^-1 with R transposed in pivot
+// order (RT[l + K i] = R(i, l)).  Four lanes per column j of X, lane li holding the rows
+// l = li (mod 4); the rows i are taken bottom-up in the same order by every column, so row i of R
+// is a broadcast read, and X(i, j) = -(sum_{i<l<=j} R(i, l) X(l, j)) / R(i, i) needs only the
+// X(l, j) the lane wrote itself.  LDS: S and L (2 K^2), then dk, 1/R(i,i), perm.
+__device__ __forceinline__ void pchol64(const CholJob& J, double* sm) {
+  const int K = J.K, tid = threadIdx.x;
+  double* S = sm;
+  double* Lc = S + K * K;
+  double* dk = Lc + K * K;
+  double* xd = dk + K;
+  int* perm = reinterpret_cast<int*>(xd + K);
+  int* mark = reinterpret_cast<int*>(xd);  // free until the inverse
+  __shared__ CholShared sh;
+  const int q = chol_phase_blk(J.g, K, J.tol, S, Lc, dk, perm, mark, sh);
+  for (int e = tid; e < q * q; e += 256) {
+    const int l = e % q, i = e / q;
+    S[l + K * i] = l >= i ? Lc[i * K + perm[l]] : 0.0;
+  }
+  for (int i = tid; i < q; i += 256) xd[i] = 1.0 / Lc[i * K + perm[i]];
+  __syncthreads();
+  double* Xs = Lc;  // X(l, j) at Xs[l + K j]
+  const int j = tid >> 2, li = tid & 3;
+  for (int i = q - 1; i >= 0; --i) {
+    if (j < q && i <= j) {  // the same for the four lanes of a column
+      double part = 0.0;
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        const int l = li + 4 * t, lc = min(l, j);
+        const double rv = S[lc + K * i], xv = Xs[lc + K * j];
+        part = (l > i && l <= j) ? fma(rv, xv, part) : part;
+      }
+      part += dpp_f64<0xB1>(part);
+      part += dpp_f64<0x4E>(part);
+      if (li == (i & 3)) Xs[i + K * j] = i == j ? xd[i] : -part * xd[i];
+    }
+  }
+  // W = P X: every row of column j written once (perm is a permutation of 0..K-1)
+  if (j < q) {
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int l = li + 4 * t;
+      if (l < K) J.w[perm[l] + (long)K * j] = l <= j ? Xs[l + K * j] : 0.0;
+    }
+  }
+  if (tid == 0 && J.q) *J.q = q;
+}
+
 template <bool SMEM, int NT>
 __global__ __launch_bounds__(NT) void k_pchol(JobBatch<CholJob> jobs) {
   extern __shared__ double sm[];
@@ -1125,6 +1319,10 @@ __global__ __launch_bounds__(NT) void k_pchol(JobBatch<CholJob> jobs) {
   const int K = J.K;
   const int tid = threadIdx.x;
   if (K <= 0) { if (tid == 0 && J.q) *J.q = 0; return; }
+  if constexpr (NT == 256) {
+    pchol64(J, sm);
+    return;
+  }
   double* S = SMEM ? sm : J.work;
   double* Rp = SMEM ? sm : J.work + (size_t)K * K;  // R (q x q, ld K, upper) then X = R^-1 below it
   double* base = SMEM ? sm + (size_t)K * K : sm;
@@ -1208,7 +1406,8 @@ hipError_t pchol_batched(const JobBatch<CholJob>& jobs_dev, int count, int Kmax,
   if (Kmax > EIG_MAX) return hipErrorInvalidValue;
   const size_t extra = (size_t)Kmax * 16 + 32 * 8 + (size_t)Kmax * 4 + 64;
   const size_t shm = (size_t)Kmax * Kmax * 8 + extra;
-  if (Kmax <= 64) return launch_gram<true, 256>(k_pchol<true, 256>, jobs_dev, count, shm, s);
+  if (Kmax <= 64)
+    return launch_gram<true, 256>(k_pchol<true, 256>, jobs_dev, count, (size_t)Kmax * Kmax * 16 + (size_t)Kmax * 20 + 64, s);
   if (Kmax <= EIG_LDS_MAX) return launch_gram<true, 512>(k_pchol<true, 512>, jobs_dev, count, shm, s);
   return launch_gram<false, 1024>(k_pchol<false, 1024>, jobs_dev, count, extra, s);
 }
@@ -1230,56 +1429,62 @@ __device__ double block_max256(double v, double* red) {
   return fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
 }
 
-// out[r, c] for the (up to) 4 x 4 block of thread (ti, tj): sum_k A[r + K k] B[k + K c]
-__device__ __forceinline__ void ns_mm(const double* A, const double* B, int K, int ti, int tj, double o[4][4]) {
+// The iterates are padded to 64 x 64 (G with the identity, so the padding stays the identity)
+// and kept in LDS with leading dimension NS_LD; the 64 x 64 x 64 products run on the FP64 matrix
+// cores, wave w computing rows 16 w .. 16 w + 15 as four 16 x 16 blocks.  Y, Z and T are
+// functions of G, so they are symmetric and commute: the second factor is read as its transpose
+// and the product is stored transposed, which keeps every LDS access contiguous along the 16
+// lanes of a block row (the difference is of the order of the rounding of the products).
+constexpr int NS_LD = 72;  // 144 dwords: the four lane groups of a read start 16 banks apart
+
+// acc[cb][v] = (A B)[16 w + c + 4 v][16 cb + r] for lane (r, c) = (lane % 16, lane / 16)
+__device__ __forceinline__ void ns_mm64(const double* A, const double* B, d4_t acc[4]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r = lane & 15, c = lane >> 4;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int cb = 0; cb < 4; ++cb) acc[cb] = d4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int k0 = 0; k0 < 64; k0 += 4) {
+    const double a = A[(16 * w + r) + NS_LD * (k0 + c)];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) o[a][b] = 0.0;
-  for (int k = 0; k < K; ++k) {
-    double av[4], bv[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int r = ti + 16 * a;
-      av[a] = r < K ? A[r + K * k] : 0.0;
-    }
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int cc = tj + 16 * b;
-      bv[b] = cc < K ? B[k + K * cc] : 0.0;
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) o[a][b] = fma(av[a], bv[b], o[a][b]);
+    for (int cb = 0; cb < 4; ++cb) acc[cb] = mfma16(a, B[(16 * cb + r) + NS_LD * (k0 + c)], acc[cb]);
   }
+}
+// stores acc transposed: M[16 cb + r][16 w + c + 4 v] (column-major, ld NS_LD)
+__device__ __forceinline__ void ns_store(double* M, const d4_t acc[4]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r = lane & 15, c = lane >> 4;
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) M[(16 * cb + r) + NS_LD * (16 * w + c + 4 * v)] = acc[cb][v];
 }
 
 __global__ __launch_bounds__(256) void k_ns_isqrt(JobBatch<NsJob> jobs) {
   extern __shared__ double sm[];
   __shared__ double red[4];
   const NsJob J = jobs.j[blockIdx.x];
-  const int K = J.K, KK = K * K, tid = threadIdx.x;
-  const int ti = tid & 15, tj = tid >> 4;  // rows ti + 16 a, columns tj + 16 b
+  const int K = J.K, tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6, r = lane & 15, c = lane >> 4;
   double* Y = sm;
-  double* Z = sm + KK;
-  double* T = sm + 2 * KK;
+  double* Z = sm + 64 * NS_LD;
+  double* T = sm + 2 * 64 * NS_LD;
   if (K <= 0) {
     if (tid == 0) *J.ok = 1;
     return;
   }
   double e2 = 0.0;
-  for (int e = tid; e < KK; e += 256) {
-    const int i = e % K, j = e / K;
-    const double g = J.g[e], d = g - (i == j ? 1.0 : 0.0);
-    Y[e] = g;
-    Z[e] = i == j ? 1.0 : 0.0;
-    e2 += d * d;
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int i = e & 63, j = e >> 6;
+    const double id = i == j ? 1.0 : 0.0;
+    const double g = (i < K && j < K) ? J.g[i + K * j] : id;
+    Y[i + NS_LD * j] = g;
+    Z[i + NS_LD * j] = id;
+    e2 += (g - id) * (g - id);
   }
-  // ||G - I||_F^2 as a block sum (the max of non-negative per-wave sums would not do: sum them)
+  // ||G - I||_F^2 as a block sum
   for (int o = 32; o > 0; o >>= 1) e2 += __shfl_xor(e2, o);
-  __syncthreads();
-  if ((tid & 63) == 0) red[tid >> 6] = e2;
+  if (lane == 0) red[w] = e2;
   __syncthreads();
   const double fro2 = red[0] + red[1] + red[2] + red[3];
   if (!(fro2 <= 0.25)) {  // uniform
@@ -1288,53 +1493,45 @@ __global__ __launch_bounds__(256) void k_ns_isqrt(JobBatch<NsJob> jobs) {
   }
   bool done = false;
   for (int it = 0; it < 10 && !done; ++it) {
-    double o[4][4];
-    ns_mm(Z, Y, K, ti, tj, o);  // T = 1.5 I - 0.5 Z Y
+    d4_t o[4];
+    ns_mm64(Z, Y, o);  // T = 1.5 I - 0.5 Z Y
     double dev = 0.0;
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int r = ti + 16 * a, cc = tj + 16 * b;
-        if (r < K && cc < K) {
-          const double t = (r == cc ? 1.5 : 0.0) - 0.5 * o[a][b];
-          T[r + K * cc] = t;
-          dev = fmax(dev, fabs(t - (r == cc ? 1.0 : 0.0)));
-        }
+      for (int v = 0; v < 4; ++v) {
+        const bool dg = (16 * w + c + 4 * v) == (16 * cb + r);
+        const double t = (dg ? 1.5 : 0.0) - 0.5 * o[cb][v];
+        o[cb][v] = t;
+        dev = fmax(dev, fabs(t - (dg ? 1.0 : 0.0)));
       }
-    dev = block_max256(dev, red);  // includes the barrier that publishes T
-    double y[4][4], z[4][4];
-    ns_mm(Y, T, K, ti, tj, y);
-    ns_mm(T, Z, K, ti, tj, z);
-    __syncthreads();
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int r = ti + 16 * a, cc = tj + 16 * b;
-        if (r < K && cc < K) {
-          Y[r + K * cc] = y[a][b];
-          Z[r + K * cc] = z[a][b];
-        }
-      }
+    ns_store(T, o);
+    for (int s2 = 32; s2 > 0; s2 >>= 1) dev = fmax(dev, __shfl_xor(dev, s2));
+    __syncthreads();  // T published; every wave is done with this iteration's reads of red
+    if (lane == 0) red[w] = dev;
+    d4_t y[4], z[4];
+    ns_mm64(Y, T, y);
+    ns_mm64(T, Z, z);
+    __syncthreads();  // every read of Y, Z, T is done, and red is published
+    dev = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    ns_store(Y, y);
+    ns_store(Z, z);
     __syncthreads();
     // T - I is of the order of the remaining error and the step squares it: from 1e-10 this step
     // has brought Z to G^(-1/2) to working precision (the products' rounding, ~K eps, is larger
     // than what a further step would remove)
     done = dev <= 1e-10;
   }
-  for (int e = tid; e < KK; e += 256) J.w[e] = Z[e];
+  for (int e = tid; e < K * K; e += 256) J.w[e] = Z[(e % K) + NS_LD * (e / K)];
   if (tid == 0) *J.ok = done ? 1 : 0;
 }
 
 hipError_t ns_isqrt_batched(const JobBatch<NsJob>& jobs, int count, int Kmax, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   if (count > kBatchJobs || Kmax > kNsMax) return hipErrorInvalidValue;
-  const size_t shm = (size_t)3 * Kmax * Kmax * sizeof(double);
-  if (shm > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_ns_isqrt, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    if (e != hipSuccess) return e;
-  }
+  const size_t shm = (size_t)3 * 64 * NS_LD * sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void*)k_ns_isqrt, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_ns_isqrt, dim3(count), dim3(256), shm, s, jobs);
   return hipGetLastError();
 }
@@ -1370,9 +1567,22 @@ __global__ __launch_bounds__(NT) void k_psd_eig(JobBatch<PsdJob> jobs) {
   // was rotated away, as float bits (non-negative floats order like their bit patterns)
   __shared__ unsigned int offmax[3];
   if (tid == 0) offmax[0] = offmax[1] = offmax[2] = 0u;
-  const int q = chol_phase<NT>(J.g, K, J.ctol, S, dk, perm, slot, rank, sh);
+  int q;
+  if constexpr (NT == 256) {
+    // blocked factorisation with L in its own LDS block (after the job's scratch), then
+    // X = R^T in pivot order: X[l][k] = R(k, l) = L(perm[l], k) (l >= k), 0 above the diagonal
+    double* Lc = base + 2 * K + 32;
+    q = chol_phase_blk(J.g, K, J.ctol, S, Lc, dk, perm, rank, sh);
+    for (int e = tid; e < K * q; e += NT) {
+      const int l = e % K, k = e / K;
+      X[e] = l >= k ? Lc[k * K + perm[l]] : 0.0;
+    }
+  } else {
+    q = chol_phase<NT>(J.g, K, J.ctol, S, dk, perm, slot, rank, sh);
+  }
   // X = R^T in pivot order: X[l][k] = R(k, l) (l >= k), 0 above the diagonal
-  if (SMEM) {
+  if constexpr (NT == 256) {
+  } else if (SMEM) {
     constexpr int GMAX = (KMAX * KMAX + NT - 1) / NT;
     double reg[GMAX];
 #pragma unroll
@@ -1519,7 +1729,8 @@ hipError_t psd_eig_batched(const JobBatch<PsdJob>& jobs_dev, int count, int Kmax
   if (Kmax > EIG_MAX) return hipErrorInvalidValue;
   const size_t extra = (size_t)Kmax * 8 + 32 * 8 + (size_t)Kmax * 8 + 64;
   const size_t shm = (size_t)Kmax * Kmax * 8 + extra;
-  if (Kmax <= 64) return launch_gram<true, 256>(k_psd_eig<true, 256>, jobs_dev, count, shm, s);
+  // K <= 64: the factor L in its own block after the scratch
+  if (Kmax <= 64) return launch_gram<true, 256>(k_psd_eig<true, 256>, jobs_dev, count, shm + (size_t)Kmax * Kmax * 8, s);
   if (Kmax <= EIG_LDS_MAX) return launch_gram<true, 512>(k_psd_eig<true, 512>, jobs_dev, count, shm, s);
   return launch_gram<false, 1024>(k_psd_eig<false, 1024>, jobs_dev, count, extra, s);
 }
@@ -1553,25 +1764,6 @@ constexpr int TRI_CPT = kTriMax / TRI_NW;    // columns of A and Q per thread
 constexpr int TRI_LD = kTriMax + 1;   // odd leading dimension: the rows of a column sit in distinct banks
 constexpr double kTiny = 2.2250738585072014e-308;
 
-// Sum / maximum over the 64 lanes (DPP within rows of 16, then the four row results read into
-// scalars); every lane receives the result, and the order of the additions is fixed.
-__device__ __forceinline__ double readlane_f64(double v, int lane) {
-  const long long b = __double_as_longlong(v);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)b, lane);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), lane);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-__device__ __forceinline__ double wave_sum_f64(double v) {
-  v = group_sum(v, 16);
-  return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
-}
-__device__ __forceinline__ double wave_max_f64(double v) {
-  v = fmax(v, dpp_f64<0xB1>(v));
-  v = fmax(v, dpp_f64<0x4E>(v));
-  v = fmax(v, dpp_f64<0x141>(v));
-  v = fmax(v, dpp_f64<0x140>(v));
-  return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)), fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
-}
 // Minimum over the four lanes of a quad (DPP quad permutations).
 __device__ __forceinline__ int quad_min(int v) {
   v = min(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false));
