@@ -115,6 +115,7 @@ struct tp_symbol {
   bool arena = false;    // memory in a batched worker's workspace (nothing to free)
   double* weights = nullptr;   // R (device)
   void* factors[3] = {nullptr, nullptr, nullptr};  // n x R (device, T)
+  void* factors_w[3] = {nullptr, nullptr, nullptr};  // the same with column k scaled by weights[k]
   double* tau = nullptr;       // K
   double* w = nullptr;         // K
   double* lam[3] = {nullptr, nullptr, nullptr};
@@ -975,7 +976,7 @@ tp_status combo_impl(tp_ctx* c, const Term* terms, int nt, tp_tensor* y, double 
     T* Vh[3];
     T* C;
     const T* S[3];
-    const double* w;
+    const T* Sw[3];  // the factors with the weights folded in
     T* A[3];
   };
   std::vector<Prep> pr(nterm);
@@ -1015,16 +1016,21 @@ tp_status combo_impl(tp_ctx* c, const Term* terms, int nt, tp_tensor* y, double 
   for (int t = 0; t < nterm; ++t) {
     Prep& P = pr[t];
     const tp_tensor* x = tv[t].x;
-    size_t csz = (size_t)P.r[0] * P.r[1] * P.r[2];
-    TPCHK(wsalloc(c, csz, &P.C));
-    HIPCHK((convert<T, T>((const T*)x->core, P.C, (long)csz, c->stream)));
+    // the core is only read here (a y aliasing x receives its core from the HOSVD after the last read)
+    P.C = (T*)x->core;
     if (tv[t].sym) {
       P.R = tv[t].sym->R;
-      for (int m = 0; m < d; ++m) P.S[m] = (const T*)tv[t].sym->factors[m];
-      P.w = tv[t].sym->weights;
+      for (int m = 0; m < d; ++m) {
+        P.S[m] = (const T*)tv[t].sym->factors[m];
+        P.Sw[m] = (const T*)tv[t].sym->factors_w[m];
+      }
     } else {
       P.R = 1;
-      for (int m = 0; m < d; ++m) TPCHK(unit_symbol<T>(c, x->n[m], &P.S[m], &P.w));
+      for (int m = 0; m < d; ++m) {
+        const double* w1 = nullptr;
+        TPCHK(unit_symbol<T>(c, x->n[m], &P.S[m], &w1));
+        P.Sw[m] = P.S[m];
+      }
     }
     // A_m[i + r_m (k + R q)] = sum_x Vh_m(x,i) S_m(x,k) Om_m(x,q), the modes in one launch
     GemmArgs<T, T, T, Tacc> ga[3];
@@ -1078,7 +1084,7 @@ tp_status combo_impl(tp_ctx* c, const Term* terms, int nt, tp_tensor* y, double 
       g.M = n; g.N = Qs; g.K = r[m] * R;
       g.alpha = tv[t].coef; g.beta = t == 0 ? 0.0 : 1.0;
       g.fsA = true; g.FA.x1 = P.Vh[m]; g.FA.ld1 = n; g.FA.r1 = r[m];
-      g.FA.x2 = P.S[m]; g.FA.ld2 = n; g.FA.w = P.w;
+      g.FA.x2 = P.Sw[m]; g.FA.ld2 = n;
       g.B = tt; g.ldb = r[m] * R;
       g.C = Y[m]; g.ldc = n;
     }
@@ -1121,7 +1127,7 @@ tp_status combo_impl(tp_ctx* c, const Term* terms, int nt, tp_tensor* y, double 
       gp.M = q[m]; gp.N = r[m] * R; gp.K = n;
       gp.A = Qt[m]; gp.lda = n; gp.tA = true;
       gp.fsB = true; gp.FB.x1 = P.Vh[m]; gp.FB.ld1 = n; gp.FB.r1 = r[m];
-      gp.FB.x2 = P.S[m]; gp.FB.ld2 = n; gp.FB.w = (m == d - 1) ? P.w : nullptr;
+      gp.FB.x2 = (m == d - 1) ? P.Sw[m] : P.S[m]; gp.FB.ld2 = n;
       gp.C = Pm[m]; gp.ldc = q[m];
     }
     TPCHK(run_group(c, gps, d));
@@ -1239,7 +1245,7 @@ tp_status inner_sym_impl(tp_ctx* c, const tp_tensor* x, const tp_symbol* S, cons
     g.M = rx[m]; g.N = ry[m] * R; g.K = n;
     g.A = Vx[m]; g.lda = n; g.tA = true;
     g.fsB = true; g.FB.x1 = Vy[m]; g.FB.ld1 = n; g.FB.r1 = ry[m];
-    g.FB.x2 = (const T*)S->factors[m]; g.FB.ld2 = n; g.FB.w = (m == d - 1) ? S->weights : nullptr;
+    g.FB.x2 = (const T*)(m == d - 1 ? S->factors_w[m] : S->factors[m]); g.FB.ld2 = n;
     g.C = G[m]; g.ldc = rx[m];
   }
   TPCHK(run_group(c, gs, d));
@@ -1452,6 +1458,19 @@ tp_status sym_alloc(tp_ctx* c, tp_symbol* s, size_t count, T** p) {
   return TP_OK;
 }
 
+// factors_w[m] = factors[m] diag(weights): the face-split operands that carry the weights read
+// them from there (one product per element instead of a third load and an FP64 multiply)
+template <typename T>
+tp_status build_weighted(tp_ctx* c, tp_symbol* s) {
+  for (int m = 0; m < s->d; ++m) {
+    T* F = nullptr;
+    TPCHK(sym_alloc(c, s, (size_t)s->n[m] * s->R, &F));
+    HIPCHK(scale_cols_copy<T>((const T*)s->factors[m], s->n[m], s->R, s->weights, F, c->stream));
+    s->factors_w[m] = F;
+  }
+  return TP_OK;
+}
+
 template <typename T>
 tp_status build_factors(tp_ctx* c, tp_symbol* s) {
   for (int m = 0; m < s->d; ++m) {
@@ -1475,7 +1494,7 @@ tp_status build_factors(tp_ctx* c, tp_symbol* s) {
     HIPCHK(hipMemcpyAsync(s->weights + (size_t)blk * s->K, s->w, sizeof(double) * s->K, hipMemcpyDeviceToDevice, c->stream));
   if (s->kind == 0 && s->R > s->d * s->K)
     HIPCHK(hipMemcpyAsync(s->weights + (size_t)s->d * s->K, &s->c0, sizeof(double), hipMemcpyHostToDevice, c->stream));
-  return TP_OK;
+  return build_weighted<T>(c, s);
 }
 
 // Rank-r preconditioner of the Sec. 6 tests: the truncated HOSVD of the exponential sum (a
@@ -1550,6 +1569,8 @@ tp_status recompress_pre(tp_ctx* c, tp_symbol* s, int r) {
   HIPCHK(hipStreamSynchronize(c->stream));  // the host vector and the workspace are released here
   s->R = R;
   s->tucker = r;
+  // unit weights: the weighted factors are the factors
+  for (int m = 0; m < d; ++m) s->factors_w[m] = s->factors[m];
   return TP_OK;
 }
 
@@ -2710,7 +2731,9 @@ extern "C" tp_status tp_workspace_query(const tp_symbol_desc* D, const tp_pcg_op
   const double sum = d * nmax * c2 * 8 * 4 + 4.0 * d * c2 * c2 * 8 + 6.0 * pw(c2) * 8 + d * nmax * c2 * T;
   // least-squares fits of the symbols (design matrices of the candidates)
   const double fits = 15.0 * 1000 * 64 * 8 * 2 + 15.0 * 64 * 64 * 8 * 4;
-  const double total = tens + fromcp + std::max(std::max(combo, isym), std::max(sum, fits)) + (64 << 20);
+  // the operator and preconditioner symbols (factors and weighted factors) in a worker's arena
+  const double syms = 4.0 * d * nmax * R * T;
+  const double total = tens + fromcp + syms + std::max(std::max(combo, isym), std::max(sum, fits)) + (64 << 20);
   *bytes = (size_t)(1.25 * total);
   return TP_OK;
 }

@@ -33,9 +33,7 @@ template <typename T>
 __device__ __forceinline__ T fs_load(const FaceSplit<T>& F, int row, int c, float inv) {
   int a, b;
   fast_divmod(c, F.r1, inv, b, a);
-  T v = F.x1[row + (long)F.ld1 * a] * F.x2[row + (long)F.ld2 * b];
-  if (F.w) v = (T)((double)v * F.w[b]);
-  return v;
+  return F.x1[row + (long)F.ld1 * a] * F.x2[row + (long)F.ld2 * b];
 }
 
 template <typename TA, typename TB, typename TC, typename Tacc>
@@ -174,15 +172,14 @@ constexpr int MNE = MBK / 4;  // elements of each operand per thread per stage
 enum { OP_N = 0, OP_T = 1, OP_FS = 2 };
 
 // The raw loads of one operand's share of a stage.  They are issued without a bounds branch
-// (indices clamped into the matrix) and combined - bounds mask, face-split product, weight,
-// conversion to the accumulation type - only when the stage is written to LDS: a load under a
+// (indices clamped into the matrix) and combined - bounds mask, face-split product, conversion
+// to the accumulation type - only when the stage is written to LDS: a load under a
 // divergent branch, or an arithmetic use of a loaded value, makes the compiler wait for it on the
 // spot, while these stay in flight through the previous stage's MFMAs.
 template <typename T, int KIND>
 struct OpRegs {
   T x[MNE];
   T y[KIND == OP_FS ? MNE : 1];
-  double w[KIND == OP_FS ? MNE : 1];
   unsigned ok;
 };
 
@@ -216,7 +213,6 @@ __device__ __forceinline__ void op_fetch(const T* P, int ld, const FaceSplit<T>&
       fast_divmod(col, F.r1, inv, b, a);
       r.x[i] = F.x1[row + (long)F.ld1 * a];
       r.y[i] = F.x2[row + (long)F.ld2 * b];
-      r.w[i] = F.w ? F.w[b] : 1.0;
     } else {
       r.x[i] = P[row + (long)ld * col];
     }
@@ -227,9 +223,7 @@ template <typename Tacc, typename T, int KIND>
 __device__ __forceinline__ Tacc op_value(const OpRegs<T, KIND>& r, int i) {
   Tacc v;
   if (KIND == OP_FS) {
-    T p = r.x[i] * r.y[i];
-    p = (T)((double)p * r.w[i]);
-    v = (Tacc)p;
+    v = (Tacc)(r.x[i] * r.y[i]);
   } else {
     v = (Tacc)r.x[i];
   }
@@ -2255,6 +2249,22 @@ hipError_t scale_cols_d(double* a, int rows, int cols, int ld, const double* sca
   hipLaunchKernelGGL(k_scale_cols, dim3((cnt + 255) / 256), dim3(256), 0, s, a, rows, cols, ld, scale);
   return hipGetLastError();
 }
+
+template <typename T>
+__global__ void k_scale_cols_copy(const T* in, int rows, int cols, const double* w, T* out) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)rows * cols) return;
+  out[e] = (T)((double)in[e] * w[e / rows]);
+}
+template <typename T>
+hipError_t scale_cols_copy(const T* in, int rows, int cols, const double* w, T* out, hipStream_t s) {
+  const long n = (long)rows * cols;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_scale_cols_copy<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, rows, cols, w, out);
+  return hipGetLastError();
+}
+template hipError_t scale_cols_copy<float>(const float*, int, int, const double*, float*, hipStream_t);
+template hipError_t scale_cols_copy<double>(const double*, int, int, const double*, double*, hipStream_t);
 
 __global__ void k_eig_inv_sqrt(const double* E, const double* w, int K, int q, double* W) {
   long e = (long)blockIdx.x * blockDim.x + threadIdx.x;

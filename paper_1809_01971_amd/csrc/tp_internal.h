@@ -6,14 +6,13 @@
 
 namespace tpk {
 
-// Face-split operand: F[row, c] = X1[row + ld1*(c % r1)] * X2[row + ld2*(c / r1)] * (w ? w[c / r1] : 1).
+// Face-split operand: F[row, c] = X1[row + ld1*(c % r1)] * X2[row + ld2*(c / r1)].
 // It stands for the Hadamard products u_k (.) x_j of the low-rank matrix-vector
-// product without forming them.
+// product without forming them (weights of the terms are folded into X2 beforehand).
 template <typename T>
 struct FaceSplit {
   const T* x1 = nullptr;
   const T* x2 = nullptr;
-  const double* w = nullptr;
   int ld1 = 0, ld2 = 0, r1 = 1;
 };
 
@@ -131,6 +130,9 @@ template <typename T>
 hipError_t permute3(const T* in, int d0, int d1, int d2, T* out, int p0, int p1, int p2, hipStream_t s);
 // Columns scaled: out[:,j] = in[:,j] * scale[j] (rows x cols, ld), in place allowed.
 hipError_t scale_cols_d(double* a, int rows, int cols, int ld, const double* scale, hipStream_t s);
+// out[:, j] = in[:, j] * w[j] (rows x cols, both with leading dimension rows), the product in FP64
+template <typename T>
+hipError_t scale_cols_copy(const T* in, int rows, int cols, const double* w, T* out, hipStream_t s);
 // W = E[:, 0:q] * diag(1/sqrt(w)) for the leading q eigenpairs; K rows, ld K.
 hipError_t eig_inv_sqrt(const double* E, const double* w, int K, int q, double* W, hipStream_t s);
 // out[0] = sum(a[i]*b[i]) in FP64; part: device scratch of 256 doubles for per-workgroup sums.
