@@ -1538,6 +1538,64 @@ hipError_t ns_isqrt_batched(const JobBatch<NsJob>& jobs, int count, int Kmax, hi
 // Jacobi step: the column pairs of a step are disjoint, the 4 to 16 lanes that share a pair
 // hold its rows in registers and add their partial dot products with DPP.
 // ---------------------------------------------------------------------------------------------
+// One-sided Jacobi on the q <= 32 columns of X (K <= 4 RT rows, ld K) by one wave: 4 lanes per
+// column pair hold the rows li + 4 t (t < RT) of both columns in registers and add their partial
+// dot products with two quad DPP steps.  A wave's LDS accesses are performed in order, so the
+// rounds need no barrier (the pairs of a round are disjoint).  The same rotation rule and stopping
+// test as the workgroup version; returns when the sweeps have converged.
+template <int RT>
+__device__ __forceinline__ void jacobi_wave(double* X, int K, int q, double jtol) {
+  const int lane = threadIdx.x & 63;
+  const int qp = q + (q & 1), np = qp / 2;
+  const int pr = lane >> 2, li = lane & 3;
+  const double jtol2 = jtol * jtol;
+  for (int sweep = 0; sweep < 40 && q > 1; ++sweep) {
+    float mx = 0.0f;  // the largest squared relative off-diagonal rotated away in this sweep
+    for (int st = 0; st < qp - 1; ++st) {
+      int p = 0, r = 0;
+      bool valid = pr < np;
+      if (valid) {
+        p = rr_index(pr, st, qp);
+        r = rr_index(qp - 1 - pr, st, qp);
+        if (p > r) { const int t = p; p = r; r = t; }
+        valid = r < q;
+      }
+      double xa[RT], xb[RT], al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const int i = li + 4 * t;
+        const bool in = valid && i < K;
+        const int ic = min(i, K - 1);
+        const double a = X[ic + K * p], b = X[ic + K * r];
+        xa[t] = in ? a : 0.0;
+        xb[t] = in ? b : 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < RT; ++t) { al += xa[t] * xa[t]; be += xb[t] * xb[t]; ga += xa[t] * xb[t]; }
+      al += dpp_f64<0xB1>(al); be += dpp_f64<0xB1>(be); ga += dpp_f64<0xB1>(ga);
+      al += dpp_f64<0x4E>(al); be += dpp_f64<0x4E>(be); ga += dpp_f64<0x4E>(ga);
+      const double ab = al * be;
+      if (valid && ga * ga > jtol2 * ab) {  // the same for the four lanes of a pair
+        const double zeta = (be - al) / (2.0 * ga);
+        const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = rsqrt(1.0 + t * t), sn = c * t;
+#pragma unroll
+        for (int u = 0; u < RT; ++u) {
+          const int i = li + 4 * u;
+          if (i < K) {
+            X[i + K * p] = c * xa[u] - sn * xb[u];
+            X[i + K * r] = sn * xa[u] + c * xb[u];
+          }
+        }
+        mx = fmaxf(mx, (float)((ga * ga) / ab));
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+    if (mx == 0.0f || (double)mx * (double)q <= jtol) break;  // uniform
+  }
+}
+
 template <bool SMEM, int NT>
 __global__ __launch_bounds__(NT) void k_psd_eig(JobBatch<PsdJob> jobs) {
   extern __shared__ double sm[];
@@ -1602,7 +1660,18 @@ __global__ __launch_bounds__(NT) void k_psd_eig(JobBatch<PsdJob> jobs) {
     }
   }
   __syncthreads();
-  // one-sided Jacobi on the q columns of X (round-robin pairs, L lanes per pair)
+  // one-sided Jacobi on the q columns of X (round-robin pairs, L lanes per pair); up to 32 columns
+  // of up to 64 rows (the least-squares fits of the symbols) by one wave without barriers
+  bool jdone = false;
+  if constexpr (NT == 256) {
+    if (q <= 32 && K <= 64) {
+      if ((tid >> 6) == 0) {
+        if (K <= 32) jacobi_wave<8>(X, K, q, J.jtol);
+        else jacobi_wave<16>(X, K, q, J.jtol);
+      }
+      jdone = true;
+    }
+  }
   const int qp = q + (q & 1), np = qp / 2;
   const int L = lanes_for(NT, np);
   const int lg = L == 16 ? 4 : (L == 8 ? 3 : (L == 4 ? 2 : (L == 2 ? 1 : 0)));
@@ -1618,7 +1687,7 @@ __global__ __launch_bounds__(NT) void k_psd_eig(JobBatch<PsdJob> jobs) {
   // row blocks at every load and store.  A lane still covers the rows li + L t, t < RMAX.
   const int rot = pr & (RMAX - 1);
   const double jtol2 = J.jtol * J.jtol;
-  for (int sweep = 0; sweep < 40 && q > 1; ++sweep) {
+  for (int sweep = 0; sweep < 40 && q > 1 && !jdone; ++sweep) {
     unsigned int* chg = &offmax[sweep % 3];
     if (tid == 0) offmax[(sweep + 1) % 3] = 0u;  // last read two sweeps ago
     for (int st = 0; st < qp - 1; ++st) {
