@@ -299,7 +299,11 @@ int gemm_class() {
 // ------------------------------------------------------------------------------ GEMM helpers
 // Up to kGemmGroup independent products with the same operand kinds in one launch.  Few output
 // tiles and a long contraction: K is split over workgroups (chunks of at least 64) so that about
-// 512 workgroups share the launch; the partial sums are added by a second kernel.
+// kSplitTarget workgroups share the launch; the partial sums are added by a second kernel.
+// Workgroups a split-K launch aims at (about three per compute unit; 512 and 1024 measured within
+// 1 % of it on the n = 2047 mixed solve)
+constexpr long kSplitTarget = 768;
+
 template <typename TA, typename TB, typename TC, typename Tacc>
 tp_status run_group(tp_ctx* c, const GemmArgs<TA, TB, TC, Tacc>* g0, int count) {
   GemmArgs<TA, TB, TC, Tacc> g[kGemmGroup];
@@ -312,8 +316,8 @@ tp_status run_group(tp_ctx* c, const GemmArgs<TA, TB, TC, Tacc>* g0, int count) 
   size_t mark = c->ws_top;
   bool split = false;
   for (int i = 0; i < count; ++i) {
-    if (tiles >= 256 || g[i].K < 128 || g[i].M <= 0 || g[i].N <= 0) continue;
-    int splits = (int)std::min<long>((g[i].K + 63) / 64, std::max<long>(1, 512 / tiles));
+    if (tiles >= kSplitTarget / 2 || g[i].K < 128 || g[i].M <= 0 || g[i].N <= 0) continue;
+    int splits = (int)std::min<long>((g[i].K + 63) / 64, std::max<long>(1, kSplitTarget / tiles));
     if (splits < 2) continue;
     Tacc* part = nullptr;
     if (wsalloc(c, (size_t)g[i].batch * splits * g[i].M * g[i].N, &part) == TP_OK) {

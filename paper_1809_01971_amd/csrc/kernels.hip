@@ -1259,9 +1259,9 @@ __device__ __forceinline__ double chol_r(const double* S, const double* dk, cons
 // lane keeps the X(l, j) of its own residue class, so no barrier is needed.
 // K <= 64 on 256 threads: the blocked factorisation, then X = R^-1 with R transposed in pivot
 // order (RT[l + K i] = R(i, l)).  Four lanes per column j of X, lane li holding the rows
-// l = li (mod 4); the rows i are taken bottom-up in the same order by every column, so row i of R
-// is a broadcast read, and X(i, j) = -(sum_{i<l<=j} R(i, l) X(l, j)) / R(i, i) needs only the
-// X(l, j) the lane wrote itself.  LDS: S and L (2 K^2), then dk, 1/R(i,i), perm.
+// l = li (mod 4) in registers; the rows i are taken bottom-up in the same order by every column,
+// so row i of R is a broadcast read, and X(i, j) = -(sum_{i<l<=j} R(i, l) X(l, j)) / R(i, i)
+// needs only the X(l, j) the lane holds itself.  LDS: S and L (2 K^2), then dk, 1/R(i,i), perm.
 __device__ __forceinline__ void pchol64(const CholJob& J, double* sm) {
   const int K = J.K, tid = threadIdx.x;
   double* S = sm;
@@ -1278,20 +1278,27 @@ __device__ __forceinline__ void pchol64(const CholJob& J, double* sm) {
   }
   for (int i = tid; i < q; i += 256) xd[i] = 1.0 / Lc[i * K + perm[i]];
   __syncthreads();
-  double* Xs = Lc;  // X(l, j) at Xs[l + K j]
+  // X(li + 4 t, j) in xr[t]; the row loop is unrolled so that the owner's write has a fixed index
   const int j = tid >> 2, li = tid & 3;
-  for (int i = q - 1; i >= 0; --i) {
-    if (j < q && i <= j) {  // the same for the four lanes of a column
+  double xr[16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) xr[t] = 0.0;
+#pragma unroll
+  for (int i = 63; i >= 0; --i) {
+    if (i < q && j < q && i <= j) {  // the same for the four lanes of a column
       double part = 0.0;
 #pragma unroll
       for (int t = 0; t < 16; ++t) {
-        const int l = li + 4 * t, lc = min(l, j);
-        const double rv = S[lc + K * i], xv = Xs[lc + K * j];
-        part = (l > i && l <= j) ? fma(rv, xv, part) : part;
+        if (4 * t + 3 > i) {  // rows l = li + 4 t <= i never contribute
+          const int l = li + 4 * t;
+          const double rv = S[min(l, j) + K * i];
+          part = (l > i && l <= j) ? fma(rv, xr[t], part) : part;
+        }
       }
       part += dpp_f64<0xB1>(part);
       part += dpp_f64<0x4E>(part);
-      if (li == (i & 3)) Xs[i + K * j] = i == j ? xd[i] : -part * xd[i];
+      const double x = i == j ? xd[i] : -part * xd[i];
+      if (li == (i & 3)) xr[i >> 2] = x;
     }
   }
   // W = P X: every row of column j written once (perm is a permutation of 0..K-1)
@@ -1299,7 +1306,7 @@ __device__ __forceinline__ void pchol64(const CholJob& J, double* sm) {
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
       const int l = li + 4 * t;
-      if (l < K) J.w[perm[l] + (long)K * j] = l <= j ? Xs[l + K * j] : 0.0;
+      if (l < K) J.w[perm[l] + (long)K * j] = l <= j ? xr[t] : 0.0;
     }
   }
   if (tid == 0 && J.q) *J.q = q;
