@@ -55,6 +55,7 @@ CLASSES = {
     "gemm_f32": ("k_gemm_mfma<float, float, float, float>", "mfma", PEAK["fp32_tflops"], "TFLOP/s"),
     "gemm_f32_f64": ("k_gemm_mfma<float, float, double, double>", "mfma", PEAK["fp64_tflops"], "TFLOP/s"),
     "gemm_f64_f32": ("k_gemm_mfma<double, double, float, double>", "mfma", PEAK["fp64_tflops"], "TFLOP/s"),
+    "gemm_f32_split64": ("k_gemm_mfma<float, float, double, float>", "mfma", PEAK["fp32_tflops"], "TFLOP/s"),
     "gemm_reduce": ("k_gemm_reduce", "hbm", PEAK["hbm_gbs"], "GB/s"),
     "dst_f64": ("k_dst1<double, double, ...>", "hbm", PEAK["hbm_gbs"], "GB/s"),
     "dst_f32": ("k_dst1<float, double, ...>", "hbm", PEAK["hbm_gbs"], "GB/s"),

@@ -383,7 +383,10 @@ typedef enum {
   TP_PROF_PSD_EIG = 8,       /* k_psd_eig: Gram eigensolver (HOSVD ranks and bases, fit normal equations) */
   TP_PROF_NS = 9,            /* k_ns_isqrt: Newton-Schulz inverse square root (second orthonormalisation) */
   TP_PROF_GEMM_REDUCE = 10,  /* k_gemm_reduce: split-K partial sums of the contractions (all types) */
-  TP_PROF_PSD_TRI = 11       /* k_psd_tri: Gram eigensolver by tridiagonal reduction (HOSVD ranks and bases) */
+  TP_PROF_PSD_TRI = 11,      /* k_psd_tri: Gram eigensolver by tridiagonal reduction (HOSVD ranks and bases) */
+  TP_PROF_GEMM_F32_SPLIT64 = 12  /* k_gemm_mfma, FP32 operands accumulated in FP32 per split of K (at most
+                                    512 long), the splits summed into FP64 results (sketches, operator
+                                    inner products of the mixed path) */
 } tp_prof_class;
 
 /* Contraction kernels: mfma != 0 (default) uses the FP32/FP64 matrix-core tiles, 0 the FMA

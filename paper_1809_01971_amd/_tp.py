@@ -99,7 +99,7 @@ _SIGS = {
 }
 
 PROF_CLASSES = ["gemm_f64", "gemm_f32", "gemm_f32_f64", "gemm_f64_f32", "dst_f64", "dst_f32", "syev", "chol",
-                "psd_eig", "ns_isqrt", "gemm_reduce", "psd_tri"]
+                "psd_eig", "ns_isqrt", "gemm_reduce", "psd_tri", "gemm_f32_split64"]
 
 
 def load_library():

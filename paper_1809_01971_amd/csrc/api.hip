@@ -149,7 +149,8 @@ struct WsScope {
 // Kernel classes reported by tp_profile_read.
 // One class per kernel (template instantiations of the contraction count apart), whoever calls it.
 enum { PC_GEMM_F64 = 0, PC_GEMM_F32 = 1, PC_GEMM_F32_F64 = 2, PC_GEMM_F64_F32 = 3, PC_DST_F64 = 4, PC_DST_F32 = 5,
-       PC_SYEV = 6, PC_CHOL = 7, PC_PSD_EIG = 8, PC_NS = 9, PC_GEMM_REDUCE = 10, PC_PSD_TRI = 11, PC_COUNT = 12 };
+       PC_SYEV = 6, PC_CHOL = 7, PC_PSD_EIG = 8, PC_NS = 9, PC_GEMM_REDUCE = 10, PC_PSD_TRI = 11,
+       PC_GEMM_F32_SPLIT64 = 12, PC_COUNT = 13 };
 
 tp_status prof_begin(tp_ctx* c, size_t* e0) {
   if (!c->prof) return TP_OK;
@@ -292,6 +293,7 @@ template <typename TA, typename TB, typename TC, typename Tacc>
 int gemm_class() {
   if (std::is_same<TA, double>::value && std::is_same<TC, double>::value) return PC_GEMM_F64;
   if (std::is_same<TA, float>::value && std::is_same<TC, float>::value) return PC_GEMM_F32;
+  if (std::is_same<TA, float>::value && std::is_same<Tacc, float>::value) return PC_GEMM_F32_SPLIT64;
   if (std::is_same<TA, float>::value) return PC_GEMM_F32_F64;
   return PC_GEMM_F64_F32;
 }
@@ -315,15 +317,23 @@ tp_status run_group(tp_ctx* c, const GemmArgs<TA, TB, TC, Tacc>* g0, int count) 
   }
   size_t mark = c->ws_top;
   bool split = false;
+  // FP32 accumulation into an FP64 result: splits of at most kF32Chunk (their sums are FP64)
+  constexpr bool chunked = std::is_same<TC, double>::value && std::is_same<Tacc, float>::value;
   for (int i = 0; i < count; ++i) {
-    if (tiles >= kSplitTarget / 2 || g[i].K < 128 || g[i].M <= 0 || g[i].N <= 0) continue;
-    int splits = (int)std::min<long>((g[i].K + 63) / 64, std::max<long>(1, kSplitTarget / tiles));
+    if (g[i].M <= 0 || g[i].N <= 0) continue;
+    const int need = chunked ? (g[i].K + kF32Chunk - 1) / kF32Chunk : 1;
+    int splits = need;
+    if (tiles < kSplitTarget / 2 && g[i].K >= 128)
+      splits = std::max(splits, (int)std::min<long>((g[i].K + 63) / 64, std::max<long>(1, kSplitTarget / tiles)));
     if (splits < 2) continue;
     Tacc* part = nullptr;
     if (wsalloc(c, (size_t)g[i].batch * splits * g[i].M * g[i].N, &part) == TP_OK) {
       g[i].splits = splits;
       g[i].part = part;
       split = true;
+    } else if (need > 1) {
+      c->ws_top = mark;
+      return fail(TP_ENOMEM, "workspace exhausted by the split partial sums of a %dx%dx%d product", g[i].M, g[i].N, g[i].K);
     }
   }
   size_t e0 = 0, em = 0;
@@ -1057,7 +1067,9 @@ tp_status combo_impl(tp_ctx* c, const Term* terms, int nt, tp_tensor* y, double 
     const int* r = P.r;
     const int R = P.R;
     WsScope s2(c);
-    GemmArgs<T, T, double, double> gy[3];
+    // FP32 operands: the matrix cores accumulate in FP32 over chunks of K, summed in FP64
+    typedef typename std::conditional<std::is_same<T, float>::value, float, double>::type TaccS;
+    GemmArgs<T, T, double, TaccS> gy[3];
     for (int m = 0; m < d; ++m) {
       const int n = y->n[m];
       T* tt;
@@ -1084,7 +1096,7 @@ tp_status combo_impl(tp_ctx* c, const Term* terms, int nt, tp_tensor* y, double 
         }
         TPCHK((mm<T, T, T, Tacc>(c, false, false, r[m], R * Qs, r[o], 1.0, Cm, r[m], P.A[o], r[o], 0.0, tt, r[m])));
       }
-      GemmArgs<T, T, double, double>& g = gy[m];
+      GemmArgs<T, T, double, TaccS>& g = gy[m];
       g.M = n; g.N = Qs; g.K = r[m] * R;
       g.alpha = tv[t].coef; g.beta = t == 0 ? 0.0 : 1.0;
       g.fsA = true; g.FA.x1 = P.Vh[m]; g.FA.ld1 = n; g.FA.r1 = r[m];
@@ -1240,12 +1252,14 @@ tp_status inner_sym_impl(tp_ctx* c, const tp_tensor* x, const tp_symbol* S, cons
     }
     TPCHK(dst_cols_batch<T>(c, nj, jn, jc, ji, jo));
   }
-  GemmArgs<T, T, double, double> gs[3];
+  // FP32 operands: the matrix cores accumulate in FP32 over chunks of n, summed in FP64
+  typedef typename std::conditional<std::is_same<T, float>::value, float, double>::type TaccS;
+  GemmArgs<T, T, double, TaccS> gs[3];
   for (int m = 0; m < d; ++m) {
     int n = x->n[m];
     // G[i + rx (j + ry k)] (sigma folded into the last mode)
     TPCHK(wsalloc(c, (size_t)rx[m] * ry[m] * R, &G[m]));
-    GemmArgs<T, T, double, double>& g = gs[m];
+    GemmArgs<T, T, double, TaccS>& g = gs[m];
     g.M = rx[m]; g.N = ry[m] * R; g.K = n;
     g.A = Vx[m]; g.lda = n; g.tA = true;
     g.fsB = true; g.FB.x1 = Vy[m]; g.FB.ld1 = n; g.FB.r1 = ry[m];
@@ -2724,7 +2738,9 @@ extern "C" tp_status tp_workspace_query(const tp_symbol_desc* D, const tp_pcg_op
   // R r q^2; 2D: one stage each, r R q and R q r)
   const double sk2 = d == 3 ? cap * cap * R * Q * T : 0.0;
   const double proj = d == 3 ? (R * Q * cap * cap + R * cap * Q * Q) * T : R * Q * cap * T;
-  const double combo = d * nmax * Q * T + 2.0 * term + sk2 + cap * R * Q * T + pw(cap) * T +
+  // FP32-accumulated sketches: one partial sum per 512 of the cap R contraction length
+  const double skparts = D->prec == TP_FP64 ? 0.0 : d * nmax * Q * 4.0 * std::ceil(cap * R / 512.0);
+  const double combo = skparts + d * nmax * Q * T + 2.0 * term + sk2 + cap * R * Q * T + pw(cap) * T +
                        d * nmax * Q * 8 * 4 + 4.0 * d * Q * Q * 8 + d * nmax * Q * T + pw(Q) * T +
                        d * Q * cap * R * T + proj + 6.0 * pw(Q) * 8 + 4.0 * d * Q * Q * 8 + d * nmax * cap * T;
   // symbol inner product (Grams per term, two batched core contractions)

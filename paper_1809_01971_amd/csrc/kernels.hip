@@ -322,9 +322,11 @@ __global__ __launch_bounds__(GTHREADS) void k_gemm_mfma(GemmGroup<TA, TB, TC, Ta
         if (g.part) {
           g.part[(long)z * g.M * g.N + row + (long)g.M * col] = x;
         } else {
+          // FP64 results of FP32 accumulation are scaled and summed in FP64
+          typedef typename std::conditional<std::is_same<TC, double>::value, double, Tacc>::type Te;
           long o = row + (long)g.ldc * col;
-          Tacc y = g.alpha * x;
-          if (g.beta != (Tacc)0) y += g.beta * (Tacc)C[o];
+          Te y = (Te)g.alpha * (Te)x;
+          if (g.beta != (Tacc)0) y += (Te)g.beta * (Te)C[o];
           C[o] = (TC)y;
         }
       }
@@ -344,20 +346,22 @@ __global__ void k_gemm_reduce(GemmGroup<TA, TB, TC, Tacc> grp) {
   const int splits = g.splits;
   int row = (int)(e % g.M), col = (int)(e / g.M);
   const Tacc* p = g.part + (long)b * splits * mn + e;
-  // four independent partial sums keep four loads in flight (fixed order: deterministic)
-  Tacc a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  // the partial sums are added in FP64 when the result is FP64 (FP32 chunks of an FP32-accumulated
+  // product); four independent sums keep four loads in flight (fixed order: deterministic)
+  typedef typename std::conditional<std::is_same<TC, double>::value, double, Tacc>::type Te;
+  Te a0 = 0, a1 = 0, a2 = 0, a3 = 0;
   int s = 0;
   for (; s + 4 <= splits; s += 4) {
-    a0 += p[(long)s * mn];
-    a1 += p[(long)(s + 1) * mn];
-    a2 += p[(long)(s + 2) * mn];
-    a3 += p[(long)(s + 3) * mn];
+    a0 += (Te)p[(long)s * mn];
+    a1 += (Te)p[(long)(s + 1) * mn];
+    a2 += (Te)p[(long)(s + 2) * mn];
+    a3 += (Te)p[(long)(s + 3) * mn];
   }
-  for (; s < splits; ++s) a0 += p[(long)s * mn];
-  Tacc acc = (a0 + a1) + (a2 + a3);
+  for (; s < splits; ++s) a0 += (Te)p[(long)s * mn];
+  Te acc = (a0 + a1) + (a2 + a3);
   long o = (long)b * g.sC + row + (long)g.ldc * col;
-  Tacc v = g.alpha * acc;
-  if (g.beta != (Tacc)0) v += g.beta * (Tacc)g.C[o];
+  Te v = (Te)g.alpha * acc;
+  if (g.beta != (Tacc)0) v += (Te)g.beta * (Te)g.C[o];
   g.C[o] = (TC)v;
 }
 
@@ -444,8 +448,10 @@ template hipError_t gemm_group<double, double, double, double>(const GemmArgs<do
 template hipError_t gemm_group<float, float, float, float>(const GemmArgs<float, float, float, float>*, int, hipStream_t, hipEvent_t);
 template hipError_t gemm_group<float, float, double, double>(const GemmArgs<float, float, double, double>*, int, hipStream_t, hipEvent_t);
 template hipError_t gemm_group<double, double, float, double>(const GemmArgs<double, double, float, double>*, int, hipStream_t, hipEvent_t);
+template hipError_t gemm_group<float, float, double, float>(const GemmArgs<float, float, double, float>*, int, hipStream_t, hipEvent_t);
 template hipError_t gemm<float, float, double, double>(const GemmArgs<float, float, double, double>&, hipStream_t, hipEvent_t);
 template hipError_t gemm<double, double, float, double>(const GemmArgs<double, double, float, double>&, hipStream_t, hipEvent_t);
+template hipError_t gemm<float, float, double, float>(const GemmArgs<float, float, double, float>&, hipStream_t, hipEvent_t);
 
 // ---------------------------------------------------------------------------------------------
 // DST-I via a length-N/2 complex FFT (N = n+1 a power of two).

@@ -18,6 +18,9 @@ struct FaceSplit {
 
 // op(A) is M x K, op(B) is K x N, C is M x N, all column-major.
 // Batch b uses A + (b / divA) * sA, B + (b / divB) * sB, C + b * sC.
+// The matrix cores accumulate in Tacc.  With FP32 operands, an FP64 result and FP32 accumulation
+// (TA = TB = float, TC = double, Tacc = float) every split of K is at most kF32Chunk long and the
+// splits' partial sums, the scaling and the beta term are added in FP64.
 template <typename TA, typename TB, typename TC, typename Tacc>
 struct GemmArgs {
   int M = 0, N = 0, K = 0, batch = 1;
@@ -40,6 +43,7 @@ hipError_t gemm(const GemmArgs<TA, TB, TC, Tacc>& g, hipStream_t s, hipEvent_t m
 // travels in the kernel arguments; z0 / r0 (prefix sums of batch x splits and of the split
 // products' batches) are set by the launch.
 constexpr int kGemmGroup = 3;
+constexpr int kF32Chunk = 512;
 template <typename TA, typename TB, typename TC, typename Tacc>
 struct GemmGroup {
   GemmArgs<TA, TB, TC, Tacc> g[kGemmGroup];
