@@ -458,7 +458,8 @@ tp_status chol(tp_ctx* c, int cnt, const int* K, const double* const* G, double 
   for (int i = 0; i < cnt; ++i) Kmax = std::max(Kmax, K[i]);
   if (Kmax > kMaxRank) return fail(TP_ERANK, "Gram matrix of size %d exceeds %d", Kmax, kMaxRank);
   double* work = nullptr;
-  if (Kmax > kGramLds) TPCHK(wsalloc(c, (size_t)2 * Kmax * Kmax * cnt, &work));
+  // above 64 the blocked factorisation keeps L (and above 128 the trailing matrix) in global memory
+  if (Kmax > 64) TPCHK(wsalloc(c, (size_t)2 * Kmax * Kmax * cnt, &work));
   int* dq = reinterpret_cast<int*>(c->dmap);
   JobBatch<CholJob> jb;
   for (int i = 0; i < cnt; ++i)
@@ -529,7 +530,8 @@ tp_status psd_eig(tp_ctx* c, int cnt, const int* K, const double* const* G, doub
     return TP_OK;
   }
   double* work = nullptr;
-  if (Kmax > kGramLds) TPCHK(wsalloc(c, (size_t)2 * Kmax * Kmax * cnt, &work));
+  // above 64 the blocked factorisation keeps L (and above 128 the trailing matrix) in global memory
+  if (Kmax > 64) TPCHK(wsalloc(c, (size_t)2 * Kmax * Kmax * cnt, &work));
   // mapped layout: eigenvalues (tot), traces (cnt), ranks (cnt ints)
   double* dres = c->dmap + tot;
   int* dq = reinterpret_cast<int*>(dres + cnt);
@@ -604,7 +606,8 @@ tp_status psd_eig_dev(tp_ctx* c, int cnt, const int* K, const double* const* G, 
   }
   if (Kmax == 0) return TP_OK;
   double* work = nullptr;
-  if (Kmax > kGramLds) TPCHK(wsalloc(c, (size_t)2 * Kmax * Kmax * cnt, &work));
+  // above 64 the blocked factorisation keeps L (and above 128 the trailing matrix) in global memory
+  if (Kmax > 64) TPCHK(wsalloc(c, (size_t)2 * Kmax * Kmax * cnt, &work));
   double* dres = c->dmap + tp_ctx::kMap / 2;
   int* dq = reinterpret_cast<int*>(dres + cnt);
   JobBatch<PsdJob> jb;

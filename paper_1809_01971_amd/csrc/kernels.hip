@@ -979,16 +979,9 @@ __device__ __forceinline__ double wave_max_f64(double v) {
 // ---------------------------------------------------------------------------------------------
 // Pivoted Cholesky of Gram matrices, shared by the orthonormalisation (k_pchol) and the Gram
 // eigensolver (k_psd_eig).  G[P,P] = R^T R, the pivot of each step being the largest remaining
-// diagonal entry; it stops once that entry is <= ctol * max diag(G).  The Schur complement is
-// kept in original index order, upper triangle only (element (a, b), a <= b, at S[a + K b]).
-// Step k with pivot p updates S[i][j] -= S[p][i] S[p][j] / S[p][p] over the unpivoted i <= j;
-// row p is never written again, so R(k, l) = S[p, perm_l] / sqrt(S[p][p]).
-// The threads form a TX x TY grid: thread (tx, ty) owns the elements (tx + TX a, ty + TY b) and
-// keeps which of its rows and columns are pivoted in registers.  Each wave reduces the
-// candidate keys of the diagonal entries it updated into a double-buffered slot, so one
-// barrier per step suffices; every wave then reads the next pivot from the slots by itself.
-// The workgroup is sized to the matrix (256 threads up to K = 64, 512 up to 128, 1024 beyond):
-// every thread runs the whole step sequence, so idle lanes would only cost issue slots.
+// diagonal entry; it stops once that entry is <= ctol * max diag(G).  The workgroup is sized to
+// the matrix (256 threads up to K = 64, 512 up to 128, 1024 beyond); the thread grid of the
+// trailing updates: thread (tx, ty) owns the elements (tx + TX a, ty + TY b).
 // ---------------------------------------------------------------------------------------------
 struct CholShared { double rest; int q; };
 
@@ -998,48 +991,18 @@ template <> struct ChGrid<256> { static constexpr int TX = 16, NBI = 4, NBJ = 4,
 template <> struct ChGrid<512> { static constexpr int TX = 32, NBI = 4, NBJ = 8, KMAX = 128; };
 template <> struct ChGrid<1024> { static constexpr int TX = 32, NBI = 8, NBJ = 8, KMAX = 256; };
 
-// Pivot candidates travel as 64-bit keys: a positive double orders like its bit pattern, and
-// its lowest 8 bits are replaced by 255 - index, so the maximum key is the largest value with
-// ties (to 2^-44 relative) going to the lowest index.  Non-positive values give key 0.
-__device__ __forceinline__ unsigned long long pivot_key(double v, int i) {
-  return v > 0.0 ? (((unsigned long long)__double_as_longlong(v) & ~0xFFull) | (unsigned long long)(255 - i)) : 0ull;
-}
-template <int CTRL>
-__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v) {
-  const int lo = __builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(v >> 32), CTRL, 0xF, 0xF, false);
-  return (unsigned long long)(unsigned)lo | ((unsigned long long)(unsigned)hi << 32);
-}
-__device__ __forceinline__ unsigned long long umax64(unsigned long long a, unsigned long long b) { return a > b ? a : b; }
-__device__ __forceinline__ unsigned long long readlane64(unsigned long long v, int lane) {
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)v, lane);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(v >> 32), lane);
-  return (unsigned long long)lo | ((unsigned long long)hi << 32);
-}
-// Maximum key over the wave (DPP within rows of 16 lanes, then the four row results are read
-// into scalars); the result is uniform.
-__device__ __forceinline__ unsigned long long wave_max_key(unsigned long long v) {
-  v = umax64(v, dpp_u64<0xB1>(v));
-  v = umax64(v, dpp_u64<0x4E>(v));
-  v = umax64(v, dpp_u64<0x141>(v));
-  v = umax64(v, dpp_u64<0x140>(v));
-  return umax64(umax64(readlane64(v, 0), readlane64(v, 16)), umax64(readlane64(v, 32), readlane64(v, 48)));
-}
 
-// The same factorisation for K <= 64, blocked (the pivoted scheme of LAPACK's dpstrf): panels of
-// 16 pivots are factored left-looking by wave 0 alone, lane i owning row i, with no barrier:
-// the Schur diagonal d_i lives in lane i's register, the pivot is the lane maximum of 32-bit keys
-// (the diagonal relative to the largest initial one, as float bits, the low 6 bits replaced by
-// 63 - index: ties to 2^-18 relative go to the lower index), and column k is
+// The factorisation blocked (the pivoted scheme of LAPACK's dpstrf): panels of NB pivots are
+// factored left-looking by wave 0 alone, lane i owning rows i + 64 r (r < RPL), with no barrier:
+// the Schur diagonal lives in those lanes' registers, the pivot is the lane maximum of 32-bit
+// keys (the diagonal relative to the largest initial one, as float bits, the low IB bits replaced
+// by 2^IB - 1 - index: ties to 2^-(23-IB) relative go to the lower index), and column k is
 // (S[:, p] - L[:, panel] L[p, panel]^T) / sqrt(d_p) with L[p, panel] read from lane p's registers.
 // After each panel the whole workgroup applies it to the trailing matrix S (one barrier on each
-// side), which is full and symmetric in LDS.  Output: Lc[k K + i] = L(i, k) (column k of L in the
-// original row order, so R(k, l) = Lc[k K + perm[l]] in pivot order), dk[k] = sqrt(pivot k), perm
-// (the pivots, then the unpivoted indices in increasing order), sh.rest (the Schur trace left).
-// S is overwritten.
-__device__ __forceinline__ unsigned pivot_key32(double v, double scale, int i) {
-  return v > 0.0 ? ((__float_as_uint((float)(v * scale)) & ~63u) | (unsigned)(63 - i)) : 0u;
-}
+// side), which is full and symmetric (in LDS, or in global memory for K > 128).  Output:
+// Lc[k K + i] = L(i, k) (column k of L in the original row order, so R(k, l) = Lc[k K + perm[l]] in
+// pivot order), dk[k] = sqrt(pivot k), perm (the pivots, then the unpivoted indices in increasing
+// order), sh.rest (the Schur trace left).  S is overwritten.
 __device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
   v = max(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false));
   v = max(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false));
@@ -1050,50 +1013,97 @@ __device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
   return max(max(r0, r1), max(r2, r3));
 }
 
-constexpr int CHOL_NB = 16;
+// Panel width, rows per lane of wave 0 (K <= 64 RPL) and bits of the pivot index in the keys
+template <int NT> struct CholBlk;
+template <> struct CholBlk<256> { static constexpr int RPL = 1, NB = 16, IB = 6; };
+template <> struct CholBlk<512> { static constexpr int RPL = 2, NB = 16, IB = 8; };
+template <> struct CholBlk<1024> { static constexpr int RPL = 4, NB = 8, IB = 8; };
 
+template <int IB>
+__device__ __forceinline__ unsigned pivot_key_ib(double v, double scale, int i) {
+  constexpr unsigned m = (1u << IB) - 1u;
+  return v > 0.0 ? ((__float_as_uint((float)(v * scale)) & ~m) | (m - (unsigned)i)) : 0u;
+}
+// a[r] of lane `lane` for a uniform r < N: every a[i] is read from the lane and the choice is made
+// among the (uniform) results, so the array is never indexed dynamically (a select among the
+// elements themselves may be folded into an indexed access, which puts the array in scratch)
+template <int N>
+__device__ __forceinline__ double readlane_pick(const double (&a)[N], int r, int lane) {
+  double v = readlane_f64(a[0], lane);
+#pragma unroll
+  for (int i = 1; i < N; ++i) {
+    const double w = readlane_f64(a[i], lane);
+    v = r == i ? w : v;
+  }
+  return v;
+}
+
+template <int NT>
 __device__ __forceinline__ int chol_phase_blk(const double* G, int K, double ctol, double* S, double* Lc, double* dk,
                                               int* perm, int* mark, CholShared& sh) {
+  constexpr int RPL = CholBlk<NT>::RPL, NB = CholBlk<NT>::NB, IB = CholBlk<NT>::IB;
+  constexpr unsigned IM = (1u << IB) - 1u;
+  constexpr int TX = ChGrid<NT>::TX, TY = NT / TX, NBI = ChGrid<NT>::NBI, NBJ = ChGrid<NT>::NBJ;
   __shared__ int pstate[2];  // rank so far, 1 once the factorisation has stopped
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int e = tid; e < K * K; e += 256) {
+  for (int e = tid; e < K * K; e += NT) {
     const int i = e % K, j = e / K;
     S[e] = G[min(i, j) + (long)K * max(i, j)];
   }
-  // wave 0: the Schur diagonal, the scale of the pivot keys and the stopping threshold
-  double d = 0.0, dmax0 = 0.0, scale = 0.0, stop = 0.0;
-  bool alive = false;  // lane's row not pivoted yet
+  // wave 0: the Schur diagonal of rows lane + 64 r, the scale of the pivot keys, the threshold
+  double d[RPL];
+  bool alive[RPL];  // row not pivoted yet
+  double scale = 0.0, stop = 0.0;
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) { d[r] = 0.0; alive[r] = false; }
   if (wave == 0) {
-    d = lane < K ? G[lane + (long)K * lane] : 0.0;
-    alive = lane < K;
-    dmax0 = wave_max_f64(lane < K ? d : 0.0);
+    double dm = 0.0;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int row = lane + 64 * r;
+      alive[r] = row < K;
+      d[r] = alive[r] ? G[row + (long)K * row] : 0.0;
+      dm = fmax(dm, d[r]);
+    }
+    const double dmax0 = wave_max_f64(dm);
     scale = dmax0 > 0.0 ? 1.0 / dmax0 : 0.0;
     stop = ctol * dmax0;
     if (lane == 0) { pstate[0] = 0; pstate[1] = dmax0 > 0.0 ? 0 : 1; }
   }
   __syncthreads();
-  for (int kb = 0; kb < K; kb += CHOL_NB) {
+  for (int kb = 0; kb < K; kb += NB) {
     if (wave == 0) {
       int k = kb;
       bool done = false;
-      double lrow[CHOL_NB];
+      double lrow[NB][RPL];
 #pragma unroll
-      for (int t = 0; t < CHOL_NB; ++t) {
-        lrow[t] = 0.0;
+      for (int t = 0; t < NB; ++t) {
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) lrow[t][r] = 0.0;
         if (done || kb + t >= K) continue;  // uniform
-        const unsigned key = wave_max_u32(alive ? pivot_key32(d, scale, lane) : 0u);
-        const int p = 63 - (int)(key & 63u);
-        const double dp = readlane_f64(d, p);
+        unsigned kl = 0u;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) kl = max(kl, alive[r] ? pivot_key_ib<IB>(d[r], scale, lane + 64 * r) : 0u);
+        const unsigned key = wave_max_u32(kl);
+        const int p = (int)(IM - (key & IM)), pr = p >> 6, pl = p & 63;
+        const double dp = readlane_pick(d, pr, pl);
         if (!key || !(dp > stop)) { done = true; continue; }  // uniform
         const double sp = sqrt(dp), rs = 1.0 / sp;
-        double c = lane < K ? S[lane + K * p] : 0.0;
+        double lp[NB];  // L(p, kb + u), u < t
 #pragma unroll
-        for (int u = 0; u < t; ++u) c = fma(-lrow[u], readlane_f64(lrow[u], p), c);
-        const double l = lane == p ? sp : c * rs;
-        lrow[t] = l;
-        if (lane < K) Lc[(kb + t) * K + lane] = l;
-        if (lane == p) alive = false;
-        d = alive ? fma(-l, l, d) : 0.0;
+        for (int u = 0; u < t; ++u) lp[u] = readlane_pick(lrow[u], pr, pl);
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+          const int row = lane + 64 * r;
+          double c = row < K ? S[row + K * p] : 0.0;
+#pragma unroll
+          for (int u = 0; u < t; ++u) c = fma(-lrow[u][r], lp[u], c);
+          const double l = row == p ? sp : c * rs;
+          lrow[t][r] = l;
+          if (row < K) Lc[(kb + t) * K + row] = l;
+          if (row == p) alive[r] = false;
+          d[r] = alive[r] ? fma(-l, l, d[r]) : 0.0;
+        }
         if (lane == 0) { perm[kb + t] = p; dk[kb + t] = sp; }
         k = kb + t + 1;
       }
@@ -1101,136 +1111,55 @@ __device__ __forceinline__ int chol_phase_blk(const double* G, int K, double cto
     }
     __syncthreads();
     if (pstate[1] || pstate[0] >= K) break;  // uniform
-    // trailing update S -= L_panel L_panel^T (thread (tx, ty) owns (tx + 16 a, ty + 16 b))
+    // trailing update S -= L_panel L_panel^T: thread (tx, ty) owns (tx + TX a, ty + TY b), taken
+    // AC rows at a time (the 1024-thread grid holds 64 entries per thread: two rows and one panel
+    // column at a time keep them in registers)
     {
-      const int tx = tid & 15, ty = tid >> 4;
-      double acc[16];
+      constexpr int AC = NT == 1024 ? 2 : NBI, UT = NT == 1024 ? 1 : 4;
+      const int tx = tid % TX, ty = tid / TX;
 #pragma unroll
-      for (int e = 0; e < 16; ++e) acc[e] = 0.0;
-#pragma unroll 4
-      for (int t = 0; t < CHOL_NB; ++t) {
-        const double* Lt = Lc + (kb + t) * K;
-        double li[4], lj[4];
+      for (int a0 = 0; a0 < NBI; a0 += AC) {
+        double acc[AC][NBJ];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) li[a] = tx + 16 * a < K ? Lt[tx + 16 * a] : 0.0;
+        for (int a = 0; a < AC; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) lj[b] = ty + 16 * b < K ? Lt[ty + 16 * b] : 0.0;
+          for (int b = 0; b < NBJ; ++b) acc[a][b] = 0.0;
+#pragma unroll UT
+        for (int t = 0; t < NB; ++t) {
+          const double* Lt = Lc + (kb + t) * K;
+          double li[AC], lj[NBJ];
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
+          for (int a = 0; a < AC; ++a) li[a] = tx + TX * (a0 + a) < K ? Lt[tx + TX * (a0 + a)] : 0.0;
 #pragma unroll
-          for (int a = 0; a < 4; ++a) acc[a + 4 * b] = fma(li[a], lj[b], acc[a + 4 * b]);
-      }
+          for (int b = 0; b < NBJ; ++b) lj[b] = ty + TY * b < K ? Lt[ty + TY * b] : 0.0;
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
+          for (int b = 0; b < NBJ; ++b)
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          const int i = tx + 16 * a, j = ty + 16 * b;
-          if (i < K && j < K) S[i + K * j] -= acc[a + 4 * b];
+            for (int a = 0; a < AC; ++a) acc[a][b] = fma(li[a], lj[b], acc[a][b]);
         }
+#pragma unroll
+        for (int b = 0; b < NBJ; ++b)
+#pragma unroll
+          for (int a = 0; a < AC; ++a) {
+            const int i = tx + TX * (a0 + a), j = ty + TY * b;
+            if (i < K && j < K) S[i + K * j] -= acc[a][b];
+          }
+      }
     }
     __syncthreads();
   }
   const int q = pstate[0];
   // unpivoted indices (in increasing order) after the pivots, and their remaining trace
-  for (int i = tid; i < K; i += 256) mark[i] = 0;
-  __syncthreads();
-  for (int k = tid; k < q; k += 256) mark[perm[k]] = 1;
-  if (wave == 0) {
-    double r = alive ? fmax(d, 0.0) : 0.0;
-    for (int o = 32; o > 0; o >>= 1) r += __shfl_xor(r, o);
-    if (lane == 0) { sh.rest = r; sh.q = q; }
-  }
-  __syncthreads();
-  for (int i = tid; i < K; i += 256)
-    if (!mark[i]) {
-      int c = 0;
-      for (int j = 0; j < i; ++j) c += mark[j] ? 0 : 1;
-      perm[q + c] = i;
-    }
-  __syncthreads();
-  return q;
-}
-
-// Returns the rank q (the same in every thread).  dk[k] = sqrt(pivot k); perm holds the pivots,
-// then the unpivoted indices in increasing order; sh.rest = trace left in the Schur complement.
-// slot: 2 x NT/64 keys; mark: K ints of scratch.  K <= ChGrid<NT>::KMAX.
-template <int NT>
-__device__ __forceinline__ int chol_phase(const double* G, int K, double ctol, double* S, double* dk, int* perm,
-                                          unsigned long long* slot, int* mark, CholShared& sh) {
-  constexpr int TX = ChGrid<NT>::TX, TY = NT / TX, NBI = ChGrid<NT>::NBI, NBJ = ChGrid<NT>::NBJ, NW = NT / 64;
-  // up to 512 threads the owned entries also live in registers (the LDS copy serves the
-  // pivot-row reads of the other threads)
-  constexpr bool REG = NT <= 512;
-  constexpr int NR = REG ? NBI * NBJ : 1;
-  const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX, lane = tid & 63, wave = tid >> 6;
-  unsigned piv_i = 0, piv_j = 0;  // bit a: row tx + TX a / column ty + TY b pivoted
-  double sv[NR];
-  unsigned long long best = 0ull;
-#pragma unroll
-  for (int b = 0; b < NBJ; ++b)
-#pragma unroll
-    for (int a = 0; a < NBI; ++a) {
-      const int i = tx + TX * a, j = ty + TY * b;
-      double v = 0.0;
-      if (i <= j && j < K) {
-        v = G[i + (long)K * j];
-        S[i + K * j] = v;
-        if (i == j) best = umax64(best, pivot_key(v, i));
-      }
-      if (REG) sv[(a + NBI * b) % NR] = v;
-    }
-  best = wave_max_key(best);
-  if (lane == 0) slot[wave] = best;
-  __syncthreads();
-  const unsigned long long k0 = wave_max_key(lane < NW ? slot[lane] : 0ull);
-  const double dmax0 = k0 ? S[(255 - (int)(k0 & 0xFF)) * (K + 1)] : 0.0;
-  const double stop = ctol * dmax0;
-  int q = K;
-  for (int k = 0; k < K; ++k) {
-    const int buf = (k & 1) * NW;
-    const unsigned long long key = wave_max_key(lane < NW ? slot[buf + lane] : 0ull);
-    const int p = 255 - (int)(key & 0xFF);
-    // the pivot row S[p][.] (and S[p][p]) is read in one batch of independent loads
-    double spi[NBI], spj[NBJ];
-#pragma unroll
-    for (int a = 0; a < NBI; ++a) {
-      const int i = tx + TX * a;
-      spi[a] = (key && i < K) ? S[min(p, i) + K * max(p, i)] : 0.0;
-    }
-#pragma unroll
-    for (int b = 0; b < NBJ; ++b) {
-      const int j = ty + TY * b;
-      spj[b] = (key && j < K) ? S[min(p, j) + K * max(p, j)] : 0.0;
-    }
-    const double pv = key ? S[p * (K + 1)] : 0.0;
-    if (!key || !(pv > stop) || !(dmax0 > 0.0)) { q = k; break; }  // uniform
-    if (tid == 0) { perm[k] = p; dk[k] = sqrt(pv); }
-    if (p % TX == tx) piv_i |= 1u << (p / TX);
-    if (p % TY == ty) piv_j |= 1u << (p / TY);
-    const double inv = 1.0 / pv;
-    best = 0ull;
-#pragma unroll
-    for (int b = 0; b < NBJ; ++b)
-#pragma unroll
-      for (int a = 0; a < NBI; ++a) {
-        const int i = tx + TX * a, j = ty + TY * b;
-        if (i <= j && j < K && !((piv_i >> a) & 1) && !((piv_j >> b) & 1)) {
-          const double old = REG ? sv[(a + NBI * b) % NR] : S[i + K * j];
-          const double v = old - spi[a] * (spj[b] * inv);
-          if (REG) sv[(a + NBI * b) % NR] = v;
-          S[i + K * j] = v;
-          if (i == j) best = umax64(best, pivot_key(v, i));
-        }
-      }
-    best = wave_max_key(best);
-    if (lane == 0) slot[NW - buf + wave] = best;
-    __syncthreads();
-  }
-  __syncthreads();
-  // unpivoted indices (in increasing order) after the pivots, and their remaining trace
   for (int i = tid; i < K; i += NT) mark[i] = 0;
   __syncthreads();
   for (int k = tid; k < q; k += NT) mark[perm[k]] = 1;
+  if (wave == 0) {
+    double r2 = 0.0;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) r2 += alive[r] ? fmax(d[r], 0.0) : 0.0;
+    for (int o = 32; o > 0; o >>= 1) r2 += __shfl_xor(r2, o);
+    if (lane == 0) { sh.rest = r2; sh.q = q; }
+  }
   __syncthreads();
   for (int i = tid; i < K; i += NT)
     if (!mark[i]) {
@@ -1238,23 +1167,10 @@ __device__ __forceinline__ int chol_phase(const double* G, int K, double ctol, d
       for (int j = 0; j < i; ++j) c += mark[j] ? 0 : 1;
       perm[q + c] = i;
     }
-  if (tid < 64) {
-    double r = 0.0;
-    for (int i = tid; i < K; i += 64)
-      if (!mark[i]) r += fmax(S[i + K * i], 0.0);
-    for (int o = 32; o > 0; o >>= 1) r += __shfl_xor(r, o);
-    if (tid == 0) { sh.rest = r; sh.q = q; }
-  }
   __syncthreads();
   return q;
 }
 
-// R(i, l) in pivot order from the Cholesky storage (i <= l < K).
-__device__ __forceinline__ double chol_r(const double* S, const double* dk, const int* perm, int K, int i, int l) {
-  if (i == l) return dk[i];
-  const int a = perm[i], b = perm[l];
-  return S[min(a, b) + K * max(a, b)] / dk[i];
-}
 
 
 // Rank-revealing orthonormalisation factor: W (K x q, ld K) = P[:, :q] R^-1, so that V W has
@@ -1277,7 +1193,7 @@ __device__ __forceinline__ void pchol64(const CholJob& J, double* sm) {
   int* perm = reinterpret_cast<int*>(xd + K);
   int* mark = reinterpret_cast<int*>(xd);  // free until the inverse
   __shared__ CholShared sh;
-  const int q = chol_phase_blk(J.g, K, J.tol, S, Lc, dk, perm, mark, sh);
+  const int q = chol_phase_blk<256>(J.g, K, J.tol, S, Lc, dk, perm, mark, sh);
   for (int e = tid; e < q * q; e += 256) {
     const int l = e % q, i = e / q;
     S[l + K * i] = l >= i ? Lc[i * K + perm[l]] : 0.0;
@@ -1330,40 +1246,21 @@ __global__ __launch_bounds__(NT) void k_pchol(JobBatch<CholJob> jobs) {
     pchol64(J, sm);
     return;
   }
-  double* S = SMEM ? sm : J.work;
-  double* Rp = SMEM ? sm : J.work + (size_t)K * K;  // R (q x q, ld K, upper) then X = R^-1 below it
+  // L in the job's global scratch (first K^2), the trailing matrix in LDS (K <= 128) or after L;
+  // R and X = R^-1 then take the trailing matrix's place
+  double* Lc = J.work;
+  double* S = SMEM ? sm : J.work + (size_t)K * K;
+  double* Rp = S;  // R (q x q, ld K, upper) then X = R^-1 below it
   double* base = SMEM ? sm + (size_t)K * K : sm;
   double* dk = base;
   double* xd = dk + K;
-  unsigned long long* slot = reinterpret_cast<unsigned long long*>(xd + K);  // 2 x NW keys
-  int* perm = reinterpret_cast<int*>(slot + 2 * NW);
+  int* perm = reinterpret_cast<int*>(xd + K + 2 * NW);
   __shared__ CholShared sh;
   int* mark = reinterpret_cast<int*>(xd);  // free until the inverse
-  const int q = chol_phase<NT>(J.g, K, J.tol, S, dk, perm, slot, mark, sh);
-  if (SMEM) {
-    constexpr int GMAX = (KMAX * KMAX + NT - 1) / NT;
-    double reg[GMAX];
-#pragma unroll
-    for (int t = 0; t < GMAX; ++t) {
-      const int e = tid + t * NT;
-      double v = 0.0;
-      if (e < q * q) {
-        const int i = e % q, l = e / q;
-        if (i <= l) v = chol_r(S, dk, perm, K, i, l);
-      }
-      reg[t] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < GMAX; ++t) {
-      const int e = tid + t * NT;
-      if (e < q * q) Rp[e % q + K * (e / q)] = reg[t];
-    }
-  } else {
-    for (int e = tid; e < q * q; e += NT) {
-      const int i = e % q, l = e / q;
-      Rp[i + K * l] = i <= l ? chol_r(S, dk, perm, K, i, l) : 0.0;
-    }
+  const int q = chol_phase_blk<NT>(J.g, K, J.tol, S, Lc, dk, perm, mark, sh);
+  for (int e = tid; e < q * q; e += NT) {
+    const int i = e % q, l = e / q;
+    Rp[i + K * l] = i <= l ? Lc[i * K + perm[l]] : 0.0;
   }
   __syncthreads();
   // X(i, j) = -(sum_{i<l<=j} R(i, l) X(l, j)) / R(i, i), bottom-up; X(l, j), l < j, at Rp[j + K l]
@@ -1620,8 +1517,10 @@ __global__ __launch_bounds__(NT) void k_psd_eig(JobBatch<PsdJob> jobs) {
     if (tid == 0) { *J.q = 0; *J.rest = 0.0; }
     return;
   }
-  double* S = SMEM ? sm : J.work;
-  double* X = SMEM ? sm : J.work + (size_t)K * K;      // K x q, ld K
+  // K > 64: L in the job's global scratch (first K^2), the trailing matrix in LDS (K <= 128) or
+  // after L, and X in the trailing matrix's place
+  double* S = SMEM ? sm : J.work + (size_t)K * K;
+  double* X = S;                                       // K x q, ld K
   double* base = SMEM ? sm + (size_t)K * K : sm;
   double* dk = base;                                   // K pivots; later column norms^2
   unsigned long long* slot = reinterpret_cast<unsigned long long*>(dk + K);  // 2 x NW keys
@@ -1637,39 +1536,17 @@ __global__ __launch_bounds__(NT) void k_psd_eig(JobBatch<PsdJob> jobs) {
     // blocked factorisation with L in its own LDS block (after the job's scratch), then
     // X = R^T in pivot order: X[l][k] = R(k, l) = L(perm[l], k) (l >= k), 0 above the diagonal
     double* Lc = base + 2 * K + 32;
-    q = chol_phase_blk(J.g, K, J.ctol, S, Lc, dk, perm, rank, sh);
+    q = chol_phase_blk<256>(J.g, K, J.ctol, S, Lc, dk, perm, rank, sh);
     for (int e = tid; e < K * q; e += NT) {
       const int l = e % K, k = e / K;
       X[e] = l >= k ? Lc[k * K + perm[l]] : 0.0;
     }
   } else {
-    q = chol_phase<NT>(J.g, K, J.ctol, S, dk, perm, slot, rank, sh);
-  }
-  // X = R^T in pivot order: X[l][k] = R(k, l) (l >= k), 0 above the diagonal
-  if constexpr (NT == 256) {
-  } else if (SMEM) {
-    constexpr int GMAX = (KMAX * KMAX + NT - 1) / NT;
-    double reg[GMAX];
-#pragma unroll
-    for (int t = 0; t < GMAX; ++t) {
-      const int e = tid + t * NT;
-      double v = 0.0;
-      if (e < K * q) {
-        const int l = e % K, k = e / K;
-        if (l >= k) v = chol_r(S, dk, perm, K, k, l);
-      }
-      reg[t] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < GMAX; ++t) {
-      const int e = tid + t * NT;
-      if (e < K * q) X[e] = reg[t];
-    }
-  } else {
+    double* Lc = J.work;
+    q = chol_phase_blk<NT>(J.g, K, J.ctol, S, Lc, dk, perm, rank, sh);
     for (int e = tid; e < K * q; e += NT) {
       const int l = e % K, k = e / K;
-      X[e] = l >= k ? chol_r(S, dk, perm, K, k, l) : 0.0;
+      X[e] = l >= k ? Lc[k * K + perm[l]] : 0.0;
     }
   }
   __syncthreads();

@@ -93,7 +93,7 @@ struct EigJob { int K; const double* a; double* w; double* v; double* work; doub
 hipError_t syev_batched(const JobBatch<EigJob>& jobs, int count, int Kmax, hipStream_t s);
 
 // Batched rank-revealing pivoted Cholesky of Gram matrices: W = P R^-1 (K x q, ld K), q to *q.
-// Matrices larger than 128 need `work` (2 K^2 doubles) in global memory.
+// Matrices larger than 64 need `work` (2 K^2 doubles) in global memory.
 struct CholJob { int K; double tol; const double* g; double* w; int* q; double* work; };
 hipError_t pchol_batched(const JobBatch<CholJob>& jobs, int count, int Kmax, hipStream_t s);
 
@@ -109,7 +109,7 @@ hipError_t ns_isqrt_batched(const JobBatch<NsJob>& jobs, int count, int Kmax, hi
 // numerical rank q), eigenvectors to v (K x K, ld K, zero columns past q), q to *q and the
 // trace left in the Schur complement when the Cholesky stopped to *rest.  Cholesky stops at
 // pivots <= ctol * max diag(G); a column pair is rotated while |x_p.x_r| > jtol |x_p||x_r|.
-// Matrices larger than 128 need `work` (2 K^2 doubles) in global memory.
+// Matrices larger than 64 need `work` (2 K^2 doubles) in global memory.
 struct PsdJob { int K; const double* g; double* w; double* v; int* q; double* rest; double* work; double ctol; double jtol; };
 hipError_t psd_eig_batched(const JobBatch<PsdJob>& jobs, int count, int Kmax, hipStream_t s);
 
