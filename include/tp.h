@@ -170,6 +170,10 @@ typedef struct {
  * min p s <= 0 on the lattice (Algorithm alg:pcg needs a positive definite preconditioner). */
 tp_status tp_symbol_build(tp_ctx* ctx, const tp_symbol_desc* desc, tp_symbol** op,
                           tp_symbol** pre, double* err);
+/* Release a symbol (NULL is accepted).  Waits for the device, then returns the symbol's device
+ * blocks to the context that built it: that context's later builds reuse them (no allocation call
+ * once the blocks exist, at most 1 GiB of idle blocks kept), and they are freed with the last of the
+ * context and its symbols.  The symbol may outlive its context. */
 tp_status tp_symbol_free(tp_symbol* sym);
 
 /* State operator of eqn:State / eqn:L_alp_state, y = beta A^-alpha u: the exponential sum

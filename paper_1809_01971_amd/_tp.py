@@ -341,7 +341,10 @@ class Context:
     def pcg_solve(self, op, pre, weights, factors, x, tau, kmax, trunc_tol, cap, sketch, true_residual=False,
                   allow=(TP_ERANK, TP_ENOCONV), stop_rule=0, recursive_residual=False, spectral_domain=False,
                   warm_start=False):
-        keep, cp = cp_struct(weights, factors)
+        if isinstance(weights, Rhs):  # already on the device
+            keep, cp = weights.keep, weights.cp
+        else:
+            keep, cp = cp_struct(weights, factors)
         sk, keep2 = sketch_struct(sketch)
         o = tp_pcg_opts(tau, kmax, trunc_tol, cap, 1 if true_residual else 0, stop_rule,
                         1 if recursive_residual else 0, 1 if spectral_domain else 0, 1 if warm_start else 0)
@@ -384,10 +387,11 @@ def workspace_query(d, n, alpha, settings, rhs_rank, c_neg=1.0, c_pos=1e-2, **de
     return v.value
 
 
-def batch_solve(ctx, problems, settings, sketches, streams=8, workspace_per_stream=0):
+def batch_solve(ctx, problems, settings, sketches, streams=8, workspace_per_stream=0, rhs=None):
     """Solve independent problems concurrently (tp_pcg_solve_batched).  settings(p) -> dict with
     prec, eps, tau, cap, op_terms, pre_terms (and optionally q); sketches[(n, q)] or sketches[n] -> device
-    sketch tensors for grid n."""
+    sketch tensors for grid n; rhs: optional list of `Rhs` (the problems' right-hand sides already on
+    the device), else they are copied here."""
     cnt = len(problems)
     descs = (tp_symbol_desc * cnt)()
     cps = (tp_cp * cnt)()
@@ -401,7 +405,7 @@ def batch_solve(ctx, problems, settings, sketches, streams=8, workspace_per_stre
         extra = {k: s[k] for k in _DESC_KEYS if k in s}
         descs[i] = _desc(p.d, p.n, p.alpha, p.c_neg, p.c_pos, s["prec"], s["op_terms"], s["pre_terms"],
                          c0=getattr(p, "c0", 0.0) or 0.0, beta=getattr(p, "beta", None) or 0.0, **extra)
-        k, cp = cp_struct(p.weights, p.factors)
+        k, cp = (rhs[i].keep, rhs[i].cp) if rhs is not None else cp_struct(p.weights, p.factors)
         keep.append(k)
         cps[i] = cp
         X = Tensor(p.d, p.n, s["cap"], s["prec"])
@@ -494,6 +498,14 @@ class Tensor:
         fs = [self.factors[m][: self.ns[m] * r[m]].double().cpu().numpy().reshape(r[m], self.ns[m]).T
               for m in range(self.d)]
         return core, fs
+
+
+class Rhs:
+    """A canonical right-hand side (weights, n x R factors) copied to the device once, for solves
+    that take their input from device memory."""
+
+    def __init__(self, weights, factors):
+        self.keep, self.cp = cp_struct(weights, factors)
 
 
 def cp_struct(weights, factors):

@@ -14,6 +14,7 @@
 #include <atomic>
 #include <functional>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <string>
@@ -65,8 +66,26 @@ constexpr int kMaxSketch = 192; // sketch width
 constexpr size_t kNoAllocScratchBytes = size_t(16) << 20;
 static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
 
+// Device blocks of freed symbols, kept for the next builds of the same context: a loop that builds
+// and frees its symbols for every solve makes no allocation call and no device-wide wait once the
+// blocks exist.  Shared by the context and every symbol built in it, so a symbol freed after its
+// context still returns its blocks; the last owner frees them.  A block is handed out again only to
+// a later build of the same context, on its stream; tp_symbol_free waits for the device first, so
+// no queued work still reads a block that goes back to the pool.
+struct SymPool {
+  std::mutex mu;
+  std::multimap<size_t, void*> idle;  // size in bytes -> block
+  size_t idle_bytes = 0;
+  static constexpr size_t kMaxIdle = size_t(1) << 30;  // beyond this, freed blocks are released
+  ~SymPool() {
+    if (!idle.empty()) (void)hipDeviceSynchronize();
+    for (auto& kv : idle) (void)hipFree(kv.second);
+  }
+};
+
 struct tp_ctx {
   int device = 0;
+  std::shared_ptr<SymPool> sympool = std::make_shared<SymPool>();
   char* scratch = nullptr;       // device address of `scratch` on this context's device
   hipStream_t stream = nullptr;
   char* ws = nullptr;
@@ -113,13 +132,14 @@ struct tp_symbol {
   int tucker = 0;        // > 0: rank-r recompressed preconditioner (general canonical factors)
   double sinc_h = 0;     // step of the sinc rule (TP_SYM_SINC)
   bool arena = false;    // memory in a batched worker's workspace (nothing to free)
+  std::shared_ptr<SymPool> pool;  // where the blocks in `owned` go back to
   double* weights = nullptr;   // R (device)
   void* factors[3] = {nullptr, nullptr, nullptr};  // n x R (device, T)
   void* factors_w[3] = {nullptr, nullptr, nullptr};  // the same with column k scaled by weights[k]
   double* tau = nullptr;       // K
   double* w = nullptr;         // K
   double* lam[3] = {nullptr, nullptr, nullptr};
-  std::vector<void*> owned;
+  std::vector<std::pair<void*, size_t>> owned;  // blocks of `pool` (address, bytes)
 };
 
 namespace {
@@ -1465,18 +1485,58 @@ tp_status from_cp_impl(tp_ctx* c, const tp_cp* b, tp_tensor* out, double tol, bo
 }
 
 // ------------------------------------------------------------------------------ symbol build
-// Device memory of a symbol: its own allocation (freed by tp_symbol_free), or in a batched worker
-// a block of the worker's workspace below every scope (released after each problem).
+// Device memory of a symbol: a block of the context's symbol pool (an idle block of at least the
+// size and at most twice it, else a new allocation), returned to the pool by tp_symbol_free; or in
+// a batched worker a block of the worker's workspace below every scope (released after each
+// problem).
 template <typename T>
 tp_status sym_alloc(tp_ctx* c, tp_symbol* s, size_t count, T** p) {
   if (c->sym_arena) {
     s->arena = true;
     return wsalloc(c, count, p);
   }
-  if (hipMalloc(p, sizeof(T) * std::max<size_t>(count, 1)) != hipSuccess)
-    return fail(TP_ENOMEM, "symbol allocation of %zu bytes failed", sizeof(T) * count);
-  s->owned.push_back(*p);
+  const size_t bytes = (sizeof(T) * std::max<size_t>(count, 1) + 255) & ~size_t(255);
+  SymPool& pool = *c->sympool;
+  void* blk = nullptr;
+  size_t have = bytes;
+  {
+    std::lock_guard<std::mutex> g(pool.mu);
+    auto it = pool.idle.lower_bound(bytes);
+    if (it != pool.idle.end() && it->first <= 2 * bytes) {
+      blk = it->second;
+      have = it->first;
+      pool.idle_bytes -= have;
+      pool.idle.erase(it);
+    }
+  }
+  if (!blk && hipMalloc(&blk, bytes) != hipSuccess)
+    return fail(TP_ENOMEM, "symbol allocation of %zu bytes failed", bytes);
+  if (!s->pool) s->pool = c->sympool;
+  s->owned.push_back({blk, have});
+  *p = reinterpret_cast<T*>(blk);
   return TP_OK;
+}
+
+// A symbol's blocks back to its pool (those beyond the pool's idle limit are freed).
+void sym_release(tp_symbol* s) {
+  if (s->owned.empty()) return;
+  std::vector<void*> drop;
+  {
+    std::lock_guard<std::mutex> g(s->pool->mu);
+    for (const auto& b : s->owned) {
+      if (s->pool->idle_bytes + b.second <= SymPool::kMaxIdle) {
+        s->pool->idle.emplace(b.second, b.first);
+        s->pool->idle_bytes += b.second;
+      } else {
+        drop.push_back(b.first);
+      }
+    }
+  }
+  s->owned.clear();
+  if (!drop.empty()) {
+    (void)hipDeviceSynchronize();
+    for (void* p : drop) (void)hipFree(p);
+  }
 }
 
 // factors_w[m] = factors[m] diag(weights): the face-split operands that carry the weights read
@@ -2005,7 +2065,7 @@ tp_status tp_symbol_build(tp_ctx* c, const tp_symbol_desc* desc, tp_symbol** op,
   tp_symbol* s[2] = {new tp_symbol(), new tp_symbol()};
   auto cleanup = [&](tp_status st) {
     for (int i = 0; i < 2; ++i) {
-      if (s[i]) { for (void* p : s[i]->owned) (void)hipFree(p); delete s[i]; }
+      if (s[i]) { sym_release(s[i]); delete s[i]; }
     }
     return st;
   };
@@ -2158,7 +2218,7 @@ tp_status tp_state_symbol_build(tp_ctx* c, const tp_symbol_desc* desc, tp_symbol
   if (K < 2 || K > 64) return fail(TP_EINVAL, "op_terms=%d must be in [2,64]", K);
   tp_symbol* s = new tp_symbol();
   auto cleanup = [&](tp_status st) {
-    for (void* p : s->owned) (void)hipFree(p);
+    sym_release(s);
     delete s;
     return st;
   };
@@ -2207,8 +2267,8 @@ tp_status tp_symbol_free(tp_symbol* s) {
     delete s;
     return TP_OK;
   }
-  (void)hipDeviceSynchronize();
-  for (void* p : s->owned) (void)hipFree(p);
+  (void)hipDeviceSynchronize();  // work of any stream that still reads the symbol ends first
+  sym_release(s);
   delete s;
   return TP_OK;
 }

@@ -227,3 +227,44 @@ def test_warm_start(ctx, spectral):
     with pytest.raises(tp.TPError):
         ctx.pcg_solve(op, pre, p.weights, p.factors, X, tau=4e-8, kmax=100, trunc_tol=1e-8, cap=48, sketch=sk,
                       warm_start=True, allow=())
+
+
+def test_symbol_blocks_reused_and_symbol_outlives_its_context():
+    """tp_symbol_free hands a symbol's device blocks back to the context that built it: rebuilding
+    the same symbols reuses them and gives bitwise the same symbol values and the same solve; a
+    build of another size takes new blocks; a symbol freed after its context was destroyed still
+    releases its blocks."""
+    import paper_1809_01971_amd as tp
+    c = tp.Context(0, workspace_bytes=1 << 30)
+    ns = (63, 63, 63)
+    rng = np.random.default_rng(5)
+    idx = rng.integers(0, 63, size=(4096, 3))
+    F = [rng.standard_normal((63, 2)) for _ in ns]
+    w = np.ones(2)
+    vals, xs = [], []
+    for _ in range(3):
+        op, pre, _ = c.symbol_build(3, ns, 0.5, 1.0, 1e-2, prec=1, op_terms=28, pre_terms=28)
+        vals.append((op.eval(idx), pre.eval(idx)))
+        X, _ = _solve_with(c, op, pre, ns, F, w)
+        core, fac = X.numpy_parts()
+        xs.append(tensor.tucker_full(core, fac))
+        op.free()
+        pre.free()
+    for v, x in zip(vals[1:], xs[1:]):
+        assert np.array_equal(v[0], vals[0][0]) and np.array_equal(v[1], vals[0][1])
+        assert np.array_equal(x, xs[0])
+    big, bigpre, _ = c.symbol_build(3, (127, 127, 127), 0.5, 1.0, 1e-2, prec=1, op_terms=28, pre_terms=28)
+    small, smallpre, _ = c.symbol_build(3, ns, 0.5, 1.0, 1e-2, prec=1, op_terms=28, pre_terms=28)
+    assert np.array_equal(small.eval(idx), vals[0][0])
+    c.close()
+    for s in (big, bigpre, small, smallpre):
+        s.free()
+
+
+def _solve_with(ctx, op, pre, ns, F, w):
+    import paper_1809_01971_amd as tp
+    from paper_1809_01971_amd._tp import sketch_tensors
+    X = tp.Tensor(3, ns, 32, 1)
+    sk = sketch_tensors(workloads.sketch_matrices(ns, 3, 40))
+    st, info = ctx.pcg_solve(op, pre, w, F, X, tau=1e-4, kmax=100, trunc_tol=3e-5, cap=32, sketch=sk)
+    return X, info
