@@ -155,6 +155,7 @@ __global__ __launch_bounds__(GTHREADS) void k_gemm(GemmArgs<TA, TB, TC, Tacc> g)
 // on gfx950 with a one-wavefront probe).
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef double d2_t __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ f4_t mfma16(float a, float b, f4_t c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -185,12 +186,22 @@ struct OpRegs {
 
 // Element i of the thread's share: A tiles are M x K, B tiles K x N.  For a column-major A tile
 // (or a face-split one) lane groups run along M; for a transposed one along K; B the other way.
+// Along M (or N) a thread takes the 8 consecutive contraction indices of its wave's quarter of the
+// stage for one row, which it stores to LDS as one contiguous run.
 template <bool IS_A, int KIND>
 __device__ __forceinline__ void tile_pos(int tid, int i, int& outer, int& kk) {
   const bool alongK = IS_A ? (KIND == OP_T) : (KIND != OP_T);
   if (alongK) { kk = tid % MBK; outer = tid / MBK + (GTHREADS / MBK) * i; }
-  else { outer = tid & 63; kk = (tid >> 6) + 4 * i; }
+  else { outer = tid & 63; kk = MNE * (tid >> 6) + i; }
 }
+
+// LDS tile layout: row o of the tile (a row of A, a column of B) holds the stage's MBK contraction
+// indices contiguously, rows padded to a multiple of 16 bytes that spreads the 16 rows a quarter
+// wave reads over all banks.
+template <typename Tacc>
+struct LdsTile {
+  static constexpr int RS = MBK + (sizeof(Tacc) == 4 ? 4 : 2);  // row stride in elements
+};
 
 // Loads op's stage at (o0 along M or N, k0 along K); nout is M or N, the contraction runs to kend.
 // P: the operand's matrix (OP_N, OP_T), F: its face-split description (OP_FS).
@@ -230,22 +241,56 @@ __device__ __forceinline__ Tacc op_value(const OpRegs<T, KIND>& r, int i) {
   return ((r.ok >> i) & 1u) ? v : (Tacc)0;
 }
 
-// Writes the stage to LDS as T[k][m] (A) or T[k][n] (B).
+// Writes the stage to LDS as T[m][k] (A) or T[n][k] (B): a run of MNE values per thread along M,
+// single values along K.
 template <bool IS_A, int KIND, typename Tacc, typename T>
-__device__ __forceinline__ void op_store(Tacc (*S)[GBM + 4], int tid, const OpRegs<T, KIND>& r) {
+__device__ __forceinline__ void op_store(Tacc (*S)[LdsTile<Tacc>::RS], int tid, const OpRegs<T, KIND>& r) {
+  const bool alongK = IS_A ? (KIND == OP_T) : (KIND != OP_T);
+  if (alongK) {
 #pragma unroll
-  for (int i = 0; i < MNE; ++i) {
-    int o, kk;
-    tile_pos<IS_A, KIND>(tid, i, o, kk);
-    S[kk][o] = op_value<Tacc>(r, i);
+    for (int i = 0; i < MNE; ++i) {
+      int o, kk;
+      tile_pos<IS_A, KIND>(tid, i, o, kk);
+      S[o][kk] = op_value<Tacc>(r, i);
+    }
+  } else {
+    typedef typename std::conditional<sizeof(Tacc) == 4, f4_t, d2_t>::type V;
+    constexpr int W = 16 / sizeof(Tacc);
+    V* dst = reinterpret_cast<V*>(&S[tid & 63][MNE * (tid >> 6)]);
+#pragma unroll
+    for (int c = 0; c < MNE / W; ++c) {
+      V v;
+#pragma unroll
+      for (int e = 0; e < W; ++e) v[e] = op_value<Tacc>(r, W * c + e);
+      dst[c] = v;
+    }
+  }
+}
+
+// MNE consecutive LDS values from a 16-byte aligned address as 16-byte reads.
+__device__ __forceinline__ void lds_run(const float* p, float (&v)[MNE]) {
+#pragma unroll
+  for (int c = 0; c < MNE / 4; ++c) {
+    const f4_t x = reinterpret_cast<const f4_t*>(p)[c];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[4 * c + e] = x[e];
+  }
+}
+__device__ __forceinline__ void lds_run(const double* p, double (&v)[MNE]) {
+#pragma unroll
+  for (int c = 0; c < MNE / 2; ++c) {
+    const d2_t x = reinterpret_cast<const d2_t*>(p)[c];
+    v[2 * c] = x[0];
+    v[2 * c + 1] = x[1];
   }
 }
 
 template <typename TA, typename TB, typename TC, typename Tacc, int AK, int BK>
 __global__ __launch_bounds__(GTHREADS) void k_gemm_mfma(GemmGroup<TA, TB, TC, Tacc> grp) {
   typedef typename std::conditional<std::is_same<Tacc, double>::value, d4_t, f4_t>::type V4;
-  __shared__ Tacc As[MBK][GBM + 4];
-  __shared__ Tacc Bs[MBK][GBN + 4];
+  constexpr int RS = LdsTile<Tacc>::RS;
+  __shared__ __align__(16) Tacc As[GBM][RS];
+  __shared__ __align__(16) Tacc Bs[GBN][RS];
   // the product this workgroup belongs to: blockIdx.z runs over the products' batch x split ranges
   int z = blockIdx.z, j = 0;
   while (j + 1 < grp.count && z >= grp.z0[j + 1]) ++j;
@@ -292,16 +337,24 @@ __global__ __launch_bounds__(GTHREADS) void k_gemm_mfma(GemmGroup<TA, TB, TC, Ta
     }
     // the blocks are formed transposed, D = (A B)^T = B^T A^T (B's values in the first operand):
     // a lane's results then lie along a column of C, so each store instruction writes runs of
-    // 16 consecutive rows (64 or 128 contiguous bytes) instead of 16 different columns
+    // 16 consecutive rows (64 or 128 contiguous bytes) instead of 16 different columns.  Lane
+    // group g = lane / 16 supplies the contraction indices 8 g .. 8 g + 7 of the stage (the
+    // instruction's k slot s of step t is index 8 g + t for both operands, so the products are
+    // the same), read as 16-byte runs
+    {
+      const int c16 = lane & 15, kq = MNE * (lane >> 4);
+      Tacc a0[MNE], a1[MNE], b0[MNE], b1[MNE];
+      lds_run(&As[wm + c16][kq], a0);
+      lds_run(&As[wm + 16 + c16][kq], a1);
+      lds_run(&Bs[wn + c16][kq], b0);
+      lds_run(&Bs[wn + 16 + c16][kq], b1);
 #pragma unroll
-    for (int kk = 0; kk < MBK; kk += 4) {
-      const int kr = kk + (lane >> 4), c16 = lane & 15;
-      Tacc a0 = As[kr][wm + c16], a1 = As[kr][wm + 16 + c16];
-      Tacc b0 = Bs[kr][wn + c16], b1 = Bs[kr][wn + 16 + c16];
-      acc[0][0] = mfma16(b0, a0, acc[0][0]);
-      acc[0][1] = mfma16(b1, a0, acc[0][1]);
-      acc[1][0] = mfma16(b0, a1, acc[1][0]);
-      acc[1][1] = mfma16(b1, a1, acc[1][1]);
+      for (int t = 0; t < MNE; ++t) {
+        acc[0][0] = mfma16(b0[t], a0[t], acc[0][0]);
+        acc[0][1] = mfma16(b1[t], a0[t], acc[0][1]);
+        acc[1][0] = mfma16(b0[t], a1[t], acc[1][0]);
+        acc[1][1] = mfma16(b1[t], a1[t], acc[1][1]);
+      }
     }
     __syncthreads();
   }
@@ -1038,7 +1091,16 @@ __device__ __forceinline__ double readlane_pick(const double (&a)[N], int r, int
   return v;
 }
 
-template <int NT>
+// Index of the trailing matrix entry S(i, j): column-major with leading dimension K, or (PACKED) the
+// lower triangle by columns, K (K + 1) / 2 entries.
+template <bool PACKED>
+__device__ __forceinline__ int s_idx(int i, int j, int K) {
+  if (!PACKED) return i + K * j;
+  const int lo = min(i, j), hi = max(i, j);
+  return lo * (2 * K - lo - 1) / 2 + hi;
+}
+
+template <int NT, bool PACKED = false>
 __device__ __forceinline__ int chol_phase_blk(const double* G, int K, double ctol, double* S, double* Lc, double* dk,
                                               int* perm, int* mark, CholShared& sh) {
   constexpr int RPL = CholBlk<NT>::RPL, NB = CholBlk<NT>::NB, IB = CholBlk<NT>::IB;
@@ -1048,7 +1110,8 @@ __device__ __forceinline__ int chol_phase_blk(const double* G, int K, double cto
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int e = tid; e < K * K; e += NT) {
     const int i = e % K, j = e / K;
-    S[e] = G[min(i, j) + (long)K * max(i, j)];
+    if (PACKED && i < j) continue;
+    S[s_idx<PACKED>(i, j, K)] = G[min(i, j) + (long)K * max(i, j)];
   }
   // wave 0: the Schur diagonal of rows lane + 64 r, the scale of the pivot keys, the threshold
   double d[RPL];
@@ -1095,7 +1158,7 @@ __device__ __forceinline__ int chol_phase_blk(const double* G, int K, double cto
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
           const int row = lane + 64 * r;
-          double c = row < K ? S[row + K * p] : 0.0;
+          double c = row < K ? S[s_idx<PACKED>(row, p, K)] : 0.0;
 #pragma unroll
           for (int u = 0; u < t; ++u) c = fma(-lrow[u][r], lp[u], c);
           const double l = row == p ? sp : c * rs;
@@ -1142,7 +1205,7 @@ __device__ __forceinline__ int chol_phase_blk(const double* G, int K, double cto
 #pragma unroll
           for (int a = 0; a < AC; ++a) {
             const int i = tx + TX * (a0 + a), j = ty + TY * b;
-            if (i < K && j < K) S[i + K * j] -= acc[a][b];
+            if (i < K && j < K && (!PACKED || i >= j)) S[s_idx<PACKED>(i, j, K)] -= acc[a][b];
           }
       }
     }
@@ -1304,6 +1367,155 @@ hipError_t launch_gram(void (*kern)(JobBatch<Job>), const JobBatch<Job>& jobs, i
   return hipGetLastError();
 }
 
+// Orders 128 < K <= 192 on 1024 threads with everything in LDS but L: the trailing matrix as its
+// packed lower triangle (K (K + 1) / 2 doubles, 148 KB at K = 192), L in the job's global scratch.
+// R (pivot order) then takes the same place as a packed upper triangle by columns, and X = R^-1 is
+// formed there by blocks of 64 rows and columns: the diagonal blocks X_II = R_II^-1 by the register
+// scheme of pchol64 (256 threads each, all blocks at once), then
+//   X_IJ = -X_II (sum_{I < L <= J} R_IL X_LJ),  I < J,
+// every block product held in registers and written over the R block it replaces once no thread
+// reads that block any more (the barriers between the steps).
+constexpr int CHOL_PACKED_MAX = 192;
+
+__device__ __forceinline__ int up_idx(int i, int l) { return l * (l + 1) / 2 + i; }
+
+// Entries (a, c + 16 u), u < 4, of the product of the 64-blocks (ra, ca) and (rb, cb) of the
+// packed upper triangle Rp (q x q) over the first kn indices; a diagonal block contributes its
+// upper triangle only.  Out-of-range rows and columns are clamped into the matrix (their results
+// are not used).
+__device__ __forceinline__ void blk_mm4(const double* Rp, int q, int ra, int ca, int rb, int cb, int kn, int a, int c,
+                                        double (&out)[4]) {
+  const int gi = min(64 * ra + a, q - 1);
+  for (int b = 0; b < kn; ++b) {
+    const int gl = 64 * ca + b, gr = 64 * rb + b;
+    const double av = gi <= gl ? Rp[up_idx(gi, gl)] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int gc = min(64 * cb + c + 16 * u, q - 1);
+      const double bv = gr <= gc ? Rp[up_idx(gr, gc)] : 0.0;
+      out[u] = fma(av, bv, out[u]);
+    }
+  }
+}
+// Writes s * v[u] to the entries (a, c + 16 u) of the 64-block (rb, cb) that lie inside it.
+__device__ __forceinline__ void blk_put4(double* Rp, int rb, int cb, int nr, int nc, int a, int c, double sgn,
+                                         const double (&v)[4]) {
+  if (a >= nr) return;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    if (c + 16 * u < nc) Rp[up_idx(64 * rb + a, 64 * cb + c + 16 * u)] = sgn * v[u];
+}
+
+__global__ __launch_bounds__(1024) void k_pchol_packed(JobBatch<CholJob> jobs) {
+  extern __shared__ double sm[];
+  constexpr int NT = 1024, NW = NT / 64;
+  const CholJob J = jobs.j[blockIdx.x];
+  const int K = J.K;
+  const int tid = threadIdx.x;
+  if (K <= 0) { if (tid == 0 && J.q) *J.q = 0; return; }
+  double* Lc = J.work;
+  double* S = sm;
+  double* dk = sm + (size_t)K * (K + 1) / 2;
+  double* xd = dk + K;
+  int* perm = reinterpret_cast<int*>(xd + K + 2 * NW);
+  int* mark = reinterpret_cast<int*>(xd);  // free until the inverse
+  __shared__ CholShared sh;
+  const int q = chol_phase_blk<NT, true>(J.g, K, J.tol, S, Lc, dk, perm, mark, sh);
+  double* Rp = S;
+  for (int e = tid; e < q * q; e += NT) {
+    const int i = e % q, l = e / q;
+    if (i <= l) Rp[up_idx(i, l)] = Lc[i * K + perm[l]];
+  }
+  for (int i = tid; i < q; i += NT) xd[i] = 1.0 / Lc[i * K + perm[i]];
+  __syncthreads();
+  const int nb = (q + 63) / 64;
+  const int n0 = min(q, 64), n1 = max(0, min(q - 64, 64)), n2 = max(0, q - 128);
+  // diagonal blocks: 256 threads per block, four lanes per column jj, lane li holding the rows
+  // li (mod 4) of X(:, jj) in registers (rows bottom-up)
+  {
+    const int bI = tid >> 8, jj = (tid & 255) >> 2, li = tid & 3;
+    const int o = 64 * bI, n = bI < nb ? min(64, q - o) : 0;
+    double xr[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) xr[t] = 0.0;
+#pragma unroll
+    for (int i = 63; i >= 0; --i) {
+      if (i < n && jj < n && i <= jj) {  // the same for the four lanes of a column
+        double part = 0.0;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+          if (4 * t + 3 > i) {  // rows l = li + 4 t <= i never contribute
+            const int l = li + 4 * t;
+            const double rv = Rp[up_idx(o + i, o + min(l, n - 1))];
+            part = (l > i && l <= jj) ? fma(rv, xr[t], part) : part;
+          }
+        }
+        part += dpp_f64<0xB1>(part);
+        part += dpp_f64<0x4E>(part);
+        const double x = i == jj ? xd[o + i] : -part * xd[o + i];
+        if (li == (i & 3)) xr[i >> 2] = x;
+      }
+    }
+    __syncthreads();
+    if (jj < n) {
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        const int l = li + 4 * t;
+        if (l <= jj) Rp[up_idx(o + l, o + jj)] = xr[t];
+      }
+    }
+    __syncthreads();
+  }
+  // off-diagonal blocks: thread (a, c) forms the entries (a, c + 16 u) of a block product
+  const int a = tid & 63, c = tid >> 6;
+  if (nb == 3) {
+    double t23[4] = {0.0, 0.0, 0.0, 0.0};
+    blk_mm4(Rp, q, 1, 2, 2, 2, n2, a, c, t23);           // R23 X33
+    __syncthreads();
+    blk_put4(Rp, 1, 2, n1, n2, a, c, 1.0, t23);
+    __syncthreads();
+    double x23[4] = {0.0, 0.0, 0.0, 0.0};
+    blk_mm4(Rp, q, 1, 1, 1, 2, n1, a, c, x23);           // X22 (R23 X33)
+    __syncthreads();
+    blk_put4(Rp, 1, 2, n1, n2, a, c, -1.0, x23);        // X23
+    __syncthreads();
+    double t13[4] = {0.0, 0.0, 0.0, 0.0}, s12[4] = {0.0, 0.0, 0.0, 0.0};
+    blk_mm4(Rp, q, 0, 1, 1, 2, n1, a, c, t13);           // R12 X23
+    blk_mm4(Rp, q, 0, 2, 2, 2, n2, a, c, t13);           //   + R13 X33
+    blk_mm4(Rp, q, 0, 1, 1, 1, n1, a, c, s12);           // R12 X22
+    __syncthreads();
+    blk_put4(Rp, 0, 2, n0, n2, a, c, 1.0, t13);
+    blk_put4(Rp, 0, 1, n0, n1, a, c, 1.0, s12);
+    __syncthreads();
+    double x13[4] = {0.0, 0.0, 0.0, 0.0}, x12[4] = {0.0, 0.0, 0.0, 0.0};
+    blk_mm4(Rp, q, 0, 0, 0, 2, n0, a, c, x13);
+    blk_mm4(Rp, q, 0, 0, 0, 1, n0, a, c, x12);
+    __syncthreads();
+    blk_put4(Rp, 0, 2, n0, n2, a, c, -1.0, x13);        // X13
+    blk_put4(Rp, 0, 1, n0, n1, a, c, -1.0, x12);        // X12
+    __syncthreads();
+  } else if (nb == 2) {
+    double s12[4] = {0.0, 0.0, 0.0, 0.0};
+    blk_mm4(Rp, q, 0, 1, 1, 1, n1, a, c, s12);           // R12 X22
+    __syncthreads();
+    blk_put4(Rp, 0, 1, n0, n1, a, c, 1.0, s12);
+    __syncthreads();
+    double x12[4] = {0.0, 0.0, 0.0, 0.0};
+    blk_mm4(Rp, q, 0, 0, 0, 1, n0, a, c, x12);
+    __syncthreads();
+    blk_put4(Rp, 0, 1, n0, n1, a, c, -1.0, x12);        // X12
+    __syncthreads();
+  }
+  // W = P X: every row of column j written once (perm is a permutation of 0..K-1)
+  for (int e = tid; e < K * q; e += NT) J.w[e] = 0.0;
+  __syncthreads();
+  for (int e = tid; e < q * q; e += NT) {
+    const int l = e % q, j = e / q;
+    if (l <= j) J.w[perm[l] + (long)K * j] = Rp[up_idx(l, j)];
+  }
+  if (tid == 0 && J.q) *J.q = q;
+}
+
 hipError_t pchol_batched(const JobBatch<CholJob>& jobs_dev, int count, int Kmax, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   if (count > kBatchJobs) return hipErrorInvalidValue;
@@ -1313,6 +1525,8 @@ hipError_t pchol_batched(const JobBatch<CholJob>& jobs_dev, int count, int Kmax,
   if (Kmax <= 64)
     return launch_gram<true, 256>(k_pchol<true, 256>, jobs_dev, count, (size_t)Kmax * Kmax * 16 + (size_t)Kmax * 20 + 64, s);
   if (Kmax <= EIG_LDS_MAX) return launch_gram<true, 512>(k_pchol<true, 512>, jobs_dev, count, shm, s);
+  if (Kmax <= CHOL_PACKED_MAX)
+    return launch_gram<true, 1024>(k_pchol_packed, jobs_dev, count, (size_t)Kmax * (Kmax + 1) / 2 * 8 + extra, s);
   return launch_gram<false, 1024>(k_pchol<false, 1024>, jobs_dev, count, extra, s);
 }
 

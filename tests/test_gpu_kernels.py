@@ -233,6 +233,35 @@ def test_truncate_sum_hosvd_bound(ctx, eps, prec):
     assert rel(got2, full_ref + tensor.cp_full(w1, F1)) <= 2.5 * eps + (0 if prec == 0 else 4e-6)
 
 
+@pytest.mark.parametrize("a,c,e", [(40, 56, 56), (4, 63, 63), (70, 26, 26), (20, 76, 40)])
+def test_truncate_large_rank_sums_fp64(ctx, a, c, e):
+    """FP64 sums X1 + X2 with X1 = A + C and X2 = -A + D (canonical ranks a, c, e): the stacked
+    factors have a + c + a + e = 134..192 columns per mode and a joint span of a + c + e (the
+    orthonormalisation's pivoted Cholesky of orders above 128, rank-deficient), while the sum is
+    exactly C + D.  Truncated at eps = 1e-12, the result is C + D (checked on every 5th grid index
+    per mode) with mode ranks c + e."""
+    import paper_1809_01971_amd as tp
+    n, d = 255, 3
+    log("truncate large ranks a=%d c=%d e=%d" % (a, c, e))
+    rng = np.random.default_rng(a + 7 * c + 13 * e)
+    FA = [rng.standard_normal((n, a)) for _ in range(d)]
+    FC = [rng.standard_normal((n, c)) for _ in range(d)]
+    FD = [rng.standard_normal((n, e)) for _ in range(d)]
+    wA, wC, wD = rng.standard_normal(a), rng.standard_normal(c), rng.standard_normal(e)
+    X1, X2, Y = tp.Tensor(d, n, 128, 0), tp.Tensor(d, n, 128, 0), tp.Tensor(d, n, 128, 0)
+    ctx.from_cp(np.concatenate([wA, wC]), [np.hstack([FA[m], FC[m]]) for m in range(d)], X1)
+    ctx.from_cp(np.concatenate([-wA, wD]), [np.hstack([FA[m], FD[m]]) for m in range(d)], X2)
+    assert list(X1.rank) == [a + c] * d and list(X2.rank) == [a + e] * d
+    ctx.truncate([1.0, 1.0], [X1, X2], Y, 1e-12, 128)
+    rows = np.arange(0, n, 5)
+    got = ctx.eval_grid(Y, [rows] * d)
+    ref = tensor.cp_full(wC, [f[rows] for f in FC]) + tensor.cp_full(wD, [f[rows] for f in FD])
+    err = rel(got, ref)
+    log("  err %.2e ranks %s" % (err, Y.rank))
+    assert err <= 1e-10
+    assert list(Y.rank) == [c + e] * d
+
+
 @pytest.mark.parametrize("d,n,alpha", [(3, 31, 0.5), (2, 63, 0.25), (3, 63, 0.75)])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_apply_matches_spectral_product(ctx, d, n, alpha, prec):
