@@ -1720,7 +1720,9 @@ __device__ __forceinline__ void jacobi_wave(double* X, int K, int q, double jtol
   }
 }
 
-template <bool SMEM, int NT>
+// PACKED (orders 129..CHOL_PACKED_MAX): the factorisation's trailing matrix packed in LDS, X in
+// global memory.
+template <bool SMEM, int NT, bool PACKED = false>
 __global__ __launch_bounds__(NT) void k_psd_eig(JobBatch<PsdJob> jobs) {
   extern __shared__ double sm[];
   constexpr int KMAX = ChGrid<NT>::KMAX, NW = NT / 64;
@@ -1731,11 +1733,11 @@ __global__ __launch_bounds__(NT) void k_psd_eig(JobBatch<PsdJob> jobs) {
     if (tid == 0) { *J.q = 0; *J.rest = 0.0; }
     return;
   }
-  // K > 64: L in the job's global scratch (first K^2), the trailing matrix in LDS (K <= 128) or
-  // after L, and X in the trailing matrix's place
-  double* S = SMEM ? sm : J.work + (size_t)K * K;
-  double* X = S;                                       // K x q, ld K
-  double* base = SMEM ? sm + (size_t)K * K : sm;
+  // K > 64: L in the job's global scratch (first K^2), the trailing matrix in LDS (K <= 128, or
+  // packed) or after L, and X in the trailing matrix's place (after L when it was packed)
+  double* S = (SMEM || PACKED) ? sm : J.work + (size_t)K * K;
+  double* X = PACKED ? J.work + (size_t)K * K : S;     // K x q, ld K
+  double* base = SMEM ? sm + (size_t)K * K : (PACKED ? sm + (size_t)K * (K + 1) / 2 : sm);
   double* dk = base;                                   // K pivots; later column norms^2
   unsigned long long* slot = reinterpret_cast<unsigned long long*>(dk + K);  // 2 x NW keys
   int* perm = reinterpret_cast<int*>(slot + 2 * NW);   // K
@@ -1757,7 +1759,7 @@ __global__ __launch_bounds__(NT) void k_psd_eig(JobBatch<PsdJob> jobs) {
     }
   } else {
     double* Lc = J.work;
-    q = chol_phase_blk<NT>(J.g, K, J.ctol, S, Lc, dk, perm, rank, sh);
+    q = chol_phase_blk<NT, PACKED>(J.g, K, J.ctol, S, Lc, dk, perm, rank, sh);
     for (int e = tid; e < K * q; e += NT) {
       const int l = e % K, k = e / K;
       X[e] = l >= k ? Lc[k * K + perm[l]] : 0.0;
@@ -1899,6 +1901,9 @@ hipError_t psd_eig_batched(const JobBatch<PsdJob>& jobs_dev, int count, int Kmax
   // K <= 64: the factor L in its own block after the scratch
   if (Kmax <= 64) return launch_gram<true, 256>(k_psd_eig<true, 256>, jobs_dev, count, shm + (size_t)Kmax * Kmax * 8, s);
   if (Kmax <= EIG_LDS_MAX) return launch_gram<true, 512>(k_psd_eig<true, 512>, jobs_dev, count, shm, s);
+  if (Kmax <= CHOL_PACKED_MAX)
+    return launch_gram<true, 1024>(k_psd_eig<false, 1024, true>, jobs_dev, count,
+                                   (size_t)Kmax * (Kmax + 1) / 2 * 8 + extra, s);
   return launch_gram<false, 1024>(k_psd_eig<false, 1024>, jobs_dev, count, extra, s);
 }
 
