@@ -388,5 +388,8 @@ def test_directional_state(ctx):
     y = sfft.idstn(beta * uh / spectral.rho_directional((n,) * d, alpha), type=1, norm="ortho")
     err = rel(ctx.eval_grid(Y, [np.arange(n)] * d), y)
     log("directional state: err %.2e (symbol %.2e)" % (err, serr))
-    # the symbol's error is measured on 4096 log-spaced points of [rho'_min, rho'_max]
-    assert serr < 1e-7 and err < 4 * serr
+    # the symbol's error is measured on 4096 log-spaced points of [rho'_min, rho'_max]; on top of
+    # it the product carries the floor of its FP64 range finder: the Gram-based orthonormalisation
+    # of the sketch keeps directions down to sqrt(1e-15) ~ 3e-8 of the largest singular value per
+    # mode, about 1.2e-7 here whatever the symbol's own error
+    assert serr < 1e-7 and err < 4 * serr + 2e-7
