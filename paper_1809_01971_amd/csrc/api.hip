@@ -812,8 +812,10 @@ tp_status hosvd(tp_ctx* c, int d, const int* q, const T* M, double tol, int cap,
       float *Uf0, *Uf1, *X1;
       TPCHK(wsalloc(c, (size_t)q[0] * q[0], &Uf0));
       TPCHK(wsalloc(c, (size_t)q[1] * q[1], &Uf1));
-      HIPCHK((convert<double, float>(U[0], Uf0, (long)q[0] * rout[0], c->stream)));
-      HIPCHK((convert<double, float>(U[1], Uf1, (long)q[1] * rout[1], c->stream)));
+      ConvBatch<double, float> cb;
+      cb.add(U[0], Uf0, (long)q[0] * rout[0]);
+      cb.add(U[1], Uf1, (long)q[1] * rout[1]);
+      HIPCHK(convert_batch(cb, c->stream));
       TPCHK(wsalloc(c, (size_t)rout[0] * q[1], &X1));
       TPCHK((mm<float, float, float, float>(c, true, false, rout[0], q[1], q[0], 1.0, Uf0, q[0], (const float*)M, q[0], 0.0, X1, rout[0])));
       TPCHK((mm<float, float, TO, typename std::conditional<std::is_same<TO, double>::value, double, float>::type>(
@@ -838,10 +840,12 @@ tp_status hosvd(tp_ctx* c, int d, const int* q, const T* M, double tol, int cap,
   } else {
     const float* Mf = (const float*)M;
     float *Uf[3], *X1, *X2;
+    ConvBatch<double, float> cb;
     for (int m = 0; m < 3; ++m) {
       TPCHK(wsalloc(c, (size_t)q[m] * rout[m], &Uf[m]));
-      HIPCHK((convert<double, float>(U[m], Uf[m], (long)q[m] * rout[m], c->stream)));
+      cb.add(U[m], Uf[m], (long)q[m] * rout[m]);
     }
+    HIPCHK(convert_batch(cb, c->stream));
     TPCHK(wsalloc(c, (size_t)rout[0] * q[1] * q[2], &X1));
     TPCHK(wsalloc(c, (size_t)rout[0] * rout[1] * q[2], &X2));
     TPCHK((mm<float, float, float, float>(c, true, false, rout[0], q[1] * q[2], q[0], 1.0, Uf[0], q[0], Mf, q[0], 0.0, X1, rout[0])));
@@ -1019,15 +1023,19 @@ tp_status combo_impl(tp_ctx* c, const Term* terms, int nt, tp_tensor* y, double 
   std::vector<Prep> pr(nterm);
   // sketch matrices in T
   const T* Om[3];
-  for (int m = 0; m < d; ++m) {
-    if (std::is_same<T, double>::value) {
-      Om[m] = (const T*)sk->omega[m];
-    } else {
-      T* o;
-      TPCHK(wsalloc(c, (size_t)y->n[m] * Qs, &o));
-      HIPCHK((convert<double, T>(sk->omega[m], o, (long)y->n[m] * Qs, c->stream)));
-      Om[m] = o;
+  {
+    ConvBatch<double, T> cb;
+    for (int m = 0; m < d; ++m) {
+      if (std::is_same<T, double>::value) {
+        Om[m] = (const T*)sk->omega[m];
+      } else {
+        T* o;
+        TPCHK(wsalloc(c, (size_t)y->n[m] * Qs, &o));
+        cb.add(sk->omega[m], o, (long)y->n[m] * Qs);
+        Om[m] = o;
+      }
     }
+    HIPCHK(convert_batch(cb, c->stream));
   }
   // the factors of every term in sine coordinates (one launch for all of them)
   {
@@ -1140,13 +1148,17 @@ tp_status combo_impl(tp_ctx* c, const Term* terms, int nt, tp_tensor* y, double 
   for (int m = 0; m < d; ++m)
     if (q[m] == 0) return set_zero<T>(c, y);
   T* Qt[3];
-  for (int m = 0; m < d; ++m) {
-    if (std::is_same<T, double>::value) {
-      Qt[m] = (T*)Qb[m];
-    } else {
-      TPCHK(wsalloc(c, (size_t)y->n[m] * q[m], &Qt[m]));
-      HIPCHK((convert<double, T>(Qb[m], Qt[m], (long)y->n[m] * q[m], c->stream)));
+  {
+    ConvBatch<double, T> cb;
+    for (int m = 0; m < d; ++m) {
+      if (std::is_same<T, double>::value) {
+        Qt[m] = (T*)Qb[m];
+      } else {
+        TPCHK(wsalloc(c, (size_t)y->n[m] * q[m], &Qt[m]));
+        cb.add(Qb[m], Qt[m], (long)y->n[m] * q[m]);
+      }
     }
+    HIPCHK(convert_batch(cb, c->stream));
   }
   // projected core
   size_t msz = (size_t)q[0] * q[1] * (d == 3 ? q[2] : 1);
@@ -1296,8 +1308,12 @@ tp_status inner_sym_impl(tp_ctx* c, const tp_tensor* x, const tp_symbol* S, cons
   TPCHK(wsalloc(c, cy, &Cy));
   TPCHK(wsalloc(c, cx, &Z));
   TPCHK(wsalloc(c, 257, &res));  // result + per-workgroup partial sums
-  HIPCHK((convert<T, double>((const T*)x->core, Cx, (long)cx, c->stream)));
-  HIPCHK((convert<T, double>((const T*)y->core, Cy, (long)cy, c->stream)));
+  {
+    ConvBatch<T, double> cb;
+    cb.add((const T*)x->core, Cx, (long)cx);
+    cb.add((const T*)y->core, Cy, (long)cy);
+    HIPCHK(convert_batch(cb, c->stream));
+  }
   // Z = sum_k Cy x_1 G1_k x_2 G2_k x_3 G3_k  (rx1 x rx2 x rx3)
   if (d == 3) {
     double *D, *E;
@@ -1385,8 +1401,12 @@ tp_status inner_impl(tp_ctx* c, const tp_tensor* x, const tp_tensor* y, double* 
   TPCHK(wsalloc(c, cx, &Cx));
   TPCHK(wsalloc(c, cx, &Z));
   TPCHK(wsalloc(c, 257, &res));  // result + per-workgroup partial sums
-  HIPCHK((convert<T, double>((const T*)y->core, Cy, (long)cy, c->stream)));
-  HIPCHK((convert<T, double>((const T*)x->core, Cx, (long)cx, c->stream)));
+  {
+    ConvBatch<T, double> cb;
+    cb.add((const T*)y->core, Cy, (long)cy);
+    cb.add((const T*)x->core, Cx, (long)cx);
+    HIPCHK(convert_batch(cb, c->stream));
+  }
   const double* A[3] = {G[0], G[1], G[2]};
   int lda[3] = {px[0], px[1], px[2]};
   bool tA[3] = {false, false, false};
@@ -1476,11 +1496,13 @@ tp_status from_cp_impl(tp_ctx* c, const tp_cp* b, tp_tensor* out, double tol, bo
   }
   for (int m = 0; m < d; ++m)
     if (q[m] > out->cap) return fail(TP_ERANK, "from_cp: mode %d rank %d exceeds cap %d", m, q[m], out->cap);
-  HIPCHK((convert<double, T>(M, (T*)out->core, (long)msz, c->stream)));
+  ConvBatch<double, T> cb;
+  cb.add(M, (T*)out->core, (long)msz);
   for (int m = 0; m < d; ++m) {
-    HIPCHK((convert<double, T>(Q[m], (T*)out->factor[m], (long)b->n[m] * q[m], c->stream)));
+    cb.add(Q[m], (T*)out->factor[m], (long)b->n[m] * q[m]);
     out->rank[m] = q[m];
   }
+  HIPCHK(convert_batch(cb, c->stream));
   return TP_OK;
 }
 
@@ -1543,33 +1565,43 @@ void sym_release(tp_symbol* s) {
 // them from there (one product per element instead of a third load and an FP64 multiply)
 template <typename T>
 tp_status build_weighted(tp_ctx* c, tp_symbol* s) {
+  ScaleBatch<T> b;
   for (int m = 0; m < s->d; ++m) {
     T* F = nullptr;
     TPCHK(sym_alloc(c, s, (size_t)s->n[m] * s->R, &F));
-    HIPCHK(scale_cols_copy<T>((const T*)s->factors[m], s->n[m], s->R, s->weights, F, c->stream));
+    b.in[m] = (const T*)s->factors[m];
+    b.out[m] = F;
+    b.rows[m] = s->n[m];
+    b.cols[m] = s->R;
+    b.w[m] = s->weights;
     s->factors_w[m] = F;
   }
+  b.count = s->d;
+  HIPCHK(scale_cols_copy_batch<T>(b, c->stream));
   return TP_OK;
 }
 
 template <typename T>
 tp_status build_factors(tp_ctx* c, tp_symbol* s) {
+  // every mode and block of the factors in one launch (at most d (d + 1) = 12 jobs)
+  ExpBatch<T> eb;
   for (int m = 0; m < s->d; ++m) {
     T* F = nullptr;
     TPCHK(sym_alloc(c, s, (size_t)s->n[m] * s->R, &F));
     s->factors[m] = F;
     if (s->kind == 0) {
       for (int blk = 0; blk < s->d; ++blk)
-        HIPCHK(expfactors<T>(s->lam[m], s->n[m], s->tau, s->K, F + (size_t)s->n[m] * s->K * blk, s->n[m],
-                             blk == m ? 1 : 0, c->stream));
+        if (!eb.add(s->lam[m], s->n[m], s->tau, s->K, F + (size_t)s->n[m] * s->K * blk, s->n[m], blk == m ? 1 : 0))
+          return fail(TP_EINVAL, "too many factor blocks");
       // constant term: exp(-0 * lambda) = 1 in every mode (tau holds a trailing zero)
       if (s->R > s->d * s->K)
-        HIPCHK(expfactors<T>(s->lam[m], s->n[m], s->tau + s->K, 1, F + (size_t)s->n[m] * s->K * s->d, s->n[m], 0,
-                             c->stream));
+        if (!eb.add(s->lam[m], s->n[m], s->tau + s->K, 1, F + (size_t)s->n[m] * s->K * s->d, s->n[m], 0))
+          return fail(TP_EINVAL, "too many factor blocks");
     } else {
-      HIPCHK(expfactors<T>(s->lam[m], s->n[m], s->tau, s->K, F, s->n[m], 0, c->stream));
+      if (!eb.add(s->lam[m], s->n[m], s->tau, s->K, F, s->n[m], 0)) return fail(TP_EINVAL, "too many factor blocks");
     }
   }
+  HIPCHK(expfactors_batch<T>(eb, c->stream));
   TPCHK(sym_alloc(c, s, (size_t)s->R, &s->weights));
   for (int blk = 0; blk < (s->kind == 0 ? s->d : 1); ++blk)
     HIPCHK(hipMemcpyAsync(s->weights + (size_t)blk * s->K, s->w, sizeof(double) * s->K, hipMemcpyDeviceToDevice, c->stream));
@@ -1809,6 +1841,9 @@ tp_status fit_expsum_multi(tp_ctx* c, std::vector<FitSpec>& fits) {
   }
   HIPCHK(hipStreamSynchronize(c->stream));
   const double* herr = c->hmap;
+  // copies on the compute stream (the workspace they read is released in stream order), two fits
+  // per launch
+  ConvBatch<double, double> cb;
   for (int i = 0; i < nf; ++i) {
     FitSpec& F = fits[i];
     const Buf& b = bf[i];
@@ -1816,9 +1851,12 @@ tp_status fit_expsum_multi(tp_ctx* c, std::vector<FitSpec>& fits) {
     for (int ci = 1; ci < b.nc; ++ci)
       if (herr[b.off + ci] < herr[b.off + best] || std::isnan(herr[b.off + best])) best = ci;
     F.err = herr[b.off + best];
-    // copies on the compute stream (the workspace they read is released in stream order)
-    HIPCHK((convert<double, double>(b.t + (size_t)best * F.K, F.tau_out, F.K, c->stream)));
-    HIPCHK((convert<double, double>(b.wsol + (size_t)best * F.K, F.w_out, F.K, c->stream)));
+    cb.add(b.t + (size_t)best * F.K, F.tau_out, F.K);
+    cb.add(b.wsol + (size_t)best * F.K, F.w_out, F.K);
+    if (cb.n + 2 > kConvJobs || i + 1 == nf) {
+      HIPCHK(convert_batch(cb, c->stream));
+      cb.n = 0;
+    }
   }
   return TP_OK;
 }
@@ -2070,6 +2108,7 @@ tp_status tp_symbol_build(tp_ctx* c, const tp_symbol_desc* desc, tp_symbol** op,
     return st;
   };
   double lam1[3], lamn[3];
+  LamBatch lb;  // the 1D spectra of both symbols in one launch
   for (int i = 0; i < 2; ++i) {
     s[i]->d = D.d;
     s[i]->prec = D.prec;
@@ -2079,9 +2118,10 @@ tp_status tp_symbol_build(tp_ctx* c, const tp_symbol_desc* desc, tp_symbol** op,
       double* l = nullptr;
       if (sym_alloc(c, s[i], (size_t)D.n[m], &l) != TP_OK) return cleanup(TP_ENOMEM);
       s[i]->lam[m] = l;
-      if (lambda_1d(D.n[m], l, c->stream, power) != hipSuccess) return cleanup(fail(TP_EHIP, "lambda kernel failed"));
+      if (!lb.add(D.n[m], l, power)) return cleanup(fail(TP_EINVAL, "too many spectra"));
     }
   }
+  if (lambda_batch(lb, c->stream) != hipSuccess) return cleanup(fail(TP_EHIP, "lambda kernel failed"));
   for (int m = 0; m < D.d; ++m) {
     double h = 1.0 / (D.n[m] + 1.0);
     lam1[m] = std::pow(4.0 / (h * h) * std::pow(std::sin(M_PI * h / 2), 2), power);
@@ -2499,11 +2539,13 @@ template <typename T>
 tp_status copy_tensor(tp_ctx* c, const tp_tensor* src, tp_tensor* dst) {
   const int d = src->d;
   size_t csz = (size_t)src->rank[0] * src->rank[1] * (d == 3 ? src->rank[2] : 1);
-  HIPCHK((convert<T, T>((const T*)src->core, (T*)dst->core, (long)csz, c->stream)));
+  ConvBatch<T, T> cb;
+  cb.add((const T*)src->core, (T*)dst->core, (long)csz);
   for (int m = 0; m < d; ++m) {
-    HIPCHK((convert<T, T>((const T*)src->factor[m], (T*)dst->factor[m], (long)src->n[m] * src->rank[m], c->stream)));
+    cb.add((const T*)src->factor[m], (T*)dst->factor[m], (long)src->n[m] * src->rank[m]);
     dst->rank[m] = src->rank[m];
   }
+  HIPCHK(convert_batch(cb, c->stream));
   return TP_OK;
 }
 

@@ -2370,6 +2370,31 @@ template hipError_t convert<float, double>(const float*, double*, long, hipStrea
 template hipError_t convert<double, double>(const double*, double*, long, hipStream_t);
 template hipError_t convert<float, float>(const float*, float*, long, hipStream_t);
 
+// blockIdx.y is the job; the workgroups of a job stride over its elements
+template <typename TI, typename TO>
+__global__ void k_convert_batch(ConvBatch<TI, TO> b) {
+  const int j = blockIdx.y;
+  const long cnt = b.count[j];
+  const TI* in = b.in[j];
+  TO* out = b.out[j];
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (long)gridDim.x * blockDim.x)
+    out[i] = (TO)in[i];
+}
+template <typename TI, typename TO>
+hipError_t convert_batch(const ConvBatch<TI, TO>& b, hipStream_t s) {
+  if (b.n < 1 || b.n > kConvJobs) return b.n == 0 ? hipSuccess : hipErrorInvalidValue;
+  long mx = 0;
+  for (int j = 0; j < b.n; ++j) mx = std::max(mx, b.count[j]);
+  if (mx <= 0) return hipSuccess;
+  const long blocks = std::min<long>((mx + 255) / 256, 2048);
+  hipLaunchKernelGGL((k_convert_batch<TI, TO>), dim3((unsigned)blocks, b.n), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+template hipError_t convert_batch<double, float>(const ConvBatch<double, float>&, hipStream_t);
+template hipError_t convert_batch<float, double>(const ConvBatch<float, double>&, hipStream_t);
+template hipError_t convert_batch<double, double>(const ConvBatch<double, double>&, hipStream_t);
+template hipError_t convert_batch<float, float>(const ConvBatch<float, float>&, hipStream_t);
+
 template <typename TI, typename TO>
 __global__ void k_copy2d(int rows, int cols, const TI* in, int ldin, TO* out, int ldout, double scale) {
   long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -2443,6 +2468,30 @@ hipError_t scale_cols_copy(const T* in, int rows, int cols, const double* w, T* 
 }
 template hipError_t scale_cols_copy<float>(const float*, int, int, const double*, float*, hipStream_t);
 template hipError_t scale_cols_copy<double>(const double*, int, int, const double*, double*, hipStream_t);
+
+template <typename T>
+__global__ void k_scale_cols_copy_batch(ScaleBatch<T> b) {
+  const int j = blockIdx.y;
+  const int rows = b.rows[j];
+  const long tot = (long)rows * b.cols[j];
+  const T* in = b.in[j];
+  T* out = b.out[j];
+  const double* w = b.w[j];
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x)
+    out[e] = (T)((double)in[e] * w[e / rows]);
+}
+template <typename T>
+hipError_t scale_cols_copy_batch(const ScaleBatch<T>& b, hipStream_t s) {
+  if (b.count <= 0 || b.count > 3) return b.count == 0 ? hipSuccess : hipErrorInvalidValue;
+  long mx = 0;
+  for (int j = 0; j < b.count; ++j) mx = std::max(mx, (long)b.rows[j] * b.cols[j]);
+  if (mx <= 0) return hipSuccess;
+  const long blocks = std::min<long>((mx + 255) / 256, 1024);
+  hipLaunchKernelGGL((k_scale_cols_copy_batch<T>), dim3((unsigned)blocks, b.count), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+template hipError_t scale_cols_copy_batch<float>(const ScaleBatch<float>&, hipStream_t);
+template hipError_t scale_cols_copy_batch<double>(const ScaleBatch<double>&, hipStream_t);
 
 __global__ void k_eig_inv_sqrt(const double* E, const double* w, int K, int q, double* W) {
   long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -2572,6 +2621,25 @@ hipError_t lambda_1d(int n, double* out, hipStream_t s, double power) {
   hipLaunchKernelGGL(k_lambda, dim3((n + 255) / 256), dim3(256), 0, s, n, power, out);
   return hipGetLastError();
 }
+__global__ void k_lambda_batch(LamBatch b) {
+  const int j = blockIdx.y, n = b.n[j];
+  const double power = b.power[j];
+  double* out = b.out[j];
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const double h = 1.0 / (double)(n + 1);
+    const double sv = sinpi(0.5 * (double)(k + 1) * h);
+    const double lam = 4.0 / (h * h) * sv * sv;
+    out[k] = power == 1.0 ? lam : pow(lam, power);
+  }
+}
+hipError_t lambda_batch(const LamBatch& b, hipStream_t s) {
+  if (b.count <= 0) return hipSuccess;
+  int mx = 0;
+  for (int j = 0; j < b.count; ++j) mx = std::max(mx, b.n[j]);
+  if (mx <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lambda_batch, dim3((unsigned)std::min(128, (mx + 255) / 256), b.count), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
 
 template <typename T>
 __global__ void k_expfactors(const double* lam, int n, const double* tau, int K, T* E, int ldE, int withLam) {
@@ -2591,6 +2659,30 @@ hipError_t expfactors(const double* lam, int n, const double* tau, int K, T* E, 
 }
 template hipError_t expfactors<double>(const double*, int, const double*, int, double*, int, int, hipStream_t);
 template hipError_t expfactors<float>(const double*, int, const double*, int, float*, int, int, hipStream_t);
+
+// blockIdx.y is the job; the workgroups of a job stride over its n x K elements
+template <typename T>
+__global__ void k_expfactors_batch(ExpBatch<T> b) {
+  const ExpJob<T>& J = b.j[blockIdx.y];
+  const long tot = (long)J.n * J.K;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(e % J.n), k = (int)(e / J.n);
+    const double v = exp(-J.tau[k] * J.lam[i]);
+    J.E[i + (long)J.ldE * k] = (T)(J.withLam ? J.lam[i] * v : v);
+  }
+}
+template <typename T>
+hipError_t expfactors_batch(const ExpBatch<T>& b, hipStream_t s) {
+  if (b.count <= 0) return hipSuccess;
+  long mx = 0;
+  for (int j = 0; j < b.count; ++j) mx = std::max(mx, (long)b.j[j].n * b.j[j].K);
+  if (mx <= 0) return hipSuccess;
+  const long blocks = std::min<long>((mx + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_expfactors_batch<T>, dim3((unsigned)blocks, b.count), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+template hipError_t expfactors_batch<double>(const ExpBatch<double>&, hipStream_t);
+template hipError_t expfactors_batch<float>(const ExpBatch<float>&, hipStream_t);
 
 // target function of the fits, in the scaled variable y = rho/rho0:
 //   kind 0: g(y) = c_neg rho^-(1+alpha) + c_pos rho^-(1-alpha), rho = rho0*y

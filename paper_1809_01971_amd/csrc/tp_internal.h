@@ -126,6 +126,20 @@ hipError_t psd_tri_batched(const JobBatch<PsdJob>& jobs, int count, int Kmax, hi
 // Elementwise helpers.
 template <typename TI, typename TO>
 hipError_t convert(const TI* in, TO* out, long count, hipStream_t s);
+// Up to kConvJobs conversions out[j][i] = (TO) in[j][i], i < count[j], in one launch; jobs with
+// count <= 0 are skipped.
+constexpr int kConvJobs = 4;
+template <typename TI, typename TO>
+struct ConvBatch {
+  const TI* in[kConvJobs];
+  TO* out[kConvJobs];
+  long count[kConvJobs];
+  int n = 0;
+  // the call sites add at most kConvJobs (a core and three factors, or three modes)
+  void add(const TI* i, TO* o, long c) { in[n] = i; out[n] = o; count[n] = c; ++n; }
+};
+template <typename TI, typename TO>
+hipError_t convert_batch(const ConvBatch<TI, TO>& b, hipStream_t s);
 // Copy a rows x cols column-major block (lds in/out) with scale.
 template <typename TI, typename TO>
 hipError_t copy2d(int rows, int cols, const TI* in, int ldin, TO* out, int ldout, double scale, hipStream_t s);
@@ -137,6 +151,17 @@ hipError_t scale_cols_d(double* a, int rows, int cols, int ld, const double* sca
 // out[:, j] = in[:, j] * w[j] (rows x cols, both with leading dimension rows), the product in FP64
 template <typename T>
 hipError_t scale_cols_copy(const T* in, int rows, int cols, const double* w, T* out, hipStream_t s);
+// scale_cols_copy of up to 3 matrices (the modes of a symbol) in one launch.
+template <typename T>
+struct ScaleBatch {
+  const T* in[3];
+  T* out[3];
+  int rows[3], cols[3];
+  const double* w[3];
+  int count = 0;
+};
+template <typename T>
+hipError_t scale_cols_copy_batch(const ScaleBatch<T>& b, hipStream_t s);
 // W = E[:, 0:q] * diag(1/sqrt(w)) for the leading q eigenpairs; K rows, ld K.
 hipError_t eig_inv_sqrt(const double* E, const double* w, int K, int q, double* W, hipStream_t s);
 // out[0] = sum(a[i]*b[i]) in FP64; part: device scratch of 256 doubles for per-workgroup sums.
@@ -159,6 +184,36 @@ hipError_t lambda_1d(int n, double* out, hipStream_t s, double power = 1.0);
 // E[:,k] = exp(-tau_k lam), times lam when withLam (the Lemma 4.1 factor).
 template <typename T>
 hipError_t expfactors(const double* lam, int n, const double* tau, int K, T* E, int ldE, int withLam, hipStream_t s);
+// Several of the above in one launch (the factors of a symbol's modes and blocks).
+constexpr int kExpJobs = 12;
+template <typename T>
+struct ExpJob { const double* lam; const double* tau; T* E; int n, K, ldE, withLam; };
+template <typename T>
+struct ExpBatch {
+  ExpJob<T> j[kExpJobs];
+  int count = 0;
+  bool add(const double* lam, int n, const double* tau, int K, T* E, int ldE, int withLam) {
+    if (count >= kExpJobs) return false;
+    j[count++] = ExpJob<T>{lam, tau, E, n, K, ldE, withLam};
+    return true;
+  }
+};
+template <typename T>
+hipError_t expfactors_batch(const ExpBatch<T>& b, hipStream_t s);
+// 1D spectra of several grids (lambda_1d each) in one launch.
+constexpr int kLamJobs = 6;
+struct LamBatch {
+  double* out[kLamJobs];
+  int n[kLamJobs];
+  double power[kLamJobs];
+  int count = 0;
+  bool add(int nn, double* o, double p) {
+    if (count >= kLamJobs) return false;
+    out[count] = o; n[count] = nn; power[count] = p; ++count;
+    return true;
+  }
+};
+hipError_t lambda_batch(const LamBatch& b, hipStream_t s);
 // The function a least-squares exponential sum approximates, in rho = rho0 y:
 //   kind 0 (operator, Lemma 4.1): g = (cn rho^-alpha + [fitpos] cp rho^beta) / rho, the part of
 //          s = c0 + cn rho^-alpha + cp rho^beta that is fitted (c0 and a beta = 1 term are exact);
