@@ -1303,45 +1303,57 @@ tp_status inner_sym_impl(tp_ctx* c, const tp_tensor* x, const tp_symbol* S, cons
   }
   TPCHK(run_group(c, gs, d));
   size_t cx = (size_t)rx[0] * rx[1] * rx[2], cy = (size_t)ry[0] * ry[1] * ry[2];
-  double *Cx, *Cy, *Z, *res;
+  double *Cx, *Z, *res;
   TPCHK(wsalloc(c, cx, &Cx));
-  TPCHK(wsalloc(c, cy, &Cy));
   TPCHK(wsalloc(c, cx, &Z));
   TPCHK(wsalloc(c, 257, &res));  // result + per-workgroup partial sums
+  // the core contractions in the tensors' precision T (FP32: the matrix cores, the last one with its
+  // long contraction over ry2 R summed in FP64 chunks); the G's are rounded to T for them
+  const T* Cy = (const T*)y->core;
+  T* Gt[3];
   {
     ConvBatch<T, double> cb;
     cb.add((const T*)x->core, Cx, (long)cx);
-    cb.add((const T*)y->core, Cy, (long)cy);
     HIPCHK(convert_batch(cb, c->stream));
+    if (std::is_same<T, double>::value) {
+      for (int m = 0; m < d; ++m) Gt[m] = (T*)G[m];
+    } else {
+      ConvBatch<double, T> cg;
+      for (int m = 0; m < d; ++m) {
+        TPCHK(wsalloc(c, (size_t)rx[m] * ry[m] * R, &Gt[m]));
+        cg.add(G[m], Gt[m], (long)rx[m] * ry[m] * R);
+      }
+      HIPCHK(convert_batch(cg, c->stream));
+    }
   }
   // Z = sum_k Cy x_1 G1_k x_2 G2_k x_3 G3_k  (rx1 x rx2 x rx3)
   if (d == 3) {
-    double *D, *E;
+    T *D, *E;
     TPCHK(wsalloc(c, (size_t)R * rx[0] * ry[1] * ry[2], &D));
     TPCHK(wsalloc(c, (size_t)R * ry[2] * rx[0] * rx[1], &E));
-    GemmArgs<double, double, double, double> g1;
+    GemmArgs<T, T, T, T> g1;
     g1.M = rx[0]; g1.N = ry[1] * ry[2]; g1.K = ry[0]; g1.batch = R;
-    g1.A = G[0]; g1.lda = rx[0]; g1.sA = (long)rx[0] * ry[0];
+    g1.A = Gt[0]; g1.lda = rx[0]; g1.sA = (long)rx[0] * ry[0];
     g1.B = Cy; g1.ldb = ry[0]; g1.sB = 0;
     g1.C = D; g1.ldc = rx[0]; g1.sC = (long)rx[0] * ry[1] * ry[2];
     TPCHK(run(c, g1));
-    GemmArgs<double, double, double, double> g2;
+    GemmArgs<T, T, T, T> g2;
     g2.M = rx[0]; g2.N = rx[1]; g2.K = ry[1]; g2.batch = R * ry[2];
     g2.A = D; g2.lda = rx[0]; g2.sA = (long)rx[0] * ry[1];
-    g2.B = G[1]; g2.ldb = rx[1]; g2.tB = true; g2.sB = (long)rx[1] * ry[1]; g2.divB = ry[2];
+    g2.B = Gt[1]; g2.ldb = rx[1]; g2.tB = true; g2.sB = (long)rx[1] * ry[1]; g2.divB = ry[2];
     g2.C = E; g2.ldc = rx[0]; g2.sC = (long)rx[0] * rx[1];
     TPCHK(run(c, g2));
-    TPCHK((mm<double, double, double, double>(c, false, true, rx[0] * rx[1], rx[2], ry[2] * R, 1.0, E, rx[0] * rx[1], G[2], rx[2], 0.0, Z, rx[0] * rx[1])));
+    TPCHK((mm<T, T, double, T>(c, false, true, rx[0] * rx[1], rx[2], ry[2] * R, 1.0, E, rx[0] * rx[1], Gt[2], rx[2], 0.0, Z, rx[0] * rx[1])));
   } else {
-    double* D;
+    T* D;
     TPCHK(wsalloc(c, (size_t)R * rx[0] * ry[1], &D));
-    GemmArgs<double, double, double, double> g1;
+    GemmArgs<T, T, T, T> g1;
     g1.M = rx[0]; g1.N = ry[1]; g1.K = ry[0]; g1.batch = R;
-    g1.A = G[0]; g1.lda = rx[0]; g1.sA = (long)rx[0] * ry[0];
+    g1.A = Gt[0]; g1.lda = rx[0]; g1.sA = (long)rx[0] * ry[0];
     g1.B = Cy; g1.ldb = ry[0]; g1.sB = 0;
     g1.C = D; g1.ldc = rx[0]; g1.sC = (long)rx[0] * ry[1];
     TPCHK(run(c, g1));
-    TPCHK((mm<double, double, double, double>(c, false, true, rx[0], rx[1], ry[1] * R, 1.0, D, rx[0], G[1], rx[1], 0.0, Z, rx[0])));
+    TPCHK((mm<T, T, double, T>(c, false, true, rx[0], rx[1], ry[1] * R, 1.0, D, rx[0], Gt[1], rx[1], 0.0, Z, rx[0])));
   }
   // the sum lands in mapped host memory: no copy command, only the synchronisation
   HIPCHK(dot<double>(Cx, Z, (long)cx, c->dmap, res + 1, c->stream));
