@@ -1995,6 +1995,11 @@ __device__ __forceinline__ void sturm2(const double* D, const double* DL2, int K
 // Point k (0..TRI_SEC) of the multisection of [a, b] into TRI_SEC parts: geometric while
 // b > 2a > 0, else equidistant.
 constexpr int TRI_SEC = 9;
+// The geometric grid of the initial Sturm counts over [2^-60 T0, T0].
+constexpr int TRI_GRID = 512;
+__device__ __forceinline__ double tri_grid(double T0, int t) {
+  return T0 * exp2(60.0 * ((double)t / (double)(TRI_GRID - 1) - 1.0));
+}
 __device__ __forceinline__ double tri_split(double a, double b, int k) {
   if (k <= 0) return a;
   if (k >= TRI_SEC) return b;
@@ -2191,16 +2196,41 @@ __global__ __launch_bounds__(TRI_NT) void k_psd_tri(JobBatch<PsdJob> jobs) {
     }
     return;
   }
-  // ---- 3. eigenvalues of T + sigma I by multisection (eigenvalue tid / 4, ascending): the four
-  // lanes of a quad count at the 8 interior points of TRI_SEC subintervals
+  // ---- 3. eigenvalues of T + sigma I by multisection (eigenvalue tid / 4, ascending).  First the
+  // Sturm counts at TRI_GRID geometric points x_t = ||T|| 2^(60 (t / (TRI_GRID - 1) - 1)), two per
+  // thread of the first half; each eigenvalue i then starts from the bracket [x_lo, x_hi) with
+  // count(x_lo) <= i < count(x_hi), hi = lo + 1 (a ratio of 2^(60 / 511), about 1.085), found by
+  // bisection over t, and the four lanes of a quad count at the 8 interior points of TRI_SEC
+  // subintervals of it.
+  const double T0 = tn + sigma;
+  int* cnt = reinterpret_cast<int*>(pw);  // free after the reduction: TRI_GRID counts
+  if (tid < TRI_GRID / 2) {
+    int c0, c1;
+    sturm2(D, DL2, K, tri_grid(T0, 2 * tid), tri_grid(T0, 2 * tid + 1), c0, c1);
+    cnt[2 * tid] = c0;
+    cnt[2 * tid + 1] = c1;
+  }
+  __syncthreads();
   {
     const int i = tid >> 2, qd = tid & 3;
-    double a = (tn + sigma) * 0x1p-60, b = tn + sigma;
+    double a = 0.0, b = 0.0;
     bool done = i >= K;   // the second half of the workgroup has no eigenvalue
     if (!done) {
-      int c0, c1;
-      sturm2(D, DL2, K, a, a, c0, c1);
-      if (c0 > i) { b = a; a = 0.0; done = true; }   // below 2^-60 ||T||: zero for every use here
+      if (cnt[0] > i) {
+        b = tri_grid(T0, 0);  // below 2^-60 ||T||: zero for every use here
+        done = true;
+      } else if (cnt[TRI_GRID - 1] <= i) {
+        a = tri_grid(T0, TRI_GRID - 1);
+        b = 2.0 * T0;
+      } else {
+        int lo = 0, hi = TRI_GRID - 1;  // cnt[lo] <= i < cnt[hi]
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (cnt[mid] > i) hi = mid; else lo = mid;
+        }
+        a = tri_grid(T0, lo);
+        b = tri_grid(T0, hi);
+      }
     }
     int iters = 0;
     while (!done) {
