@@ -135,8 +135,12 @@ struct ConvBatch {
   TO* out[kConvJobs];
   long count[kConvJobs];
   int n = 0;
-  // the call sites add at most kConvJobs (a core and three factors, or three modes)
-  void add(const TI* i, TO* o, long c) { in[n] = i; out[n] = o; count[n] = c; ++n; }
+  // the call sites add at most kConvJobs (a core and three factors, or three modes); one more
+  // marks the batch invalid, and convert_batch then fails instead of writing past the table
+  void add(const TI* i, TO* o, long c) {
+    if (n >= kConvJobs) { n = kConvJobs + 1; return; }
+    in[n] = i; out[n] = o; count[n] = c; ++n;
+  }
 };
 template <typename TI, typename TO>
 hipError_t convert_batch(const ConvBatch<TI, TO>& b, hipStream_t s);
