@@ -164,9 +164,9 @@ __device__ __forceinline__ d4_t mfma16(double a, double b, d4_t c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// One stage of the MFMA kernel covers MBK contraction indices; each thread loads 8 elements of
-// the A tile and 8 of the B tile per stage.
-constexpr int MBK = 32;
+// One stage of the MFMA kernel covers MBK contraction indices; each thread loads MNE elements of
+// the A tile and MNE of the B tile per stage.
+constexpr int MBK = 16;
 constexpr int MNE = MBK / 4;  // elements of each operand per thread per stage
 
 // How an operand's tile elements are read: column-major, transposed, or face-split.
@@ -186,7 +186,7 @@ struct OpRegs {
 
 // Element i of the thread's share: A tiles are M x K, B tiles K x N.  For a column-major A tile
 // (or a face-split one) lane groups run along M; for a transposed one along K; B the other way.
-// Along M (or N) a thread takes the 8 consecutive contraction indices of its wave's quarter of the
+// Along M (or N) a thread takes the MNE consecutive contraction indices of its wave's quarter of the
 // stage for one row, which it stores to LDS as one contiguous run.
 template <bool IS_A, int KIND>
 __device__ __forceinline__ void tile_pos(int tid, int i, int& outer, int& kk) {
@@ -338,9 +338,9 @@ __global__ __launch_bounds__(GTHREADS) void k_gemm_mfma(GemmGroup<TA, TB, TC, Ta
     // the blocks are formed transposed, D = (A B)^T = B^T A^T (B's values in the first operand):
     // a lane's results then lie along a column of C, so each store instruction writes runs of
     // 16 consecutive rows (64 or 128 contiguous bytes) instead of 16 different columns.  Lane
-    // group g = lane / 16 supplies the contraction indices 8 g .. 8 g + 7 of the stage (the
-    // instruction's k slot s of step t is index 8 g + t for both operands, so the products are
-    // the same), read as 16-byte runs
+    // group g = lane / 16 supplies the contraction indices MNE g .. MNE g + MNE - 1 of the stage
+    // (the instruction's k slot g of step t is index MNE g + t for both operands, so the products
+    // are the same), read as 16-byte runs
     {
       const int c16 = lane & 15, kq = MNE * (lane >> 4);
       Tacc a0[MNE], a1[MNE], b0[MNE], b1[MNE];
