@@ -155,6 +155,31 @@ def test_cfg3_n2047_global_error(ctx, prec):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+def test_cfg3_n2047_printed_recursion(ctx, prec):
+    """Algorithm alg:pcg as printed, on the benchmark workload: the recursive residual
+    R = trunc(R - a trunc(fun(P))) and the stop on ||R|| / ||B|| <= tau; the error against the exact
+    control by Parseval over every 8th spectral slab of the 2047^3 grid."""
+    import paper_1809_01971_amd as tp
+    from paper_1809_01971_amd._tp import TP_STOP_RESIDUAL, sketch_tensors
+    p = workloads.cfg3()
+    log("cfg3 printed recursion prec=%d" % prec)
+    if prec == 1:
+        eps, tau, cap, q, K, tol = 3e-5, 1e-4, 56, 64, 28, MIXED_TOL
+    else:
+        eps, tau, cap, q, K, tol = 1.5e-7, 1e-6, 96, 112, 36, FP64_TOL
+    op, pre, errs = ctx.symbol_build(3, p.n, p.alpha, p.c_neg, p.c_pos, prec=prec, op_terms=K, pre_terms=K)
+    sk = sketch_tensors(workloads.sketch_matrices(p.n, 3, q))
+    X = tp.Tensor(3, p.n, cap, prec)
+    st, info = ctx.pcg_solve(op, pre, p.weights, p.factors, X, tau=tau, kmax=100, trunc_tol=eps, cap=cap,
+                             sketch=sk, stop_rule=TP_STOP_RESIDUAL, recursive_residual=True)
+    core, fs = X.numpy_parts()
+    err = global_rel_error(p, core, fs, stride=8)
+    log("  err %.2e info %s" % (err, info))
+    assert info["status"] in (0, 4)
+    assert err < tol
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 def test_state_recovery_and_cost(ctx, prec):
     """y = beta A^-alpha u (eqn:State) and J(y,u) = 1/2||y - y_Omega||^2 + gamma/2 ||u||^2 from the
     GPU control, against the exact state and cost of the exact control."""
