@@ -299,7 +299,7 @@ def main():
                    "ms_per_call": 1000.0 * dtb / args.batch_steps,
                    "iters": sorted({r["iters"] for r in res}), "statuses": sorted({r["status"] for r in res}),
                    "rel_diff_first_vs_single": float(np.linalg.norm(a - b) / np.linalg.norm(b)),
-                   "note": "16 independent n=2047 control problems (rhs seeds 2-17) per call, concurrent"}
+                   "note": "16 independent n=2047 control problems (rhs seeds 2-17) per call, concurrent; one operator, so the 16 share one symbol build"}
         del outs
 
     sweep = None

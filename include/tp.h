@@ -331,8 +331,10 @@ tp_status tp_workspace_peak(tp_ctx* ctx, int32_t reset, size_t* peak);
  * own workspace of workspace_per_stream bytes (0 = 2 GiB).  The worker streams and workspaces are
  * created on first use and kept in ctx for later calls (more are added when a call asks for more
  * streams; all are replaced when the workspace size changes; tp_destroy releases them).  A
- * worker's symbols are built in its workspace, so a call allocates no device memory per problem.  Returns the first hard error (TP_ERANK / TP_ENOCONV of a problem are reported only
- * in its info). */
+ * worker's symbols are built in its workspace, so a call allocates no device memory per problem.
+ * Problems whose descriptors are equal field by field (several right-hand sides of one operator)
+ * share one build of the symbols, made on ctx before the workers start.  Returns the first hard
+ * error (TP_ERANK / TP_ENOCONV of a problem are reported only in its info). */
 tp_status tp_pcg_solve_batched(tp_ctx* ctx, int32_t count, const tp_symbol_desc* descs,
                                const tp_cp* bs, tp_tensor* xs, const tp_pcg_opts* opts,
                                const tp_sketch* sks, tp_pcg_info* infos, int32_t streams,

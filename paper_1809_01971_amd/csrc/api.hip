@@ -2876,9 +2876,23 @@ extern "C" tp_status tp_workspace_query(const tp_symbol_desc* D, const tp_pcg_op
 }
 
 // ------------------------------------------------------------------------------ batched solves
+// The symbols are a function of the descriptor alone: descriptors equal field by field build the
+// same symbols.
+static bool same_desc(const tp_symbol_desc& a, const tp_symbol_desc& b) {
+  if (a.d != b.d) return false;
+  for (int m = 0; m < a.d && m < 3; ++m)
+    if (a.n[m] != b.n[m]) return false;
+  return a.alpha == b.alpha && a.c_neg == b.c_neg && a.c_pos == b.c_pos && a.method == b.method &&
+         a.op_terms == b.op_terms && a.pre_terms == b.pre_terms && a.sinc_kl == b.sinc_kl &&
+         a.sinc_kr == b.sinc_kr && a.sinc_h == b.sinc_h && a.prec == b.prec && a.c0 == b.c0 && a.beta == b.beta &&
+         a.pre_rank == b.pre_rank && a.directional == b.directional;
+}
+
 // Independent problems run concurrently on `streams` HIP streams (default priority), each
 // stream owned by a worker thread with its own context and workspace; workers take the next
-// problem from a shared counter, so uneven problems balance themselves.
+// problem from a shared counter, so uneven problems balance themselves.  Problems that share a
+// descriptor (several right-hand sides of one operator) share one build of its symbols: it runs on
+// the calling context before the workers start, and the workers only read the symbols.
 extern "C" tp_status tp_pcg_solve_batched(tp_ctx* c, int32_t count, const tp_symbol_desc* descs, const tp_cp* bs,
                                           tp_tensor* xs, const tp_pcg_opts* opts, const tp_sketch* sks,
                                           tp_pcg_info* infos, int32_t streams, size_t workspace_per_stream) {
@@ -2910,6 +2924,30 @@ extern "C" tp_status tp_pcg_solve_batched(tp_ctx* c, int32_t count, const tp_sym
     c->worker_streams.push_back(sw);
   }
   const std::vector<tp_ctx*>& ctxs = c->workers;
+  // descriptors of two or more problems: symbols built once here (freed after the workers end)
+  struct Shared { tp_symbol* op = nullptr; tp_symbol* pre = nullptr; tp_status st = TP_OK; std::string msg; };
+  std::vector<int> group(count, -1);
+  std::vector<Shared> shared;
+  for (int i = 0; i < count; ++i) {
+    if (group[i] >= 0) continue;
+    bool more = false;
+    for (int j = i + 1; j < count && !more; ++j) more = same_desc(descs[i], descs[j]);
+    if (!more) continue;
+    const int g = (int)shared.size();
+    for (int j = i; j < count; ++j)
+      if (group[j] < 0 && same_desc(descs[i], descs[j])) group[j] = g;
+    Shared sh;
+    double errs[2];
+    sh.st = tp_symbol_build(c, &descs[i], &sh.op, &sh.pre, errs);
+    if (sh.st != TP_OK) sh.msg = g_err;  // the error text is per thread
+    shared.push_back(sh);
+  }
+  auto free_shared = [&]() {
+    for (Shared& sh : shared) {
+      if (sh.op) tp_symbol_free(sh.op);
+      if (sh.pre) tp_symbol_free(sh.pre);
+    }
+  };
   std::atomic<int> next(0);
   std::vector<tp_status> wst(nw, TP_OK);
   std::vector<std::string> werr(nw);
@@ -2922,7 +2960,15 @@ extern "C" tp_status tp_pcg_solve_batched(tp_ctx* c, int32_t count, const tp_sym
       tp_symbol *op = nullptr, *pre = nullptr;
       double errs[2];
       const size_t mark = cw->ws_top;  // the symbols go to the workspace below the solve's scopes
-      tp_status st = tp_symbol_build(cw, &descs[i], &op, &pre, errs);
+      const bool own = group[i] < 0;
+      tp_status st;
+      if (own) {
+        st = tp_symbol_build(cw, &descs[i], &op, &pre, errs);
+      } else {
+        op = shared[group[i]].op;
+        pre = shared[group[i]].pre;
+        st = shared[group[i]].st;
+      }
       const bool indefinite = st == TP_EINDEF;  // symbols returned; the solve may break down
       if (st == TP_OK || indefinite) {
         st = tp_pcg_solve(cw, op, pre, &bs[i], &xs[i], &opts[i], &sks[i], &infos[i]);
@@ -2930,19 +2976,20 @@ extern "C" tp_status tp_pcg_solve_batched(tp_ctx* c, int32_t count, const tp_sym
       } else {
         infos[i].status = st;
       }
-      if (op) tp_symbol_free(op);
-      if (pre) tp_symbol_free(pre);
+      if (own && op) tp_symbol_free(op);
+      if (own && pre) tp_symbol_free(pre);
       (void)hipStreamSynchronize(cw->stream);  // the next problem reuses the symbols' workspace
       cw->ws_top = mark;
       if (st != TP_OK && st != TP_ERANK && st != TP_ENOCONV && st != TP_EINDEF && wst[w] == TP_OK) {
         wst[w] = st;
-        werr[w] = g_err;
+        werr[w] = (!own && !op) ? shared[group[i]].msg : g_err;
       }
     }
   };
   std::vector<std::thread> th;
   for (int w = 0; w < nw; ++w) th.emplace_back(worker, w);
   for (auto& t : th) t.join();
+  free_shared();
   tp_status res = TP_OK;
   std::string msg;
   for (int w = 0; w < nw; ++w)
