@@ -299,3 +299,27 @@ def test_device_resident_rhs_matches_host_arrays(ctx):
         core, fac = outs[0].numpy_parts()
         full.append(tensor.tucker_full(core, fac))
     assert np.array_equal(full[0], full[1])
+
+
+def test_batch_problems_sharing_a_descriptor(ctx):
+    """Problems of a batch with equal descriptors share one symbol build: every result equals the
+    single solve of the same problem bitwise, next to a problem with another descriptor."""
+    import dataclasses
+    import paper_1809_01971_amd as tp
+    from paper_1809_01971_amd._tp import batch_solve, sketch_tensors
+    n = 63
+    probs = []
+    for seed, alpha in ((3, 0.5), (4, 0.5), (5, 0.3), (6, 0.5)):
+        p = workloads.cfg3(seed=seed)
+        probs.append(dataclasses.replace(p, n=n, alpha=alpha, factors=[f[:n] for f in p.factors]))
+    s = dict(prec=1, eps=3e-5, tau=1e-4, cap=32, q=40, op_terms=28, pre_terms=28)
+    sk = {(n, 40): sketch_tensors(workloads.sketch_matrices(n, 3, 40))}
+    outs, res = batch_solve(ctx, probs, lambda _: s, sk, streams=2, workspace_per_stream=1 << 30)
+    for p, X in zip(probs, outs):
+        op, pre, _ = ctx.symbol_build(3, n, p.alpha, p.c_neg, p.c_pos, prec=1, op_terms=28, pre_terms=28)
+        Y = tp.Tensor(3, n, 32, 1)
+        ctx.pcg_solve(op, pre, p.weights, p.factors, Y, tau=1e-4, kmax=100, trunc_tol=3e-5, cap=32,
+                      sketch=sk[(n, 40)])
+        a = tensor.tucker_full(*X.numpy_parts())
+        b = tensor.tucker_full(*Y.numpy_parts())
+        assert np.array_equal(a, b)
