@@ -42,11 +42,11 @@ ERR_SLAB_STRIDE = 4   # exact error over every 4th first-index spectral slab (un
 # by the reading of a 256 MiB device copy; valid only for the sources and mixed settings they were
 # taken with, identified by traffic_key() (SHA-256 prefix of csrc/kernels.hip, csrc/api.hip and the
 # settings' JSON); null otherwise.
-TRAFFIC = {"src": "edf5f7feb4e3feb4",
-           "bytes_per_launch": {"gemm_f32": 27929369, "gemm_f32_split64": 35172112, "gemm_f64": 3407236,
-                                "gemm_f32_f64": 3851284, "gemm_f64_f32": 3269732, "gemm_reduce": 6569290,
+TRAFFIC = {"src": "1c443998944f7766",
+           "bytes_per_launch": {"gemm_f32": 27928852, "gemm_f32_split64": 35169466, "gemm_f64": 3407235,
+                                "gemm_f32_f64": 3851283, "gemm_f64_f32": 3269731, "gemm_reduce": 6569288,
                                 "psd_tri": 380635, "psd_eig": 447074, "chol": 434150, "ns_isqrt": 189393,
-                                "dst_f32": 3054804}}
+                                "dst_f32": 3054798}}
 
 # kernel classes of tp_profile_read: the kernel, its bound and the peak it is priced against (the
 # contractions run on the FP32 / FP64 matrix cores, whose dense peaks on MI355X equal the vector
