@@ -197,7 +197,7 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--sinc-steps", type=int, default=None,
                     help="timed steps of each sinc-symbol leg (default: --steps // 2; 0 skips them)")
-    ap.add_argument("--batch-steps", type=int, default=2,
+    ap.add_argument("--batch-steps", type=int, default=8,
                     help="timed calls of the concurrent leg: 16 independent problems of the workload's "
                          "shape on 8 streams per call (0 skips it)")
     ap.add_argument("--spectral-steps", type=int, default=None,
