@@ -1,6 +1,7 @@
-"""Host-side behaviour of the C ABI that needs no device: argument checks of every entry point and
-the workspace estimate (tp_workspace_query takes no context).  Each call here returns before any
-HIP call is made, so the tests run on a machine without a GPU."""
+"""Host-side behaviour of the C ABI that needs no device: argument checks of every entry point, the
+workspace estimate (tp_workspace_query takes no context), and the absence of any host fallback in
+the package.  Each library call here returns before any HIP call is made, so the tests run on a
+machine without a GPU."""
 import ctypes as C
 import os
 
@@ -144,3 +145,28 @@ def test_batched_solve_argument_ranges():
     for streams in (0, 17):
         assert lib.tp_pcg_solve_batched(fake, 1, *args, streams, 0) == _tp.TP_EINVAL
         assert "streams" in _err()
+
+
+def test_missing_library_raises_instead_of_falling_back(monkeypatch, tmp_path):
+    """With no built library the binding raises at load time: nothing in the package computes on
+    the host in its place."""
+    monkeypatch.setattr(_tp, "_LIB", None)
+    monkeypatch.setattr(_tp, "library_path", lambda: str(tmp_path / "libtp.so"))
+    with pytest.raises(OSError, match="not built"):
+        _tp.load_library()
+
+
+def test_package_sources_do_not_reach_the_oracle():
+    """The product package (binding and HIP sources) names no module of the oracle: the oracle is
+    test infrastructure only."""
+    import re
+    pkg = os.path.dirname(_tp.__file__)
+    hits = []
+    for root, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                src = open(os.path.join(root, f), errors="replace").read()
+                if re.search(r"^\s*(from|import)\s+oracle\b|\boracle\.(exact|tensor|spectral|sinc|expfit|lowrank_pcg)\b",
+                             src, flags=re.M):
+                    hits.append(f)
+    assert hits == []
