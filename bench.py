@@ -3,7 +3,8 @@
 One step = one complete control solve (operator and preconditioner symbols built on the GPU, then
 the low-rank PCG to its stopping rule; result left in device memory) in mixed precision.  Beside it:
 the same solve in FP64, both with the paper's sinc-quadrature operator symbol, the spectral-domain
-variant, concurrent independent solves, and the per-solve time over grid sizes n = 1023..32767.  The
+variant, the mixed solve with split-BF16 products in its FP32 contractions, concurrent independent
+solves, and the per-solve time over grid sizes n = 1023..32767.  The
 results are compared with the exact control by Parseval's identity over sampled first-index spectral
 slabs of the 2047^3 grid (oracle O1), and that oracle is timed on the host cores as the CPU baseline.
 The timed steps run without per-launch events; a second pass of the same steps records HIP events
@@ -42,11 +43,11 @@ ERR_SLAB_STRIDE = 4   # exact error over every 4th first-index spectral slab (un
 # by the reading of a 256 MiB device copy; valid only for the sources and mixed settings they were
 # taken with, identified by traffic_key() (SHA-256 prefix of csrc/kernels.hip, csrc/api.hip and the
 # settings' JSON); null otherwise.
-TRAFFIC = {"src": "1c443998944f7766",
-           "bytes_per_launch": {"gemm_f32": 27928852, "gemm_f32_split64": 35169466, "gemm_f64": 3407235,
-                                "gemm_f32_f64": 3851283, "gemm_f64_f32": 3269731, "gemm_reduce": 6569288,
-                                "psd_tri": 380635, "psd_eig": 447074, "chol": 434150, "ns_isqrt": 189393,
-                                "dst_f32": 3054798}}
+TRAFFIC = {"src": "1e99d8c205d3d822",
+           "bytes_per_launch": {"gemm_f32": 27932824, "gemm_f32_split64": 35192331, "gemm_f64": 3408414,
+                                "gemm_f32_f64": 3839517, "gemm_f64_f32": 3269687, "gemm_reduce": 6569913,
+                                "psd_tri": 378717, "psd_eig": 444146, "chol": 436723, "ns_isqrt": 189394,
+                                "dst_f32": 3054783}}
 
 # kernel classes of tp_profile_read: the kernel, its bound and the peak it is priced against (the
 # contractions run on the FP32 / FP64 matrix cores, whose dense peaks on MI355X equal the vector
@@ -202,6 +203,8 @@ def main():
                          "shape on 8 streams per call (0 skips it)")
     ap.add_argument("--spectral-steps", type=int, default=None,
                     help="timed steps of the spectral-domain variant (default: --steps; 0 skips it)")
+    ap.add_argument("--split-steps", type=int, default=None,
+                    help="timed steps of the split-BF16 variant of the mixed solve (default: --steps; 0 skips it)")
     ap.add_argument("--no-sweep", action="store_true", help="skip the grid-size sweep n = 1023..32767")
     ap.add_argument("--cpu-workers", type=int, default=None,
                     help="host processes of the oracle (default: the usable CPUs, at most 16)")
@@ -272,6 +275,28 @@ def main():
                     "iters": infs[-1]["iters"], "ranks": infs[-1]["rank"],
                     "rel_diff_vs_stated_path": float(np.linalg.norm(a - b) / np.linalg.norm(b)),
                     "note": "outside the paper: PCG in DST coordinates, same settings"}
+
+    bsteps = args.split_steps if args.split_steps is not None else args.steps
+    split, split_parts = None, None
+    if bsteps > 0:
+        # the same mixed solve with split-BF16 products (hi hi' + hi lo' + lo hi' on the BF16 matrix
+        # cores, FP32 accumulation) in its FP32 contractions: tp_gemm_mode(2); its FP32 contraction
+        # class timed in a profiled pass as in the headline
+        log("bench: mixed split-BF16 steps=%d (+ profiled pass)" % bsteps)
+        try:
+            ctx.gemm_mode(2)
+            Xb, dtbs, infb, _ = run_solver(ctx, p, sk_by_q, SETTINGS["mixed"], bsteps, 1, False)
+            _, _, _, prof_b = run_solver(ctx, p, sk_by_q, SETTINGS["mixed"], bsteps, 0, True)
+        finally:
+            ctx.gemm_mode(1)
+        split_parts = Xb.numpy_parts()
+        cb = kernel_classes(prof_b, bsteps)["gemm_f32"]
+        split = {"solves_per_s": bsteps / dtbs, "ms_per_step": 1000.0 * dtbs / bsteps,
+                 "iters": infb[-1]["iters"], "ranks": infb[-1]["rank"], "status": infb[-1]["status"],
+                 "gemm_f32_launches_per_step": cb["launches_per_step"], "gemm_f32_avg_launch_us": cb["avg_launch_us"],
+                 "gemm_f32_tflops": cb["achieved"],
+                 "note": "tp_gemm_mode(2): the FP32 contractions with FP32 results take split-BF16 products "
+                         "accumulated in FP32; gemm_f32_tflops counts the FP32 product's 2 M N K flops"}
 
     batched = None
     if args.batch_steps > 0:
@@ -359,6 +384,9 @@ def main():
         errs = oracle_errors(p, [parts_m], sample, workers)
         tc = time.perf_counter() - t0
         errs += oracle_errors(p, [parts_d], sample, workers) if parts_d else [None]
+        if split_parts:
+            split["rel_err_vs_oracle"] = oracle_errors(p, [split_parts], sample, workers)[0]
+            split["rel_err_note"] = "Parseval over every %dth spectral slab, as the headline" % ERR_SLAB_STRIDE
         if sinc_parts:
             sub = list(range(0, p.n, 4 * ERR_SLAB_STRIDE))
             names = sorted(sinc_parts)
@@ -392,6 +420,7 @@ def main():
         "symbol_err_mixed": infm[-1]["sym_err"][0], "precond_err": infm[-1]["sym_err"][1],
         "sinc_symbol": sinc or None,
         "spectral_domain_mixed": spectral,
+        "split_bf16_mixed": split,
         "batched_mixed": batched,
         "grid_sweep_mixed": sweep,
         "roofline": roofline, "kernel_classes_mixed": classes, "kernel_classes_fp64": classes_d,

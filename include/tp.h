@@ -395,8 +395,17 @@ typedef enum {
                                     inner products of the mixed path) */
 } tp_prof_class;
 
-/* Contraction kernels: mfma != 0 (default) uses the FP32/FP64 matrix-core tiles, 0 the FMA
- * tiles.  Process-wide; both give the same results up to rounding order. */
+/* Contraction kernels, process-wide (set it while no call of the library runs):
+ *   mfma = 1 (default): FP32 / FP64 matrix-core tiles;
+ *   mfma = 0: FMA tiles (the same results up to rounding order);
+ *   mfma = 2: as 1, but the contractions with FP32 operands, FP32 accumulation and FP32 results
+ *     (the sketch, projection and core contractions of the mixed path's products and truncations)
+ *     take split-BF16 products on the BF16 matrix cores, accumulated in FP32: each operand
+ *     x = hi + lo with hi = bf16(x), lo = bf16(x - hi), and a product is hi hi' + hi lo' + lo hi'
+ *     (relative error about 2^-16 per product instead of the FP32 product's 2^-24).  The FP32
+ *     contractions that sum into FP64 (inner products, the sketches' FP64 chunk sums) and all FP64
+ *     contractions are unchanged.
+ * Returns TP_EINVAL for any other value (the mode is then unchanged). */
 tp_status tp_gemm_mode(int32_t mfma);
 
 /* enable != 0: record a HIP event pair around every launch of the classes above on the

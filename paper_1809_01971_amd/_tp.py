@@ -208,7 +208,9 @@ class Context:
 
     # ---- measurement
     def gemm_mode(self, mfma=True):
-        _check(self.lib.tp_gemm_mode(1 if mfma else 0))
+        """tp_gemm_mode: True / 1 matrix cores (default), False / 0 FMA tiles, 2 split-BF16 products
+        for the FP32 contractions."""
+        _check(self.lib.tp_gemm_mode(int(mfma)))
 
     def profile(self, enable=True):
         _check(self.lib.tp_profile(self.h, 1 if enable else 0))

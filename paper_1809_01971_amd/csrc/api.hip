@@ -1990,7 +1990,8 @@ tp_status tp_destroy(tp_ctx* c) {
 }
 
 tp_status tp_gemm_mode(int32_t mfma) {
-  gemm_set_mfma(mfma != 0);
+  if (mfma < 0 || mfma > 2) return fail(TP_EINVAL, "gemm mode %d must be 0, 1 or 2", mfma);
+  gemm_set_mfma(mfma);
   return TP_OK;
 }
 

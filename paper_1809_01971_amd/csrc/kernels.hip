@@ -164,6 +164,26 @@ __device__ __forceinline__ d4_t mfma16(double a, double b, d4_t c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Split-BF16 products of FP32 operands: x = hi + lo + r with hi = bf16(x), lo = bf16(x - hi), both
+// rounded to nearest even, so |r| <= 2^-17 |x|; a product is taken as hi*hi' + hi*lo' + lo*hi'
+// (lo*lo' and the r terms dropped: relative error about 2^-16 per product), each term exact in the
+// FP32 accumulation of the BF16 matrix cores.  The 16x16x16 BF16 instruction takes from lane l
+// the 4 consecutive contraction slots 4 (l/16) .. 4 (l/16) + 3 of row (A) or column (B) l % 16 and
+// leaves its 16x16 FP32 result in the layout of the FP32 16x16x4 instruction.
+typedef short s4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 b4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void bf16_split4(const float (&x)[4], s4_t& hi, s4_t& lo) {
+  // FP32 -> BF16 conversions round to nearest even (two values per conversion instruction)
+  const f4_t v = {x[0], x[1], x[2], x[3]};
+  const b4_t h = __builtin_convertvector(v, b4_t);
+  const b4_t l = __builtin_convertvector(v - __builtin_convertvector(h, f4_t), b4_t);
+  hi = __builtin_bit_cast(s4_t, h);
+  lo = __builtin_bit_cast(s4_t, l);
+}
+__device__ __forceinline__ f4_t mfma16_bf16(s4_t a, s4_t b, f4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
 // One stage of the MFMA kernel covers MBK contraction indices; each thread loads MNE elements of
 // the A tile and MNE of the B tile per stage.
 constexpr int MBK = 16;
@@ -285,8 +305,11 @@ __device__ __forceinline__ void lds_run(const double* p, double (&v)[MNE]) {
   }
 }
 
-template <typename TA, typename TB, typename TC, typename Tacc, int AK, int BK>
+// SPLIT (FP32 operands and accumulation only): the products of a stage are split-BF16 products on
+// the BF16 matrix cores instead of FP32 ones (the loads, LDS tiles and epilogue are the same).
+template <typename TA, typename TB, typename TC, typename Tacc, int AK, int BK, bool SPLIT = false>
 __global__ __launch_bounds__(GTHREADS) void k_gemm_mfma(GemmGroup<TA, TB, TC, Tacc> grp) {
+  static_assert(!SPLIT || (std::is_same<Tacc, float>::value && MNE == 4), "split-BF16 takes FP32 16-deep stages");
   typedef typename std::conditional<std::is_same<Tacc, double>::value, d4_t, f4_t>::type V4;
   constexpr int RS = LdsTile<Tacc>::RS;
   __shared__ __align__(16) Tacc As[GBM][RS];
@@ -348,12 +371,33 @@ __global__ __launch_bounds__(GTHREADS) void k_gemm_mfma(GemmGroup<TA, TB, TC, Ta
       lds_run(&As[wm + 16 + c16][kq], a1);
       lds_run(&Bs[wn + c16][kq], b0);
       lds_run(&Bs[wn + 16 + c16][kq], b1);
+      if constexpr (SPLIT) {
+        // the stage's 16 indices in one instruction per term: lane group g holds indices 4g .. 4g+3
+        s4_t ah0, al0, ah1, al1, bh0, bl0, bh1, bl1;
+        bf16_split4(a0, ah0, al0);
+        bf16_split4(a1, ah1, al1);
+        bf16_split4(b0, bh0, bl0);
+        bf16_split4(b1, bh1, bl1);
+        acc[0][0] = mfma16_bf16(bl0, ah0, acc[0][0]);
+        acc[0][1] = mfma16_bf16(bl1, ah0, acc[0][1]);
+        acc[1][0] = mfma16_bf16(bl0, ah1, acc[1][0]);
+        acc[1][1] = mfma16_bf16(bl1, ah1, acc[1][1]);
+        acc[0][0] = mfma16_bf16(bh0, al0, acc[0][0]);
+        acc[0][1] = mfma16_bf16(bh1, al0, acc[0][1]);
+        acc[1][0] = mfma16_bf16(bh0, al1, acc[1][0]);
+        acc[1][1] = mfma16_bf16(bh1, al1, acc[1][1]);
+        acc[0][0] = mfma16_bf16(bh0, ah0, acc[0][0]);
+        acc[0][1] = mfma16_bf16(bh1, ah0, acc[0][1]);
+        acc[1][0] = mfma16_bf16(bh0, ah1, acc[1][0]);
+        acc[1][1] = mfma16_bf16(bh1, ah1, acc[1][1]);
+      } else {
 #pragma unroll
-      for (int t = 0; t < MNE; ++t) {
-        acc[0][0] = mfma16(b0[t], a0[t], acc[0][0]);
-        acc[0][1] = mfma16(b1[t], a0[t], acc[0][1]);
-        acc[1][0] = mfma16(b0[t], a1[t], acc[1][0]);
-        acc[1][1] = mfma16(b1[t], a1[t], acc[1][1]);
+        for (int t = 0; t < MNE; ++t) {
+          acc[0][0] = mfma16(b0[t], a0[t], acc[0][0]);
+          acc[0][1] = mfma16(b1[t], a0[t], acc[0][1]);
+          acc[1][0] = mfma16(b0[t], a1[t], acc[1][0]);
+          acc[1][1] = mfma16(b1[t], a1[t], acc[1][1]);
+        }
       }
     }
     __syncthreads();
@@ -418,19 +462,33 @@ __global__ void k_gemm_reduce(GemmGroup<TA, TB, TC, Tacc> grp) {
   g.C[o] = (TC)v;
 }
 
+// 0: plain FMA kernel, 1: FP32 / FP64 matrix cores, 2: as 1 with split-BF16 products for the
+// contractions with FP32 operands, accumulation and result
 static int g_use_mfma = 1;
 bool gemm_use_mfma() { return g_use_mfma != 0; }
-void gemm_set_mfma(int on) { g_use_mfma = on; }
+void gemm_set_mfma(int mode) { g_use_mfma = mode; }
 
 // The operand kinds are template parameters: each kernel holds only its own loads and registers.
-template <typename TA, typename TB, typename TC, typename Tacc, int AK>
+template <typename TA, typename TB, typename TC, typename Tacc, int AK, bool SPLIT>
 static void launch_mfma_b(const GemmGroup<TA, TB, TC, Tacc>& h, bool fsB, bool tB, dim3 grid, hipStream_t s) {
   if (fsB)
-    hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TC, Tacc, AK, OP_FS>), grid, dim3(GTHREADS), 0, s, h);
+    hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TC, Tacc, AK, OP_FS, SPLIT>), grid, dim3(GTHREADS), 0, s, h);
   else if (tB)
-    hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TC, Tacc, AK, OP_T>), grid, dim3(GTHREADS), 0, s, h);
+    hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TC, Tacc, AK, OP_T, SPLIT>), grid, dim3(GTHREADS), 0, s, h);
   else
-    hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TC, Tacc, AK, OP_N>), grid, dim3(GTHREADS), 0, s, h);
+    hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TC, Tacc, AK, OP_N, SPLIT>), grid, dim3(GTHREADS), 0, s, h);
+}
+template <typename TA, typename TB, typename TC, typename Tacc, int AK>
+static void launch_mfma_a(const GemmGroup<TA, TB, TC, Tacc>& h, bool fsB, bool tB, dim3 grid, hipStream_t s) {
+  constexpr bool f32 = std::is_same<TA, float>::value && std::is_same<TB, float>::value &&
+                       std::is_same<TC, float>::value && std::is_same<Tacc, float>::value;
+  if constexpr (f32) {
+    if (g_use_mfma == 2) {
+      launch_mfma_b<TA, TB, TC, Tacc, AK, true>(h, fsB, tB, grid, s);
+      return;
+    }
+  }
+  launch_mfma_b<TA, TB, TC, Tacc, AK, false>(h, fsB, tB, grid, s);
 }
 
 template <typename TA, typename TB, typename TC, typename Tacc>
@@ -464,11 +522,11 @@ hipError_t gemm_group(const GemmArgs<TA, TB, TC, Tacc>* gs, int count, hipStream
   dim3 grid(gx, gy, z);
   if (gemm_use_mfma()) {
     if (f.fsA)
-      launch_mfma_b<TA, TB, TC, Tacc, OP_FS>(h, f.fsB, f.tB, grid, s);
+      launch_mfma_a<TA, TB, TC, Tacc, OP_FS>(h, f.fsB, f.tB, grid, s);
     else if (f.tA)
-      launch_mfma_b<TA, TB, TC, Tacc, OP_T>(h, f.fsB, f.tB, grid, s);
+      launch_mfma_a<TA, TB, TC, Tacc, OP_T>(h, f.fsB, f.tB, grid, s);
     else
-      launch_mfma_b<TA, TB, TC, Tacc, OP_N>(h, f.fsB, f.tB, grid, s);
+      launch_mfma_a<TA, TB, TC, Tacc, OP_N>(h, f.fsB, f.tB, grid, s);
   } else {
     for (int i = 0; i < h.count; ++i) {
       const GemmArgs<TA, TB, TC, Tacc>& a = h.g[i];

@@ -55,7 +55,7 @@ template <typename TA, typename TB, typename TC, typename Tacc>
 hipError_t gemm_group(const GemmArgs<TA, TB, TC, Tacc>* g, int count, hipStream_t s, hipEvent_t mid = nullptr);
 // Matrix-core (MFMA) tiles on (default) or the FMA tiles.
 bool gemm_use_mfma();
-void gemm_set_mfma(int on);
+void gemm_set_mfma(int mode);  // 0 FMA tiles, 1 matrix cores, 2 with split-BF16 FP32 products
 
 // Orthonormal DST-I on `cols` columns of length n = N-1 (N a power of two).
 // tab holds cos(pi m/N), sin(pi m/N), m = 0..N-1, interleaved (tab64 the same in double; FP32

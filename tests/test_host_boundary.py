@@ -170,3 +170,13 @@ def test_package_sources_do_not_reach_the_oracle():
                              src, flags=re.M):
                     hits.append(f)
     assert hits == []
+
+
+def test_gemm_mode_range():
+    """tp_gemm_mode takes 0, 1 or 2 (a process-wide switch, no device call) and rejects the rest."""
+    lib = _lib()
+    for bad in (-1, 3, 100):
+        assert lib.tp_gemm_mode(bad) == _tp.TP_EINVAL
+        assert "gemm mode" in _err()
+    for ok in (2, 0, 1):
+        assert lib.tp_gemm_mode(ok) == _tp.TP_OK
