@@ -43,7 +43,7 @@ ERR_SLAB_STRIDE = 4   # exact error over every 4th first-index spectral slab (un
 # by the reading of a 256 MiB device copy; valid only for the sources and mixed settings they were
 # taken with, identified by traffic_key() (SHA-256 prefix of csrc/kernels.hip, csrc/api.hip and the
 # settings' JSON); null otherwise.
-TRAFFIC = {"src": "1e99d8c205d3d822",
+TRAFFIC = {"src": "82c1495f1da07055",
            "bytes_per_launch": {"gemm_f32": 27932824, "gemm_f32_split64": 35192331, "gemm_f64": 3408414,
                                 "gemm_f32_f64": 3839517, "gemm_f64_f32": 3269687, "gemm_reduce": 6569913,
                                 "psd_tri": 378717, "psd_eig": 444146, "chol": 436723, "ns_isqrt": 189394,

@@ -402,7 +402,8 @@ typedef enum {
  *     (the sketch, projection and core contractions of the mixed path's products and truncations)
  *     take split-BF16 products on the BF16 matrix cores, accumulated in FP32: each operand
  *     x = hi + lo with hi = bf16(x), lo = bf16(x - hi), and a product is hi hi' + hi lo' + lo hi'
- *     (relative error about 2^-16 per product instead of the FP32 product's 2^-24).  The FP32
+ *     (relative error at most about 3 * 2^-16 per product, from the dropped lo lo' and the
+ *     remainders |x - hi - lo| <= 2^-16 |x|, instead of the FP32 product's 2^-24).  The FP32
  *     contractions that sum into FP64 (inner products, the sketches' FP64 chunk sums) and all FP64
  *     contractions are unchanged.
  * Returns TP_EINVAL for any other value (the mode is then unchanged). */

@@ -165,8 +165,9 @@ __device__ __forceinline__ d4_t mfma16(double a, double b, d4_t c) {
 }
 
 // Split-BF16 products of FP32 operands: x = hi + lo + r with hi = bf16(x), lo = bf16(x - hi), both
-// rounded to nearest even, so |r| <= 2^-17 |x|; a product is taken as hi*hi' + hi*lo' + lo*hi'
-// (lo*lo' and the r terms dropped: relative error about 2^-16 per product), each term exact in the
+// rounded to nearest even (8 significant bits each), so |x - hi| <= 2^-8 |x| and |r| <= 2^-16 |x|; a
+// product is taken as hi*hi' + hi*lo' + lo*hi' (lo*lo' and the r terms dropped: relative error at
+// most about 3 * 2^-16 per product), each term exact in the
 // FP32 accumulation of the BF16 matrix cores.  The 16x16x16 BF16 instruction takes from lane l
 // the 4 consecutive contraction slots 4 (l/16) .. 4 (l/16) + 3 of row (A) or column (B) l % 16 and
 // leaves its 16x16 FP32 result in the layout of the FP32 16x16x4 instruction.

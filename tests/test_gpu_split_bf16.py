@@ -1,8 +1,9 @@
 """Split-BF16 products for the FP32 contractions (tp_gemm_mode(2)): each FP32 operand x is split
 into hi = bf16(x) and lo = bf16(x - hi), and a product is hi hi' + hi lo' + lo hi' on the BF16
-matrix cores, accumulated in FP32, so each product carries a relative error of about 2^-16
-instead of 2^-24.  Checked against the oracle at the contraction (symbol product) and at the
-benchmark workload's full solve, where the mixed tolerance of 1e-4 applies."""
+matrix cores, accumulated in FP32, so each product carries a relative error of at most about
+3 * 2^-16 (typically far less) instead of 2^-24.  Checked against the oracle at the contraction
+(symbol product) and at the benchmark workload's full solve, where the mixed tolerance of 1e-4
+applies."""
 import numpy as np
 import pytest
 
@@ -13,7 +14,7 @@ from tests.gpu_helpers import global_rel_error, log, rel
 pytestmark = pytest.mark.gpu
 
 MIXED_TOL = 1e-4     # relative error vs the exact control, mixed precision
-SPLIT_EPS = 2.0 ** -16  # relative error of one split-BF16 product
+SPLIT_EPS = 2.0 ** -16  # unit of the split products' relative error (at most about 3 of it per product)
 
 
 @pytest.fixture(scope="module")
@@ -29,8 +30,8 @@ def ctx():
 def test_split_bf16_symbol_product(ctx, d, n, alpha):
     """y = F(s (.) F x) for a low-rank x with the split-BF16 contractions, against the exact symbol
     on the full grid and against the same product with FP32 matrix-core contractions.  The split
-    adds about 2^-16 per product to the FP32 path's rounding; the bound allows four times that
-    beside the symbol fit error and the truncation tolerance."""
+    adds at most about 3 * 2^-16 per product to the FP32 path's rounding; the bound allows 4 * 2^-16
+    of relative error in the result beside the symbol fit error and the truncation tolerance."""
     import paper_1809_01971_amd as tp
     from paper_1809_01971_amd._tp import sketch_tensors
     log("split-bf16 apply d=%d n=%d alpha=%g" % (d, n, alpha))
